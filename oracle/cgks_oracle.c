@@ -1,0 +1,1360 @@
+/*
+ * cgks_oracle.c -- plain, slow FP64 CPU oracle of the ASE-DFF compact
+ * gas-kinetic scheme (Mu, Zhang, Ji, Zhang, Chen, Xu: "Very high-order compact
+ * gas-kinetic scheme with discontinuity feedback factor", arXiv 2508.13705).
+ *
+ * TEST INFRASTRUCTURE. Only tests/, __graft_entry__.smoke() and the
+ * cpu_baseline leg of bench.py may load this library. The GPU product path
+ * shares no code, header, table or constant generator with it.
+ *
+ * Style: every step is the plain definition of what the paper states, in the
+ * paper's order, with no fusion and no algebraic short cuts:
+ *   - Maxwellian moments are sums over the monomials of explicit velocity-space
+ *     polynomials, the Gaussian moments by binomial expansion about the mean and
+ *     by truncated-Gaussian integrals (Sec. 2.1, Eq. 2.2).
+ *   - micro-coefficients solve the moment system <a psi> = b by Gaussian
+ *     elimination with partial pivoting (Eq. 2.8).
+ *   - the interface distribution is integrated term by term from Eq. 2.6, with
+ *     no compatibility identity used to drop a term.
+ *   - reconstruction polynomials are fitted to the Hermite conditions
+ *     (Eq. 3.6, 3.7, 3.9 and the 7th/9th-order stencils of Eq. 3.18) by a
+ *     long-double inverse of the condition matrix built at start-up; no
+ *     printed coefficient is typed in.
+ *   - smoothness indicators integrate squared derivatives exactly (Eq. 3.13).
+ *   - the two-stage update follows Eq. 2.19-2.23 and the slopes Eq. 2.25,
+ *     2.29, 2.30 and the 2-D relations of Sec. 3.3 literally.
+ * Readings of points the paper leaves open are those listed in the design
+ * notes (ids A1..A31); each is named where it is used.
+ * Parity unpinned: none of the routines here is unpinned; see tests/.
+ */
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+#include <stdio.h>
+
+#define NPU 8   /* powers of u kept in a velocity polynomial: 0..7 */
+#define NPV 8   /* powers of v */
+#define NPX 4   /* powers of xi^2 */
+#define HALO 3
+
+typedef struct {
+  int dim, nx, ny, order;
+  double dx, dy;
+  int bc[4];          /* x-lo, x-hi, y-lo, y-hi: 0 periodic, 1 transmissive, 2 reflective */
+  double gamma;
+  int tau_model;      /* 0: tau = 0, 1: inviscid, 2: viscous */
+  double c1, c2, mu, prandtl;
+  double sigma_thres, gamma_hi, gamma_lo, weno_eps;
+  double cfl;
+} orc_params;
+
+/* ------------------------------------------------------------------------- */
+/* Gauss-Legendre points on [-1/2, 1/2] (textbook closed forms), weights sum 1 */
+/* ------------------------------------------------------------------------- */
+void orc_gauss_legendre(int m, double* x, double* w) {
+  if (m == 1) { x[0] = 0.0; w[0] = 1.0; }
+  else if (m == 2) {
+    double a = 0.5 / sqrt(3.0);
+    x[0] = -a; x[1] = a; w[0] = w[1] = 0.5;
+  } else if (m == 3) {
+    double a = 0.5 * sqrt(0.6);
+    x[0] = -a; x[1] = 0.0; x[2] = a;
+    w[0] = w[2] = 5.0 / 18.0; w[1] = 8.0 / 18.0;
+  } else if (m == 4) {
+    double r = 2.0 / 7.0 * sqrt(6.0 / 5.0);
+    double a = 0.5 * sqrt(3.0 / 7.0 - r), b = 0.5 * sqrt(3.0 / 7.0 + r);
+    double wa = (18.0 + sqrt(30.0)) / 72.0, wb = (18.0 - sqrt(30.0)) / 72.0;
+    x[0] = -b; x[1] = -a; x[2] = a; x[3] = b;
+    w[0] = wb; w[1] = wa; w[2] = wa; w[3] = wb;
+  }
+}
+
+static int gauss_count(int order) { return order == 5 ? 2 : (order == 7 ? 3 : 4); }
+
+/* ------------------------------------------------------------------------- */
+/* Maxwellian moments (Sec. 2.1, Eq. 2.2)                                     */
+/* ------------------------------------------------------------------------- */
+typedef struct { double rho, U, V, lam; } maxw_t;
+
+static double binom(int n, int k) {
+  double r = 1.0;
+  for (int i = 1; i <= k; ++i) r = r * (double)(n - k + i) / (double)i;
+  return r;
+}
+
+/* <u^n>, n = 0..nmax, of the normalised Gaussian with mean U and variance
+ * 1/(2 lam): binomial expansion about the mean with the central moments
+ * (k-1)!! (1/(2 lam))^(k/2) of even order k. */
+void orc_full_moments(double U, double lam, int nmax, double* M) {
+  double s2 = 1.0 / (2.0 * lam);
+  double cm[16];
+  cm[0] = 1.0;
+  for (int k = 1; k <= nmax; ++k) cm[k] = (k % 2) ? 0.0 : (double)(k - 1) * s2 * cm[k - 2];
+  for (int n = 0; n <= nmax; ++n) {
+    double s = 0.0;
+    for (int k = 0; k <= n; ++k) s += binom(n, k) * pow(U, n - k) * cm[k];
+    M[n] = s;
+  }
+}
+
+/* <u^n> over u > 0 of the same Gaussian: u = U + w and
+ * J_k = int_{-U}^{inf} w^k phi(w) dw with phi(w) = sqrt(lam/pi) exp(-lam w^2);
+ * J_0 = erfc(-sqrt(lam) U)/2, J_k = s2 a^(k-1) phi(a) + (k-1) s2 J_{k-2}, a = -U
+ * (integration by parts). */
+static void half_moments_pos(double U, double lam, int nmax, double* M) {
+  double s2 = 1.0 / (2.0 * lam);
+  double a = -U;
+  double phi = sqrt(lam / M_PI) * exp(-lam * a * a);
+  double J[16];
+  J[0] = 0.5 * erfc(-sqrt(lam) * U);
+  for (int k = 1; k <= nmax; ++k)
+    J[k] = s2 * pow(a, k - 1) * phi + (k >= 2 ? (double)(k - 1) * s2 * J[k - 2] : 0.0);
+  for (int n = 0; n <= nmax; ++n) {
+    double s = 0.0;
+    for (int k = 0; k <= n; ++k) s += binom(n, k) * pow(U, n - k) * J[k];
+    M[n] = s;
+  }
+}
+
+/* region: 0 full space, +1 u > 0, -1 u < 0.  <u^n>_{u<0}(U) = (-1)^n <u^n>_{u>0}(-U). */
+void orc_u_moments(double U, double lam, int region, int nmax, double* M) {
+  if (region == 0) { orc_full_moments(U, lam, nmax, M); return; }
+  if (region > 0) { half_moments_pos(U, lam, nmax, M); return; }
+  half_moments_pos(-U, lam, nmax, M);
+  for (int n = 1; n <= nmax; n += 2) M[n] = -M[n];
+}
+
+/* <(xi^2)^c> for K internal degrees of freedom of variance 1/(2 lam) each. */
+void orc_xi_moments(double K, double lam, int cmax, double* M) {
+  M[0] = 1.0;
+  for (int c = 1; c <= cmax; ++c) M[c] = M[c - 1] * (K + 2.0 * (c - 1)) / (2.0 * lam);
+}
+
+/* velocity-space polynomial: sum of terms c u^a v^b (xi^2)^k, kept as a list */
+#define MAXT 64
+typedef struct { int n; int a[MAXT], b[MAXT], k[MAXT]; double c[MAXT]; } vpoly;
+
+typedef struct {
+  maxw_t g;
+  int D;
+  double K;
+  double Mu[3][NPU + 2];   /* region 0 full, 1 u>0, 2 u<0 */
+  double Mv[NPV + 2];
+  double Mx[NPX + 2];
+  double gram[4][4];       /* int psi_a psi_b g dXi, filled by mom_init */
+} mom_t;
+
+static void vp_zero(vpoly* p) { p->n = 0; }
+
+static void vp_term(vpoly* p, int a, int b, int k, double c) {
+  if (a >= NPU || b >= NPV || k >= NPX) {
+    fprintf(stderr, "oracle: velocity polynomial degree overflow\n");
+    abort();
+  }
+  for (int t = 0; t < p->n; ++t)
+    if (p->a[t] == a && p->b[t] == b && p->k[t] == k) { p->c[t] += c; return; }
+  if (p->n >= MAXT) { fprintf(stderr, "oracle: too many velocity terms\n"); abort(); }
+  p->a[p->n] = a; p->b[p->n] = b; p->k[p->n] = k; p->c[p->n] = c;
+  p->n++;
+}
+
+/* int P g dXi over the region: rho * sum c <u^a>_region <v^b> <xi^2k> */
+static double vp_moment(const vpoly* P, const mom_t* m, int region) {
+  const double* Mu = m->Mu[region == 0 ? 0 : (region > 0 ? 1 : 2)];
+  double s = 0.0;
+  for (int t = 0; t < P->n; ++t) s += P->c[t] * Mu[P->a[t]] * m->Mv[P->b[t]] * m->Mx[P->k[t]];
+  return m->g.rho * s;
+}
+
+/* psi_alpha of Eq. 2.3: 2-D (1, u, v, (u^2+v^2+xi^2)/2); 1-D (1, u, (u^2+xi^2)/2) */
+static void vp_psi(vpoly* p, int alpha, int D) {
+  vp_zero(p);
+  int last = D + 1;
+  if (alpha == 0) vp_term(p, 0, 0, 0, 1.0);
+  else if (alpha == 1) vp_term(p, 1, 0, 0, 1.0);
+  else if (alpha == 2 && D == 2) vp_term(p, 0, 1, 0, 1.0);
+  if (alpha == last) {
+    vp_term(p, 2, 0, 0, 0.5);
+    if (D == 2) vp_term(p, 0, 2, 0, 0.5);
+    vp_term(p, 0, 0, 1, 0.5);
+  }
+}
+
+static void vp_add(vpoly* y, double s, const vpoly* x) {
+  for (int t = 0; t < x->n; ++t) vp_term(y, x->a[t], x->b[t], x->k[t], s * x->c[t]);
+}
+
+/* sum_beta a_beta psi_beta */
+static void vp_lin(vpoly* p, const double* a, int D) {
+  vp_zero(p);
+  vpoly t;
+  for (int b = 0; b < D + 2; ++b) {
+    vp_psi(&t, b, D);
+    vp_add(p, a[b], &t);
+  }
+}
+
+static void vp_mul(vpoly* out, const vpoly* A, const vpoly* B) {
+  vpoly r;
+  vp_zero(&r);
+  for (int s = 0; s < A->n; ++s)
+    for (int t = 0; t < B->n; ++t)
+      vp_term(&r, A->a[s] + B->a[t], A->b[s] + B->b[t], A->k[s] + B->k[t], A->c[s] * B->c[t]);
+  *out = r;
+}
+
+static void vp_mono(vpoly* p, int a, int b) { vp_zero(p); vp_term(p, a, b, 0, 1.0); }
+
+static void mom_init(mom_t* m, maxw_t g, int D, double K) {
+  m->g = g; m->D = D; m->K = K;
+  orc_u_moments(g.U, g.lam, 0, NPU - 1, m->Mu[0]);
+  orc_u_moments(g.U, g.lam, +1, NPU - 1, m->Mu[1]);
+  orc_u_moments(g.U, g.lam, -1, NPU - 1, m->Mu[2]);
+  if (D == 2) orc_full_moments(g.V, g.lam, NPV - 1, m->Mv);
+  else { for (int b = 0; b < NPV; ++b) m->Mv[b] = (b == 0) ? 1.0 : 0.0; }
+  orc_xi_moments(K, g.lam, NPX - 1, m->Mx);
+  vpoly pa, pb, pp;
+  for (int i = 0; i < D + 2; ++i) {
+    vp_psi(&pa, i, D);
+    for (int j = 0; j < D + 2; ++j) {
+      vp_psi(&pb, j, D);
+      vp_mul(&pp, &pa, &pb);
+      m->gram[i][j] = vp_moment(&pp, m, 0);
+    }
+  }
+}
+
+/* ------------------------------------------------------------------------- */
+/* Macroscopic <-> Maxwellian (Eq. 2.2, internal degrees of freedom K)        */
+/* ------------------------------------------------------------------------- */
+/* K = 2/(gamma-1) - D: the paper's K = (5-3 gamma)/(gamma-1) + 1 in 2-D (A13). */
+static double internal_dof(double gamma, int D) { return 2.0 / (gamma - 1.0) - (double)D; }
+
+static double pressure_of(const double* W, int D, double gamma) {
+  double ke = 0.5 * W[1] * W[1] / W[0];
+  if (D == 2) ke += 0.5 * W[2] * W[2] / W[0];
+  return (gamma - 1.0) * (W[D + 1] - ke);
+}
+
+static maxw_t maxw_of(const double* W, int D, double gamma) {
+  maxw_t g;
+  g.rho = W[0];
+  g.U = W[1] / W[0];
+  g.V = (D == 2) ? W[2] / W[0] : 0.0;
+  double p = pressure_of(W, D, gamma);
+  g.lam = W[0] / (2.0 * p);
+  return g;
+}
+
+/* Solve sum_beta <psi_alpha psi_beta> a_beta = b_alpha (moments of g, rho
+ * included): Gaussian elimination with partial pivoting (Eq. 2.8). */
+static void micro_solve(const mom_t* m, const double* b, double* a) {
+  int n = m->D + 2;
+  double A[4][5];
+  for (int i = 0; i < n; ++i) {
+    for (int j = 0; j < n; ++j) A[i][j] = m->gram[i][j];
+    A[i][n] = b[i];
+  }
+  for (int c = 0; c < n; ++c) {
+    int piv = c;
+    for (int r = c + 1; r < n; ++r) if (fabs(A[r][c]) > fabs(A[piv][c])) piv = r;
+    if (piv != c) for (int k = 0; k <= n; ++k) { double t = A[c][k]; A[c][k] = A[piv][k]; A[piv][k] = t; }
+    for (int r = c + 1; r < n; ++r) {
+      double f = A[r][c] / A[c][c];
+      for (int k = c; k <= n; ++k) A[r][k] -= f * A[c][k];
+    }
+  }
+  for (int r = n - 1; r >= 0; --r) {
+    double s = A[r][n];
+    for (int k = r + 1; k < n; ++k) s -= A[r][k] * a[k];
+    a[r] = s / A[r][r];
+  }
+}
+
+/* moment vector int psi_alpha * P g over a region */
+static void psi_moment(const vpoly* P, const mom_t* m, int region, double* out) {
+  vpoly ps, pp;
+  for (int al = 0; al < m->D + 2; ++al) {
+    vp_psi(&ps, al, m->D);
+    vp_mul(&pp, &ps, P);
+    out[al] = vp_moment(&pp, m, region);
+  }
+}
+
+/* exported for the moment pins: the 4x4 (3x3) solve for conservative state W */
+void orc_micro_solve(int D, const double* W, double gamma, const double* b, double* a) {
+  mom_t m;
+  mom_init(&m, maxw_of(W, D, gamma), D, internal_dof(gamma, D));
+  micro_solve(&m, b, a);
+}
+
+/* exported for the moment pins: int psi * u^pa v^pb g dXi over region */
+void orc_psi_moment(int D, const double* W, double gamma, int pa, int pb, int region, double* out) {
+  mom_t m;
+  mom_init(&m, maxw_of(W, D, gamma), D, internal_dof(gamma, D));
+  vpoly P;
+  vp_mono(&P, pa, pb);
+  psi_moment(&P, &m, region, out);
+}
+
+/* ------------------------------------------------------------------------- */
+/* Gas-kinetic flux at one Gauss point (Eq. 2.6 - 2.8, 2.11, 2.12, 2.15)      */
+/* ------------------------------------------------------------------------- */
+/* Inputs per side: Wk[d][v], d = 0 value, 1 d/dn, 2 d/dt, 3 d2/dn2, 4 d2/dndt,
+ * 5 d2/dt2 (n = interface normal, the local x), conservative variables in the
+ * local frame (rho, rho u_n, [rho u_t], rho E).
+ * Outputs: out[0..3] F(dt/2), [4..7] F(dt) (time integrals of Eq. 2.15),
+ * [8..11] W(0), [12..15] W(dt/2), [16..19] W(dt) (Eq. 2.11), [20] sigma of
+ * Eq. 3.2, [21] tau. */
+static void flux_point(const orc_params* P, int D, const double Wl[6][4], const double Wr[6][4],
+                       double dt, double* out) {
+  const int nv = D + 2;
+  const double gam = P->gamma;
+  const double K = internal_dof(gam, D);
+
+  mom_t ml, mr, m0;
+  mom_init(&ml, maxw_of(Wl[0], D, gam), D, K);
+  mom_init(&mr, maxw_of(Wr[0], D, gam), D, K);
+
+  /* micro-coefficients of the two initial states: <a^k> = derivative (Eq. 2.8).
+   * index: 0 a1 (x), 1 a2 (y), 2 a11, 3 a12, 4 a22 (A16: literal second-order) */
+  const int dsrc[5] = {1, 2, 3, 4, 5};
+  const int nder = (D == 2) ? 5 : 2;   /* 1-D: a1 and a11 only */
+  const int dsrc1[2] = {1, 3};
+  double al[5][4] = {{0}}, ar[5][4] = {{0}};
+  for (int q = 0; q < nder; ++q) {
+    int d = (D == 2) ? dsrc[q] : dsrc1[q];
+    micro_solve(&ml, Wl[d], al[q]);
+    micro_solve(&mr, Wr[d], ar[q]);
+  }
+
+  /* kinetic-weighted equilibrium and its derivatives (Eq. 2.7) */
+  double Q0[4], dQ0[5][4];
+  {
+    vpoly one, pl, pr;
+    vp_mono(&one, 0, 0);
+    double a[4], b[4];
+    psi_moment(&one, &ml, +1, a);
+    psi_moment(&one, &mr, -1, b);
+    for (int v = 0; v < nv; ++v) Q0[v] = a[v] + b[v];
+    for (int q = 0; q < nder; ++q) {
+      vp_lin(&pl, al[q], D);
+      vp_lin(&pr, ar[q], D);
+      psi_moment(&pl, &ml, +1, a);
+      psi_moment(&pr, &mr, -1, b);
+      for (int v = 0; v < nv; ++v) dQ0[q][v] = a[v] + b[v];
+    }
+  }
+  mom_init(&m0, maxw_of(Q0, D, gam), D, K);
+
+  /* equilibrium micro-coefficients: <abar> = dQ0 (Eq. 2.8) */
+  double ab[5][4] = {{0}};
+  for (int q = 0; q < nder; ++q) micro_solve(&m0, dQ0[q], ab[q]);
+  double *ab1 = ab[0], *ab2 = ab[1], *ab11, *ab12 = ab[3], *ab22 = ab[4];
+  ab11 = (D == 2) ? ab[2] : ab[1];
+  double zero4[4] = {0, 0, 0, 0};
+  if (D == 1) { ab2 = zero4; ab12 = zero4; ab22 = zero4; }
+
+  vpoly U1, V1;
+  vp_mono(&U1, 1, 0);
+  vp_mono(&V1, 0, 1);
+
+  /* <abar1 u + abar2 v + Abar> = 0 */
+  double Abar[4], ab1t[4], ab2t[4] = {0, 0, 0, 0}, abtt[4];
+  vpoly t1, t2, s;
+  {
+    double rhs[4];
+    vp_lin(&t1, ab1, D); vp_mul(&t1, &t1, &U1);
+    vp_zero(&s); vp_add(&s, 1.0, &t1);
+    if (D == 2) { vp_lin(&t2, ab2, D); vp_mul(&t2, &t2, &V1); vp_add(&s, 1.0, &t2); }
+    psi_moment(&s, &m0, 0, rhs);
+    for (int v = 0; v < nv; ++v) rhs[v] = -rhs[v];
+    micro_solve(&m0, rhs, Abar);
+  }
+  /* <abar11 u + abar12 v + abar1t> = 0, <abar12 u + abar22 v + abar2t> = 0 */
+  {
+    double rhs[4];
+    vp_lin(&t1, ab11, D); vp_mul(&t1, &t1, &U1);
+    vp_zero(&s); vp_add(&s, 1.0, &t1);
+    if (D == 2) { vp_lin(&t2, ab12, D); vp_mul(&t2, &t2, &V1); vp_add(&s, 1.0, &t2); }
+    psi_moment(&s, &m0, 0, rhs);
+    for (int v = 0; v < nv; ++v) rhs[v] = -rhs[v];
+    micro_solve(&m0, rhs, ab1t);
+    if (D == 2) {
+      vp_lin(&t1, ab12, D); vp_mul(&t1, &t1, &U1);
+      vp_lin(&t2, ab22, D); vp_mul(&t2, &t2, &V1);
+      vp_zero(&s); vp_add(&s, 1.0, &t1); vp_add(&s, 1.0, &t2);
+      psi_moment(&s, &m0, 0, rhs);
+      for (int v = 0; v < nv; ++v) rhs[v] = -rhs[v];
+      micro_solve(&m0, rhs, ab2t);
+    }
+  }
+  /* <abar1t u + abar2t v + abartt> = 0 */
+  {
+    double rhs[4];
+    vp_lin(&t1, ab1t, D); vp_mul(&t1, &t1, &U1);
+    vp_zero(&s); vp_add(&s, 1.0, &t1);
+    if (D == 2) { vp_lin(&t2, ab2t, D); vp_mul(&t2, &t2, &V1); vp_add(&s, 1.0, &t2); }
+    psi_moment(&s, &m0, 0, rhs);
+    for (int v = 0; v < nv; ++v) rhs[v] = -rhs[v];
+    micro_solve(&m0, rhs, abtt);
+  }
+
+  /* collision time (Sec. 4): tau models, A17/A18 */
+  double pl = pressure_of(Wl[0], D, gam), pr = pressure_of(Wr[0], D, gam);
+  double jump = fabs((pl - pr) / (pl + pr));
+  double tau = 0.0;
+  if (P->tau_model == 1) tau = P->c1 * dt + P->c2 * jump * dt;
+  else if (P->tau_model == 2) tau = P->mu / pressure_of(Q0, D, gam) + P->c2 * jump * dt;
+
+  /* velocity polynomials of Eq. 2.6 */
+  vpoly PA, Ptt, P1, P1A, Pt, P1l, P1r, one;
+  vp_mono(&one, 0, 0);
+  vp_lin(&PA, Abar, D);
+  vp_lin(&Ptt, abtt, D);
+  vp_lin(&t1, ab1, D); vp_mul(&t1, &t1, &U1);
+  vp_zero(&P1); vp_add(&P1, 1.0, &t1);
+  if (D == 2) { vp_lin(&t2, ab2, D); vp_mul(&t2, &t2, &V1); vp_add(&P1, 1.0, &t2); }
+  P1A = P1; vp_add(&P1A, 1.0, &PA);
+  vp_lin(&t1, ab1t, D); vp_mul(&t1, &t1, &U1);
+  vp_zero(&Pt); vp_add(&Pt, 1.0, &t1);
+  if (D == 2) { vp_lin(&t2, ab2t, D); vp_mul(&t2, &t2, &V1); vp_add(&Pt, 1.0, &t2); }
+  vp_add(&Pt, 1.0, &Ptt);
+  /* non-equilibrium parts use a^l for u > 0 and a^r for u < 0 (A14) */
+  vp_lin(&t1, al[0], D); vp_mul(&t1, &t1, &U1);
+  vp_zero(&P1l); vp_add(&P1l, 1.0, &t1);
+  vp_lin(&t1, ar[0], D); vp_mul(&t1, &t1, &U1);
+  vp_zero(&P1r); vp_add(&P1r, 1.0, &t1);
+  if (D == 2) {
+    vp_lin(&t2, al[1], D); vp_mul(&t2, &t2, &V1); vp_add(&P1l, 1.0, &t2);
+    vp_lin(&t2, ar[1], D); vp_mul(&t2, &t2, &V1); vp_add(&P1r, 1.0, &t2);
+  }
+
+  /* the ten terms of f(t): distribution, region, polynomial */
+  const vpoly* tp[10] = {&one, &PA, &Ptt, &P1A, &Pt, &P1, &one, &P1l, &one, &P1r};
+  const mom_t* tm[10] = {&m0, &m0, &m0, &m0, &m0, &m0, &ml, &ml, &mr, &mr};
+  const int treg[10] = {0, 0, 0, 0, 0, 0, +1, +1, -1, -1};
+  double mflux[10][4], mval[10][4];
+  for (int k = 0; k < 10; ++k) {
+    vpoly up;
+    vp_mul(&up, &U1, tp[k]);
+    psi_moment(&up, tm[k], treg[k], mflux[k]);
+    psi_moment(tp[k], tm[k], treg[k], mval[k]);
+  }
+
+  /* time weights: integral over [0, delta] for fluxes, value at t for W(t) */
+  for (int which = 0; which < 2; ++which) {
+    double d = (which == 0) ? 0.5 * dt : dt;
+    double E0 = 0.0, E1 = 0.0;
+    if (tau > 0.0) {
+      double e = exp(-d / tau);
+      E0 = -tau * expm1(-d / tau);
+      E1 = tau * tau - tau * (tau + d) * e;
+    }
+    double w[10] = {d - E0, 0.5 * d * d, 0.0, -tau * d, -tau * 0.5 * d * d,
+                    E1, E0, -E1, E0, -E1};
+    for (int v = 0; v < nv; ++v) {
+      double sum = 0.0;
+      for (int k = 0; k < 10; ++k) sum += w[k] * mflux[k][v];
+      out[4 * which + v] = sum;
+    }
+  }
+  for (int which = 0; which < 3; ++which) {
+    double t = (which == 0) ? 0.0 : (which == 1 ? 0.5 * dt : dt);
+    double e;
+    if (t == 0.0) e = 1.0;
+    else e = (tau > 0.0) ? exp(-t / tau) : 0.0;
+    double w[10] = {1.0 - e, t, 0.5 * t * t, -tau, -tau * t, t * e, e, -t * e, e, -t * e};
+    for (int v = 0; v < nv; ++v) {
+      double sum = 0.0;
+      for (int k = 0; k < 10; ++k) sum += w[k] * mval[k][v];
+      out[8 + 4 * which + v] = sum;
+    }
+  }
+  if (nv == 3) for (int k = 0; k < 5; ++k) out[4 * k + 3] = 0.0;
+
+  /* discontinuity strength at this Gauss point (Eq. 3.2, A11) */
+  {
+    double cl = sqrt(gam * pl / Wl[0][0]), cr = sqrt(gam * pr / Wr[0][0]);
+    double dp = fabs(pl - pr);
+    double man = Wl[0][1] / Wl[0][0] / cl - Wr[0][1] / Wr[0][0] / cr;
+    double mat = (D == 2) ? (Wl[0][2] / Wl[0][0] / cl - Wr[0][2] / Wr[0][0] / cr) : 0.0;
+    out[20] = dp / pl + dp / pr + man * man + mat * mat;
+  }
+  out[21] = tau;
+}
+
+/* exported for the flux pins; Wl, Wr are [6][4] row-major */
+void orc_flux_point(const orc_params* P, int D, const double* Wl, const double* Wr, double dt, double* out) {
+  double a[6][4], b[6][4];
+  memcpy(a, Wl, sizeof(a));
+  memcpy(b, Wr, sizeof(b));
+  flux_point(P, D, a, b, dt, out);
+}
+
+/* sigma of Eq. 3.2 from two states (used for the first step, A10) */
+static double sigma_of(const double* Wl, const double* Wr, int D, double gam) {
+  double pl = pressure_of(Wl, D, gam), pr = pressure_of(Wr, D, gam);
+  double cl = sqrt(gam * pl / Wl[0]), cr = sqrt(gam * pr / Wr[0]);
+  double dp = fabs(pl - pr);
+  double man = Wl[1] / Wl[0] / cl - Wr[1] / Wr[0] / cr;
+  double mat = (D == 2) ? (Wl[2] / Wl[0] / cl - Wr[2] / Wr[0] / cr) : 0.0;
+  return dp / pl + dp / pr + man * man + mat * mat;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Hermite reconstruction polynomials (Eq. 3.6-3.10, 3.18)                   */
+/* ------------------------------------------------------------------------- */
+/* Stencils, offsets relative to the reconstructed cell (A2):
+ *   S0 = r3: averages {-1,0}, gradient {-1}      (Eq. 3.7)
+ *   S1 = r3: averages {0,1},  gradient {+1}
+ *   S2 = r3: averages {-1,0,1}
+ *   R5:      averages {-1,0,1}, gradients {-1,+1}   (Eq. 3.9, 3.10)
+ *   R7:      averages {-2..2}, gradients {-1,+1}    (Eq. 3.18)
+ *   R9:      averages {-2..2}, gradients {-2,-1,+1,+2}
+ * The polynomial is in xi = (x - x_i)/dx; a gradient condition reads
+ * int_{cell} p'(xi) dxi = dx * (Qx)_cell. */
+enum { ST_S0 = 0, ST_S1, ST_S2, ST_R5, ST_R7, ST_R9, ST_COUNT };
+
+typedef struct {
+  int navg, ngrad, n;
+  int avg[5], grad[4];
+  long double inv[9][9];
+} stencil_t;
+
+static stencil_t g_st[ST_COUNT];
+static int g_st_ready = 0;
+
+static void stencil_def(stencil_t* s, int navg, const int* avg, int ngrad, const int* grad) {
+  s->navg = navg; s->ngrad = ngrad; s->n = navg + ngrad;
+  for (int i = 0; i < navg; ++i) s->avg[i] = avg[i];
+  for (int i = 0; i < ngrad; ++i) s->grad[i] = grad[i];
+  int n = s->n;
+  long double A[9][18];
+  for (int r = 0; r < n; ++r) {
+    for (int k = 0; k < n; ++k) {
+      long double v;
+      if (r < navg) {
+        long double o = avg[r];
+        v = (powl(o + 0.5L, k + 1) - powl(o - 0.5L, k + 1)) / (long double)(k + 1);
+      } else {
+        long double o = grad[r - navg];
+        v = (k == 0) ? 0.0L : (powl(o + 0.5L, k) - powl(o - 0.5L, k));
+      }
+      A[r][k] = v;
+    }
+    for (int k = 0; k < n; ++k) A[r][n + k] = (r == k) ? 1.0L : 0.0L;
+  }
+  /* Gauss-Jordan with partial pivoting */
+  for (int c = 0; c < n; ++c) {
+    int piv = c;
+    for (int r = c + 1; r < n; ++r) if (fabsl(A[r][c]) > fabsl(A[piv][c])) piv = r;
+    if (piv != c) for (int k = 0; k < 2 * n; ++k) { long double t = A[c][k]; A[c][k] = A[piv][k]; A[piv][k] = t; }
+    long double d = A[c][c];
+    for (int k = 0; k < 2 * n; ++k) A[c][k] /= d;
+    for (int r = 0; r < n; ++r) {
+      if (r == c) continue;
+      long double f = A[r][c];
+      if (f != 0.0L) for (int k = 0; k < 2 * n; ++k) A[r][k] -= f * A[c][k];
+    }
+  }
+  for (int k = 0; k < n; ++k)
+    for (int r = 0; r < n; ++r) s->inv[k][r] = A[k][n + r];
+}
+
+static void stencils_init(void) {
+  if (g_st_ready) return;
+  int a2[] = {-1, 0}, g2[] = {-1};
+  int b2[] = {0, 1}, h2[] = {1};
+  int a3[] = {-1, 0, 1};
+  int g55[] = {-1, 1};
+  int a5[] = {-2, -1, 0, 1, 2};
+  int g9[] = {-2, -1, 1, 2};
+  stencil_def(&g_st[ST_S0], 2, a2, 1, g2);
+  stencil_def(&g_st[ST_S1], 2, b2, 1, h2);
+  stencil_def(&g_st[ST_S2], 3, a3, 0, NULL);
+  stencil_def(&g_st[ST_R5], 3, a3, 2, g55);
+  stencil_def(&g_st[ST_R7], 5, a5, 2, g55);
+  stencil_def(&g_st[ST_R9], 5, a5, 4, g9);
+  g_st_ready = 1;
+}
+
+/* fit: q[k] = cell averages at offsets k-2, hq[k] = dx * cell-averaged
+ * derivative at offsets k-2 (k = 0..4). c[0..8] = polynomial in xi. */
+static void stencil_fit(int which, const double* q, const double* hq, double* c) {
+  const stencil_t* s = &g_st[which];
+  long double data[9];
+  for (int r = 0; r < s->navg; ++r) data[r] = q[s->avg[r] + 2];
+  for (int r = 0; r < s->ngrad; ++r) data[s->navg + r] = hq[s->grad[r] + 2];
+  for (int k = 0; k < 9; ++k) c[k] = 0.0;
+  for (int k = 0; k < s->n; ++k) {
+    long double acc = 0.0L;
+    for (int r = 0; r < s->n; ++r) acc += s->inv[k][r] * data[r];
+    c[k] = (double)acc;
+  }
+}
+
+/* d-th derivative in xi of the polynomial at xi */
+static double poly_eval(const double* c, double xi, int d) {
+  double s = 0.0;
+  for (int k = d; k < 9; ++k) {
+    double f = 1.0;
+    for (int t = 0; t < d; ++t) f *= (double)(k - t);
+    s += f * c[k] * pow(xi, k - d);
+  }
+  return s;
+}
+
+/* smoothness indicator of Eq. 3.13 in xi units (A4):
+ * sum_{q=1}^{deg} int_{-1/2}^{1/2} (d^q p / dxi^q)^2 dxi, exact */
+double orc_beta(const double* c, int deg) {
+  double beta = 0.0;
+  for (int q = 1; q <= deg; ++q) {
+    double d[9] = {0};
+    for (int j = 0; j + q <= deg; ++j) {
+      double f = 1.0;
+      for (int t = 0; t < q; ++t) f *= (double)(j + q - t);
+      d[j] = f * c[j + q];
+    }
+    double e[17] = {0};
+    for (int a = 0; a < 9; ++a)
+      for (int b = 0; b < 9; ++b) if (a + b < 17) e[a + b] += d[a] * d[b];
+    for (int sdeg = 0; sdeg < 17; sdeg += 2) beta += e[sdeg] * 2.0 * pow(0.5, sdeg + 1) / (double)(sdeg + 1);
+  }
+  return beta;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Discontinuity feedback factor (Eq. 3.3, 3.4; A7)                           */
+/* ------------------------------------------------------------------------- */
+/* sig[f] holds the face strengths of the line, f = 0..5 for faces -2..3 (face
+ * k is the left face of the cell at offset k).  A_S = sum over the faces of the
+ * stencil's cells of eta*sigma, eta = 2 on a face of a cell whose gradient the
+ * stencil uses, else 1 (A7); summed in ascending face order. */
+static double dff_alpha(int which, const double* sig, double thres) {
+  const stencil_t* s = &g_st[which];
+  int lo = 99, hi = -99;
+  for (int r = 0; r < s->navg; ++r) { if (s->avg[r] < lo) lo = s->avg[r]; if (s->avg[r] > hi) hi = s->avg[r]; }
+  double A = 0.0;
+  for (int f = lo; f <= hi + 1; ++f) {
+    int eta = 1;
+    for (int g = 0; g < s->ngrad; ++g)
+      if (f == s->grad[g] || f == s->grad[g] + 1) eta = 2;
+    A += (double)eta * sig[f + 2];
+  }
+  return (A < thres) ? 1.0 : thres / A;
+}
+
+double orc_dff(int which, const double* sig, double thres) {
+  stencils_init();
+  return dff_alpha(which, sig, thres);
+}
+
+/* ------------------------------------------------------------------------- */
+/* ASE-DFF reconstruction of one cell on one line (Algorithm 1, Eq. 3.5,      */
+/* 3.11-3.19).  Returns the branch: 0 AO(5,3), 5/7/9 linear order.            */
+/* ------------------------------------------------------------------------- */
+static int ase_dff_poly(const orc_params* P, const double* q, const double* hq, const double* sig,
+                        double* c) {
+  const double th = P->sigma_thres;
+  const int order = P->order;
+  double a5 = dff_alpha(ST_R5, sig, th);
+  if (a5 < 1.0) {
+    /* AO(5,3) with every sub-stencil scaled by its own DFF (Eq. 3.19, A5, A6) */
+    double pk[4][9], alpha[4], beta[4];
+    const int which[4] = {ST_S0, ST_S1, ST_S2, ST_R5};
+    const int deg[4] = {2, 2, 2, 4};
+    double Q0 = q[2];
+    for (int k = 0; k < 4; ++k) {
+      stencil_fit(which[k], q, hq, pk[k]);
+      alpha[k] = (k < 3) ? dff_alpha(which[k], sig, th) : a5;
+      pk[k][0] = Q0 + alpha[k] * (pk[k][0] - Q0);
+      for (int j = 1; j < 9; ++j) pk[k][j] *= alpha[k];
+      beta[k] = orc_beta(pk[k], deg[k]);
+    }
+    /* linear weights (Eq. 3.12 read as A3) */
+    double gH = P->gamma_hi, gL = P->gamma_lo;
+    double g[4] = {(1.0 - gH) * (1.0 - gL) / 2.0, (1.0 - gH) * (1.0 - gL) / 2.0, (1.0 - gH) * gL, gH};
+    /* WENO-Z weights (Eq. 3.14-3.16, A4) */
+    double tz = (fabs(beta[3] - beta[0]) + fabs(beta[3] - beta[1]) + fabs(beta[3] - beta[2])) / 3.0;
+    double w[4], ws = 0.0;
+    for (int k = 0; k < 4; ++k) {
+      double r = tz / (beta[k] + P->weno_eps);
+      w[k] = g[k] * (1.0 + r * r);
+      ws += w[k];
+    }
+    for (int k = 0; k < 4; ++k) w[k] /= ws;
+    /* Eq. 3.17 */
+    for (int j = 0; j < 9; ++j) {
+      double hi = pk[3][j];
+      for (int k = 0; k < 3; ++k) hi -= g[k] * pk[k][j];
+      hi /= g[3];
+      double v = w[3] * hi;
+      for (int k = 0; k < 3; ++k) v += w[k] * pk[k][j];
+      c[j] = v;
+    }
+    return 0;
+  }
+  int use;
+  if (order == 5) use = ST_R5;
+  else if (dff_alpha(ST_R7, sig, th) < 1.0) use = ST_R5;
+  else if (order == 7) use = ST_R7;
+  else if (dff_alpha(ST_R9, sig, th) < 1.0) use = ST_R7;
+  else use = ST_R9;
+  /* linear polynomial scaled by its DFF (Eq. 3.5); the cascade only reaches a
+   * stencil whose DFF is 1, so the scaling is the identity here */
+  stencil_fit(use, q, hq, c);
+  return use == ST_R5 ? 5 : (use == ST_R7 ? 7 : 9);
+}
+
+/* exported for the reconstruction pins */
+int orc_recon_poly(const orc_params* P, const double* q, const double* hq, const double* sig, double* c) {
+  stencils_init();
+  return ase_dff_poly(P, q, hq, sig, c);
+}
+
+void orc_stencil_fit(int which, const double* q, const double* hq, double* c) {
+  stencils_init();
+  stencil_fit(which, q, hq, c);
+}
+
+double orc_poly_eval(const double* c, double xi, int d) { return poly_eval(c, xi, d); }
+
+/* ------------------------------------------------------------------------- */
+/* Grids, ghost cells, boundary conditions (A25)                              */
+/* ------------------------------------------------------------------------- */
+typedef struct {
+  int nx, ny, m, NX, NY, D;
+  double dx, dy;
+  double* avg;   /* [nv][NY][NX] */
+  double* sx;    /* [nv][m][NY][NX]  line-averaged x-slopes (1-D: cell-averaged slope, m = 1) */
+  double* sy;    /* [nv][m][NY][NX]  line-averaged y-slopes (2-D) */
+  double* sigx;  /* [NY][NX+1]  x-face strengths, face F at F+HALO, row j at j+HALO */
+  double* sigy;  /* [NX][NY+1]  y-face strengths, column i at i+HALO, face G at G+HALO */
+} grid_t;
+
+#define GA(g, v, j, i) (g)->avg[((size_t)(v) * (g)->NY + (j) + HALO) * (g)->NX + (i) + HALO]
+#define GSX(g, v, l, j, i) (g)->sx[(((size_t)(v) * (g)->m + (l)) * (g)->NY + (j) + HALO) * (g)->NX + (i) + HALO]
+#define GSY(g, v, l, j, i) (g)->sy[(((size_t)(v) * (g)->m + (l)) * (g)->NY + (j) + HALO) * (g)->NX + (i) + HALO]
+#define GSIGX(g, j, F) (g)->sigx[((size_t)(j) + HALO) * ((g)->NX + 1) + (F) + HALO]
+#define GSIGY(g, i, G) (g)->sigy[((size_t)(i) + HALO) * ((g)->NY + 1) + (G) + HALO]
+
+static int src_index(int k, int n, int bc_lo, int bc_hi, int* mirrored) {
+  /* source of ghost cell k (k < 0 or k >= n) */
+  *mirrored = 0;
+  if (k < 0) {
+    if (bc_lo == 0) return k + n;
+    *mirrored = 1;
+    return -k - 1;
+  }
+  if (bc_hi == 0) return k - n;
+  *mirrored = 1;
+  return 2 * n - 1 - k;
+}
+
+static int face_src(int F, int n, int bc_lo, int bc_hi) {
+  /* source of ghost face F (F < 0 or F > n); faces 0 and n are interior */
+  if (F < 0) return (bc_lo == 0) ? F + n : -F;
+  return (bc_hi == 0) ? F - n : 2 * n - F;
+}
+
+/* fill ghost cells: x-ghosts for the interior rows, then y-ghosts for all
+ * columns (corners included).  Mirrored ghosts: averages copied, the normal
+ * slope negated, the tangential line slopes copied with the Gauss nodes in
+ * mirror order; reflective walls also negate the normal momentum. */
+static void fill_state(const orc_params* P, grid_t* g) {
+  const int nv = g->D + 2, m = g->m;
+  for (int j = 0; j < g->ny; ++j)
+    for (int k = -HALO; k < g->nx + HALO; ++k) {
+      if (k >= 0 && k < g->nx) continue;
+      int mir, s = src_index(k, g->nx, P->bc[0], P->bc[1], &mir);
+      int refl = mir && ((k < 0 ? P->bc[0] : P->bc[1]) == 2);
+      for (int v = 0; v < nv; ++v) {
+        double odd = (refl && v == 1) ? -1.0 : 1.0;
+        GA(g, v, j, k) = odd * GA(g, v, j, s);
+        for (int l = 0; l < m; ++l) {
+          GSX(g, v, l, j, k) = (mir ? -1.0 : 1.0) * odd * GSX(g, v, l, j, s);
+          if (g->D == 2) GSY(g, v, l, j, k) = odd * GSY(g, v, mir ? m - 1 - l : l, j, s);
+        }
+      }
+    }
+  if (g->D == 1) return;
+  for (int k = -HALO; k < g->ny + HALO; ++k) {
+    if (k >= 0 && k < g->ny) continue;
+    int mir, s = src_index(k, g->ny, P->bc[2], P->bc[3], &mir);
+    int refl = mir && ((k < 0 ? P->bc[2] : P->bc[3]) == 2);
+    for (int i = -HALO; i < g->nx + HALO; ++i)
+      for (int v = 0; v < nv; ++v) {
+        double odd = (refl && v == 2) ? -1.0 : 1.0;
+        GA(g, v, k, i) = odd * GA(g, v, s, i);
+        for (int l = 0; l < m; ++l) {
+          GSY(g, v, l, k, i) = (mir ? -1.0 : 1.0) * odd * GSY(g, v, l, s, i);
+          GSX(g, v, l, k, i) = odd * GSX(g, v, mir ? m - 1 - l : l, s, i);
+        }
+      }
+  }
+}
+
+static void fill_sigma(const orc_params* P, grid_t* g) {
+  const int ny = (g->D == 2) ? g->ny : 1;
+  for (int j = 0; j < ny; ++j)
+    for (int F = -HALO; F <= g->nx + HALO; ++F) {
+      if (F >= 0 && F <= g->nx) continue;
+      GSIGX(g, j, F) = GSIGX(g, j, face_src(F, g->nx, P->bc[0], P->bc[1]));
+    }
+  if (g->D == 1) return;
+  for (int i = 0; i < g->nx; ++i)
+    for (int G = -HALO; G <= g->ny + HALO; ++G) {
+      if (G >= 0 && G <= g->ny) continue;
+      GSIGY(g, i, G) = GSIGY(g, i, face_src(G, g->ny, P->bc[2], P->bc[3]));
+    }
+  /* ghost rows of x-face strengths, ghost columns of y-face strengths */
+  for (int k = -HALO; k < g->ny + HALO; ++k) {
+    if (k >= 0 && k < g->ny) continue;
+    int mir, s = src_index(k, g->ny, P->bc[2], P->bc[3], &mir);
+    for (int F = -HALO; F <= g->nx + HALO; ++F) GSIGX(g, k, F) = GSIGX(g, s, F);
+  }
+  for (int k = -HALO; k < g->nx + HALO; ++k) {
+    if (k >= 0 && k < g->nx) continue;
+    int mir, s = src_index(k, g->nx, P->bc[0], P->bc[1], &mir);
+    for (int G = -HALO; G <= g->ny + HALO; ++G) GSIGY(g, k, G) = GSIGY(g, s, G);
+  }
+}
+
+/* ------------------------------------------------------------------------- */
+/* Face passes                                                                */
+/* ------------------------------------------------------------------------- */
+#define NOUT 22
+typedef struct { long fallback, ao, linear5, linear7, linear9; } counters_t;
+
+static int nonphysical(const double* W, int D, double gam) {
+  return !(W[0] > 0.0) || !(pressure_of(W, D, gam) > 0.0);
+}
+
+/* 1-D: all faces F = 0..nx; out[F][NOUT] */
+static void faces_1d(const orc_params* P, grid_t* g, double dt, double* out, counters_t* cnt) {
+  const int nx = g->nx, nv = 3;
+  const double h = g->dx;
+  /* reconstruct cells -1..nx: right-face (xi=+1/2) and left-face (xi=-1/2)
+   * value, d/dx, d2/dx2 */
+  double* R = (double*)calloc((size_t)(nx + 2) * 2 * 3 * nv, sizeof(double));
+  long ao = 0, l5 = 0, l7 = 0, l9 = 0;
+#pragma omp parallel for reduction(+ : ao, l5, l7, l9)
+  for (int i = -1; i <= nx; ++i) {
+    double sig[6];
+    for (int f = 0; f < 6; ++f) sig[f] = GSIGX(g, 0, i - 2 + f);
+    for (int v = 0; v < nv; ++v) {
+      double q[5], hq[5], c[9];
+      for (int k = 0; k < 5; ++k) { q[k] = GA(g, v, 0, i + k - 2); hq[k] = h * GSX(g, v, 0, 0, i + k - 2); }
+      int br = ase_dff_poly(P, q, hq, sig, c);
+      if (v == 0) { if (br == 0) ++ao; else if (br == 5) ++l5; else if (br == 7) ++l7; else ++l9; }
+      for (int s = 0; s < 2; ++s) {
+        double xi = (s == 0) ? 0.5 : -0.5;
+        double* r = R + (((size_t)(i + 1) * 2 + s) * 3) * nv;
+        r[0 * nv + v] = poly_eval(c, xi, 0);
+        r[1 * nv + v] = poly_eval(c, xi, 1) / h;
+        r[2 * nv + v] = poly_eval(c, xi, 2) / (h * h);
+      }
+    }
+  }
+  cnt->ao += ao; cnt->linear5 += l5; cnt->linear7 += l7; cnt->linear9 += l9;
+  long fb = 0;
+#pragma omp parallel for reduction(+ : fb)
+  for (int F = 0; F <= nx; ++F) {
+    double Wl[6][4] = {{0}}, Wr[6][4] = {{0}};
+    const double* rl = R + (((size_t)(F - 1 + 1) * 2 + 0) * 3) * nv;
+    const double* rr = R + (((size_t)(F + 1) * 2 + 1) * 3) * nv;
+    for (int v = 0; v < nv; ++v) {
+      Wl[0][v] = rl[v]; Wl[1][v] = rl[nv + v]; Wl[3][v] = rl[2 * nv + v];
+      Wr[0][v] = rr[v]; Wr[1][v] = rr[nv + v]; Wr[3][v] = rr[2 * nv + v];
+    }
+    /* nonphysical reconstructed state: first order from the cell average (A30) */
+    if (nonphysical(Wl[0], 1, P->gamma)) {
+      memset(Wl, 0, sizeof(Wl));
+      for (int v = 0; v < nv; ++v) Wl[0][v] = GA(g, v, 0, F - 1);
+      ++fb;
+    }
+    if (nonphysical(Wr[0], 1, P->gamma)) {
+      memset(Wr, 0, sizeof(Wr));
+      for (int v = 0; v < nv; ++v) Wr[0][v] = GA(g, v, 0, F);
+      ++fb;
+    }
+    flux_point(P, 1, Wl, Wr, dt, out + (size_t)F * NOUT);
+  }
+  cnt->fallback += fb;
+  free(R);
+}
+
+/* Weights of the first and second derivative, at Gauss point l of the middle
+ * row, of the polynomial of degree 3m-1 interpolating values at the m Gauss
+ * points of rows -1, 0, +1 (node r*m+q at xi = r-1+x_q).  Built once by a
+ * long-double Vandermonde inverse.  Units: derivatives in xi. */
+typedef struct { int m; double d1[4][12], d2[4][12]; } tanw_t;
+static tanw_t g_tw[5];
+static int g_tw_ready[5];
+
+static const tanw_t* tangential_weights(int m) {
+  if (g_tw_ready[m]) return &g_tw[m];
+#pragma omp critical(orc_tw)
+  if (!g_tw_ready[m]) {
+    double xg[4], wg[4];
+    orc_gauss_legendre(m, xg, wg);
+    int n = 3 * m;
+    long double A[12][24], X[12];
+    for (int r = 0; r < 3; ++r) for (int q = 0; q < m; ++q) X[r * m + q] = (long double)(r - 1) + (long double)xg[q];
+    for (int a = 0; a < n; ++a) {
+      for (int k = 0; k < n; ++k) A[a][k] = powl(X[a], k);
+      for (int k = 0; k < n; ++k) A[a][n + k] = (a == k) ? 1.0L : 0.0L;
+    }
+    for (int c = 0; c < n; ++c) {
+      int piv = c;
+      for (int r = c + 1; r < n; ++r) if (fabsl(A[r][c]) > fabsl(A[piv][c])) piv = r;
+      if (piv != c) for (int k = 0; k < 2 * n; ++k) { long double t = A[c][k]; A[c][k] = A[piv][k]; A[piv][k] = t; }
+      long double d = A[c][c];
+      for (int k = 0; k < 2 * n; ++k) A[c][k] /= d;
+      for (int r = 0; r < n; ++r) {
+        if (r == c) continue;
+        long double f = A[r][c];
+        if (f != 0.0L) for (int k = 0; k < 2 * n; ++k) A[r][k] -= f * A[c][k];
+      }
+    }
+    /* coefficient k of the interpolant = sum_a inv[k][a] y_a */
+    tanw_t* t = &g_tw[m];
+    t->m = m;
+    for (int l = 0; l < m; ++l)
+      for (int a = 0; a < n; ++a) {
+        long double s1 = 0.0L, s2 = 0.0L, x0 = (long double)xg[l];
+        for (int k = 1; k < n; ++k) s1 += (long double)k * A[k][n + a] * powl(x0, k - 1);
+        for (int k = 2; k < n; ++k) s2 += (long double)(k * (k - 1)) * A[k][n + a] * powl(x0, k - 2);
+        t->d1[l][a] = (double)s1;
+        t->d2[l][a] = (double)s2;
+      }
+    g_tw_ready[m] = 1;
+  }
+  return &g_tw[m];
+}
+
+/* 2-D x-faces F = 0..nx, rows j = 0..ny-1, Gauss lines l: out[(j*(nx+1)+F)*m + l][NOUT].
+ * Sec. 3.3 Steps 1-4.  The y-faces are the x-faces of the transposed grid. */
+static void xfaces_2d(const orc_params* P, grid_t* g, double dt, double* out, counters_t* cnt) {
+  const int nx = g->nx, ny = g->ny, m = g->m, nv = 4;
+  const double hx = g->dx, hy = g->dy;
+  double xg[4], wg[4];
+  orc_gauss_legendre(m, xg, wg);
+  const tanw_t* tw = tangential_weights(m);
+
+  /* cell-averaged y-gradient = Gauss sum of the line-averaged y-slopes (A21) */
+  const int NXg = g->NX, NYg = g->NY;
+  double* Wy = (double*)malloc((size_t)nv * NYg * NXg * sizeof(double));
+#define WY(v, j, i) Wy[((size_t)(v) * NYg + (j) + HALO) * NXg + (i) + HALO]
+  for (int v = 0; v < nv; ++v)
+    for (int j = -HALO; j < ny + HALO; ++j)
+      for (int i = -HALO; i < nx + HALO; ++i) {
+        double s = 0.0;
+        for (int l = 0; l < m; ++l) s += wg[l] * GSY(g, v, l, j, i);
+        WY(v, j, i) = s;
+      }
+
+  /* Step 1: tangential (y) ASE-DFF in each column -> line averages on the
+   * horizontal Gauss lines, cells i = -3..nx+2, rows j = -1..ny (A23) */
+  const int LI0 = -3, LI1 = nx + 2, LJ0 = -1, LJ1 = ny;
+  const int LNI = LI1 - LI0 + 1, LNJ = LJ1 - LJ0 + 1;
+  double* LV = (double*)malloc((size_t)nv * m * LNJ * LNI * sizeof(double));
+#define LVA(v, l, j, i) LV[(((size_t)(v) * m + (l)) * LNJ + (j) - LJ0) * LNI + (i) - LI0]
+  long ao = 0, l5 = 0, l7 = 0, l9 = 0;
+#pragma omp parallel for collapse(2) reduction(+ : ao, l5, l7, l9)
+  for (int j = LJ0; j <= LJ1; ++j)
+    for (int i = LI0; i <= LI1; ++i) {
+      double sig[6];
+      for (int f = 0; f < 6; ++f) sig[f] = GSIGY(g, i, j - 2 + f);
+      for (int v = 0; v < nv; ++v) {
+        double q[5], hq[5], c[9];
+        for (int k = 0; k < 5; ++k) { q[k] = GA(g, v, j + k - 2, i); hq[k] = hy * WY(v, j + k - 2, i); }
+        int br = ase_dff_poly(P, q, hq, sig, c);
+        if (v == 0 && j >= 0 && j < ny && i >= 0 && i < nx) {
+          if (br == 0) ++ao; else if (br == 5) ++l5; else if (br == 7) ++l7; else ++l9;
+        }
+        for (int l = 0; l < m; ++l) LVA(v, l, j, i) = poly_eval(c, xg[l], 0);
+      }
+    }
+
+  /* Step 2: normal (x) ASE-DFF on every Gauss line, cells i = -1..nx, rows
+   * j = -1..ny: value, d/dx, d2/dx2 at both faces of the cell */
+  const int RI0 = -1, RI1 = nx, RNI = RI1 - RI0 + 1;
+  double* R = (double*)malloc((size_t)2 * 3 * nv * m * LNJ * RNI * sizeof(double));
+#define RA(s, d, v, l, j, i) R[(((((size_t)(s) * 3 + (d)) * nv + (v)) * m + (l)) * LNJ + (j) - LJ0) * RNI + (i) - RI0]
+#pragma omp parallel for collapse(2) reduction(+ : ao, l5, l7, l9)
+  for (int j = LJ0; j <= LJ1; ++j)
+    for (int i = RI0; i <= RI1; ++i) {
+      double sig[6];
+      for (int f = 0; f < 6; ++f) sig[f] = GSIGX(g, j, i - 2 + f);
+      for (int l = 0; l < m; ++l)
+        for (int v = 0; v < nv; ++v) {
+          double q[5], hq[5], c[9];
+          for (int k = 0; k < 5; ++k) { q[k] = LVA(v, l, j, i + k - 2); hq[k] = hx * GSX(g, v, l, j, i + k - 2); }
+          int br = ase_dff_poly(P, q, hq, sig, c);
+          if (v == 0 && j >= 0 && j < ny && i >= 0 && i < nx) {
+            if (br == 0) ++ao; else if (br == 5) ++l5; else if (br == 7) ++l7; else ++l9;
+          }
+          for (int s = 0; s < 2; ++s) {
+            double xi = (s == 0) ? 0.5 : -0.5;
+            RA(s, 0, v, l, j, i) = poly_eval(c, xi, 0);
+            RA(s, 1, v, l, j, i) = poly_eval(c, xi, 1) / hx;
+            RA(s, 2, v, l, j, i) = poly_eval(c, xi, 2) / (hx * hx);
+          }
+        }
+    }
+  cnt->ao += ao; cnt->linear5 += l5; cnt->linear7 += l7; cnt->linear9 += l9;
+
+  /* Steps 3-4 at each face Gauss point */
+  long fb = 0;
+#pragma omp parallel for collapse(2) reduction(+ : fb)
+  for (int j = 0; j < ny; ++j)
+    for (int F = 0; F <= nx; ++F)
+      for (int l = 0; l < m; ++l) {
+        double Wk[2][6][4];
+        memset(Wk, 0, sizeof(Wk));
+        for (int side = 0; side < 2; ++side) {
+          int i = (side == 0) ? F - 1 : F;     /* source cell */
+          int s = (side == 0) ? 0 : 1;         /* its right face / its left face */
+          /* DFF of the tangential three-cell stencil {j-1, j, j+1} (A22) */
+          double A = 0.0;
+          for (int G = j - 1; G <= j + 2; ++G) A += GSIGY(g, i, G);
+          double at = (A < P->sigma_thres) ? 1.0 : P->sigma_thres / A;
+          for (int v = 0; v < nv; ++v) {
+            Wk[side][0][v] = RA(s, 0, v, l, j, i);
+            Wk[side][1][v] = RA(s, 1, v, l, j, i);
+            Wk[side][3][v] = RA(s, 2, v, l, j, i);
+            /* tangential derivatives: the interpolant through the values at
+             * all Gauss points of this face in rows j-1, j, j+1 (A22) */
+            double d1 = 0.0, d2 = 0.0, dx1 = 0.0;
+            for (int r = 0; r < 3; ++r)
+              for (int q = 0; q < m; ++q) {
+                double wv = RA(s, 0, v, q, j - 1 + r, i), wx = RA(s, 1, v, q, j - 1 + r, i);
+                d1 += tw->d1[l][r * m + q] * wv;
+                d2 += tw->d2[l][r * m + q] * wv;
+                dx1 += tw->d1[l][r * m + q] * wx;
+              }
+            Wk[side][2][v] = at * d1 / hy;
+            Wk[side][5][v] = at * d2 / (hy * hy);
+            Wk[side][4][v] = at * dx1 / hy;
+          }
+          if (nonphysical(Wk[side][0], 2, P->gamma)) {
+            memset(Wk[side], 0, sizeof(Wk[side]));
+            for (int v = 0; v < nv; ++v) Wk[side][0][v] = GA(g, v, j, i);
+            ++fb;
+          }
+        }
+        flux_point(P, 2, Wk[0], Wk[1], dt, out + (((size_t)j * (nx + 1) + F) * m + l) * NOUT);
+      }
+  cnt->fallback += fb;
+  free(R);
+  free(LV);
+  free(Wy);
+#undef WY
+#undef LVA
+#undef RA
+}
+
+/* transposed copy: x <-> y, components rho u <-> rho v, slopes sx <-> sy,
+ * strengths sigx <-> sigy (shared storage layout) */
+static void transpose_grid(const grid_t* g, grid_t* t) {
+  t->nx = g->ny; t->ny = g->nx; t->m = g->m; t->NX = g->NY; t->NY = g->NX; t->D = 2;
+  t->dx = g->dy; t->dy = g->dx;
+  size_t cells = (size_t)g->NX * g->NY;
+  t->avg = (double*)malloc(4 * cells * sizeof(double));
+  t->sx = (double*)malloc(4 * g->m * cells * sizeof(double));
+  t->sy = (double*)malloc(4 * g->m * cells * sizeof(double));
+  const int perm[4] = {0, 2, 1, 3};
+  for (int v = 0; v < 4; ++v)
+    for (int J = 0; J < g->NY; ++J)
+      for (int I = 0; I < g->NX; ++I) {
+        t->avg[((size_t)perm[v] * t->NY + I) * t->NX + J] = g->avg[((size_t)v * g->NY + J) * g->NX + I];
+        for (int l = 0; l < g->m; ++l) {
+          t->sy[(((size_t)perm[v] * g->m + l) * t->NY + I) * t->NX + J] = g->sx[(((size_t)v * g->m + l) * g->NY + J) * g->NX + I];
+          t->sx[(((size_t)perm[v] * g->m + l) * t->NY + I) * t->NX + J] = g->sy[(((size_t)v * g->m + l) * g->NY + J) * g->NX + I];
+        }
+      }
+  t->sigx = g->sigy;
+  t->sigy = g->sigx;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Time step (Sec. 4, A19) and the two-stage update (Sec. 2.2, Sec. 3.3)     */
+/* ------------------------------------------------------------------------- */
+static double cfl_dt(const orc_params* P, const grid_t* g) {
+  const int D = g->D;
+  double smax = 0.0, rmin = 1e300;
+  for (int j = 0; j < (D == 2 ? g->ny : 1); ++j)
+    for (int i = 0; i < g->nx; ++i) {
+      double W[4];
+      for (int v = 0; v < D + 2; ++v) W[v] = GA(g, v, j, i);
+      double p = pressure_of(W, D, P->gamma);
+      double U = W[1] / W[0], V = (D == 2) ? W[2] / W[0] : 0.0;
+      double s = sqrt(U * U + V * V) + sqrt(P->gamma * p / W[0]);
+      if (s > smax) smax = s;
+      if (W[0] < rmin) rmin = W[0];
+    }
+  double h = (D == 2 && g->dy < g->dx) ? g->dy : g->dx;
+  double dt = h / smax;
+  if (P->tau_model == 2 && P->mu > 0.0) {
+    double dv = h * h * rmin / (4.0 * P->mu);
+    if (dv < dt) dt = dv;
+  }
+  return P->cfl * dt;
+}
+
+static int state_bad(const orc_params* P, const grid_t* g) {
+  const int D = g->D;
+  for (int j = 0; j < (D == 2 ? g->ny : 1); ++j)
+    for (int i = 0; i < g->nx; ++i) {
+      double W[4];
+      for (int v = 0; v < D + 2; ++v) W[v] = GA(g, v, j, i);
+      if (nonphysical(W, D, P->gamma) || !isfinite(W[D + 1])) return 1;
+    }
+  return 0;
+}
+
+static void init_sigma(const orc_params* P, grid_t* g) {
+  const int D = g->D;
+  fill_state(P, g);
+  for (int j = 0; j < (D == 2 ? g->ny : 1); ++j)
+    for (int F = 0; F <= g->nx; ++F) {
+      double Wl[4], Wr[4];
+      for (int v = 0; v < D + 2; ++v) { Wl[v] = GA(g, v, j, F - 1); Wr[v] = GA(g, v, j, F); }
+      GSIGX(g, j, F) = sigma_of(Wl, Wr, D, P->gamma);
+    }
+  if (D == 1) return;
+  for (int i = 0; i < g->nx; ++i)
+    for (int G = 0; G <= g->ny; ++G) {
+      double Wl[4], Wr[4];
+      const int perm[4] = {0, 2, 1, 3};
+      for (int v = 0; v < 4; ++v) { Wl[perm[v]] = GA(g, v, G - 1, i); Wr[perm[v]] = GA(g, v, G, i); }
+      GSIGY(g, i, G) = sigma_of(Wl, Wr, 2, P->gamma);
+    }
+}
+
+/* one stage: all interface results.  xo: x-faces, yo: y-faces (transposed
+ * layout [(i*(ny+1)+G)*m+l], local components) */
+static void stage_faces(const orc_params* P, grid_t* g, double dt, double* xo, double* yo, counters_t* cnt) {
+  fill_state(P, g);
+  if (g->D == 1) { faces_1d(P, g, dt, xo, cnt); return; }
+  xfaces_2d(P, g, dt, xo, cnt);
+  grid_t t;
+  transpose_grid(g, &t);
+  fill_state(P, g);  /* the transposed copy already holds the ghosts */
+  xfaces_2d(P, &t, dt, yo, cnt);
+  free(t.avg); free(t.sx); free(t.sy);
+}
+
+static size_t idx_state(const grid_t* g, int v, int j, int i) {
+  return ((size_t)v * g->NY + j + HALO) * g->NX + i + HALO;
+}
+
+/* Public driver.  State arrays (interior only): avg[nv][ny][nx],
+ * sx[nv][m][ny][nx] (1-D: [3][nx]), sy[nv][m][ny][nx] (2-D), sigx[ny][nx+1]
+ * (1-D: [nx+1]), sigy[ny+1][nx].  init_sigma != 0 computes the first-step
+ * strengths from the cell averages (A10); otherwise the arrays are used as the
+ * strengths of the previous step.  dt_fixed > 0 fixes the step; else CFL.
+ * t_end > 0 clips the last step and stops there.  nsteps < 0: until t_end.
+ * stats[0] fallbacks, [1] AO branches, [2..4] linear 5/7/9, [5] steps.
+ * Returns 0, or 4 when a cell average becomes nonphysical. */
+int orc_run(const orc_params* P, double* avg, double* sx, double* sy, double* sigx, double* sigy,
+            int init_sig, int nsteps, double dt_fixed, double t_end, double* t_io, long* stats) {
+  stencils_init();
+  const int D = P->dim, nv = D + 2;
+  const int m = (D == 2) ? gauss_count(P->order) : 1;
+  grid_t g;
+  g.D = D; g.nx = P->nx; g.ny = (D == 2) ? P->ny : 1; g.m = m;
+  g.NX = g.nx + 2 * HALO; g.NY = (D == 2) ? g.ny + 2 * HALO : 1 + 2 * HALO;
+  g.dx = P->dx; g.dy = (D == 2) ? P->dy : 1.0;
+  size_t cells = (size_t)g.NX * g.NY;
+  g.avg = (double*)calloc(nv * cells, sizeof(double));
+  g.sx = (double*)calloc((size_t)nv * m * cells, sizeof(double));
+  g.sy = (double*)calloc((size_t)nv * m * cells, sizeof(double));
+  g.sigx = (double*)calloc((size_t)g.NY * (g.NX + 1), sizeof(double));
+  g.sigy = (double*)calloc((size_t)g.NX * (g.NY + 1), sizeof(double));
+  double* sigx_new = (double*)calloc((size_t)g.NY * (g.NX + 1), sizeof(double));
+  double* sigy_new = (double*)calloc((size_t)g.NX * (g.NY + 1), sizeof(double));
+  const int ny = g.ny, nx = g.nx;
+  for (int v = 0; v < nv; ++v)
+    for (int j = 0; j < ny; ++j)
+      for (int i = 0; i < nx; ++i) {
+        g.avg[idx_state(&g, v, j, i)] = avg[((size_t)v * ny + j) * nx + i];
+        for (int l = 0; l < m; ++l) {
+          GSX(&g, v, l, j, i) = sx[(((size_t)v * m + l) * ny + j) * nx + i];
+          if (D == 2) GSY(&g, v, l, j, i) = sy[(((size_t)v * m + l) * ny + j) * nx + i];
+        }
+      }
+  if (init_sig) init_sigma(P, &g);
+  else {
+    for (int j = 0; j < ny; ++j)
+      for (int F = 0; F <= nx; ++F) GSIGX(&g, j, F) = sigx[(size_t)j * (nx + 1) + F];
+    if (D == 2)
+      for (int G = 0; G <= ny; ++G)
+        for (int i = 0; i < nx; ++i) GSIGY(&g, i, G) = sigy[(size_t)G * nx + i];
+  }
+
+  double xg[4], wg[4];
+  orc_gauss_legendre(m, xg, wg);
+  const size_t nxf = (size_t)ny * (nx + 1) * m, nyf = (D == 2) ? (size_t)nx * (ny + 1) * m : 0;
+  double* X1 = (double*)malloc(nxf * NOUT * sizeof(double));
+  double* X2 = (double*)malloc(nxf * NOUT * sizeof(double));
+  double* Y1 = nyf ? (double*)malloc(nyf * NOUT * sizeof(double)) : NULL;
+  double* Y2 = nyf ? (double*)malloc(nyf * NOUT * sizeof(double)) : NULL;
+  grid_t gs = g;  /* stage state U* */
+  gs.avg = (double*)calloc(nv * cells, sizeof(double));
+  gs.sx = (double*)calloc((size_t)nv * m * cells, sizeof(double));
+  gs.sy = (double*)calloc((size_t)nv * m * cells, sizeof(double));
+
+  counters_t cnt = {0, 0, 0, 0, 0};
+  double t = *t_io;
+  int status = 0;
+  long steps = 0;
+  const int perm[4] = {0, 2, 1, 3};
+  for (;;) {
+    if (nsteps >= 0 && steps >= nsteps) break;
+    if (t_end > 0.0 && t >= t_end) break;
+    fill_state(P, &g);
+    fill_sigma(P, &g);
+    double dt = (dt_fixed > 0.0) ? dt_fixed : cfl_dt(P, &g);
+    if (t_end > 0.0 && t + dt > t_end) dt = t_end - t;
+
+    /* stage 1 on W^n (Eq. 2.21; Sec. 3.3 slope relations) */
+    stage_faces(P, &g, dt, X1, Y1, &cnt);
+    for (int j = 0; j < ny; ++j)
+      for (int i = 0; i < nx; ++i)
+        for (int v = 0; v < nv; ++v) {
+          double fl = 0.0;
+          for (int l = 0; l < m; ++l) {
+            const double* a = X1 + (((size_t)j * (nx + 1) + i) * m + l) * NOUT;
+            const double* b = X1 + (((size_t)j * (nx + 1) + i + 1) * m + l) * NOUT;
+            fl += wg[l] * (b[v] - a[v]);
+            GSX(&gs, v, l, j, i) = (b[12 + v] - a[12 + v]) / g.dx;   /* W(dt/2) = W* at the face */
+          }
+          double val = GA(&g, v, j, i) - fl / g.dx;
+          if (D == 2) {
+            int lv = perm[v];
+            double gl = 0.0;
+            for (int l = 0; l < m; ++l) {
+              const double* a = Y1 + (((size_t)i * (ny + 1) + j) * m + l) * NOUT;
+              const double* b = Y1 + (((size_t)i * (ny + 1) + j + 1) * m + l) * NOUT;
+              gl += wg[l] * (b[lv] - a[lv]);
+              GSY(&gs, v, l, j, i) = (b[12 + lv] - a[12 + lv]) / g.dy;
+            }
+            val -= gl / g.dy;
+          }
+          gs.avg[idx_state(&gs, v, j, i)] = val;
+        }
+    /* new interface strengths, mean over the Gauss points (Eq. 3.1, A9, A10) */
+    for (int j = 0; j < ny; ++j)
+      for (int F = 0; F <= nx; ++F) {
+        double s = 0.0;
+        for (int l = 0; l < m; ++l) s += X1[(((size_t)j * (nx + 1) + F) * m + l) * NOUT + 20];
+        sigx_new[((size_t)j + HALO) * (g.NX + 1) + F + HALO] = s / m;
+      }
+    if (D == 2)
+      for (int i = 0; i < nx; ++i)
+        for (int G = 0; G <= ny; ++G) {
+          double s = 0.0;
+          for (int l = 0; l < m; ++l) s += Y1[(((size_t)i * (ny + 1) + G) * m + l) * NOUT + 20];
+          sigy_new[((size_t)i + HALO) * (g.NY + 1) + G + HALO] = s / m;
+        }
+    if (state_bad(P, &gs)) { status = 4; break; }
+
+    /* stage 2 on W* with the same dt and the old strengths (A28) */
+    stage_faces(P, &gs, dt, X2, Y2, &cnt);
+    for (int j = 0; j < ny; ++j)
+      for (int i = 0; i < nx; ++i)
+        for (int v = 0; v < nv; ++v) {
+          /* Eq. 2.19, 2.20, 2.22, 2.23 literally */
+          double flux_sum = 0.0;
+          for (int l = 0; l < m; ++l) {
+            double Fc[2];
+            for (int side = 0; side < 2; ++side) {
+              size_t k = (((size_t)j * (nx + 1) + i + side) * m + l) * NOUT;
+              double Fh = X1[k + v], F1 = X1[k + 4 + v], Fsh = X2[k + v], Fs1 = X2[k + 4 + v];
+              double Fn = (4.0 * Fh - F1) / dt;
+              double dFn = 4.0 * (F1 - 2.0 * Fh) / (dt * dt);
+              double dFs = 4.0 * (Fs1 - 2.0 * Fsh) / (dt * dt);
+              Fc[side] = Fn + dt / 6.0 * (dFn + 2.0 * dFs);
+            }
+            flux_sum += wg[l] * (Fc[1] - Fc[0]);
+            /* interface value at t^{n+1} (Eq. 2.25, 2.29) and slope (Eq. 2.30) */
+            double Wn1[2];
+            for (int side = 0; side < 2; ++side) {
+              size_t k = (((size_t)j * (nx + 1) + i + side) * m + l) * NOUT;
+              double w0 = X1[k + 8 + v], wh = X1[k + 12 + v], w1 = X1[k + 16 + v];
+              double s0 = X2[k + 8 + v], sh = X2[k + 12 + v], s1 = X2[k + 16 + v];
+              double ft = (4.0 * wh - 3.0 * w0 - w1) / dt;
+              double ftt = 4.0 * (w1 + w0 - 2.0 * wh) / (dt * dt);
+              double fstt = 4.0 * (s1 + s0 - 2.0 * sh) / (dt * dt);
+              Wn1[side] = w0 + dt * ft + dt * dt / 6.0 * (ftt + 2.0 * fstt);
+            }
+            GSX(&g, v, l, j, i) = (Wn1[1] - Wn1[0]) / g.dx;
+          }
+          double val = GA(&g, v, j, i) - dt / g.dx * flux_sum;
+          if (D == 2) {
+            int lv = perm[v];
+            double gsum = 0.0;
+            for (int l = 0; l < m; ++l) {
+              double Gc[2], Wn1[2];
+              for (int side = 0; side < 2; ++side) {
+                size_t k = (((size_t)i * (ny + 1) + j + side) * m + l) * NOUT;
+                double Fh = Y1[k + lv], F1 = Y1[k + 4 + lv], Fsh = Y2[k + lv], Fs1 = Y2[k + 4 + lv];
+                double Fn = (4.0 * Fh - F1) / dt;
+                double dFn = 4.0 * (F1 - 2.0 * Fh) / (dt * dt);
+                double dFs = 4.0 * (Fs1 - 2.0 * Fsh) / (dt * dt);
+                Gc[side] = Fn + dt / 6.0 * (dFn + 2.0 * dFs);
+                double w0 = Y1[k + 8 + lv], wh = Y1[k + 12 + lv], w1 = Y1[k + 16 + lv];
+                double s0 = Y2[k + 8 + lv], sh = Y2[k + 12 + lv], s1 = Y2[k + 16 + lv];
+                double ft = (4.0 * wh - 3.0 * w0 - w1) / dt;
+                double ftt = 4.0 * (w1 + w0 - 2.0 * wh) / (dt * dt);
+                double fstt = 4.0 * (s1 + s0 - 2.0 * sh) / (dt * dt);
+                Wn1[side] = w0 + dt * ft + dt * dt / 6.0 * (ftt + 2.0 * fstt);
+              }
+              gsum += wg[l] * (Gc[1] - Gc[0]);
+              GSY(&g, v, l, j, i) = (Wn1[1] - Wn1[0]) / g.dy;
+            }
+            val -= dt / g.dy * gsum;
+          }
+          g.avg[idx_state(&g, v, j, i)] = val;
+        }
+    /* strengths of this step feed the next one */
+    for (int j = 0; j < ny; ++j)
+      for (int F = 0; F <= nx; ++F)
+        GSIGX(&g, j, F) = sigx_new[((size_t)j + HALO) * (g.NX + 1) + F + HALO];
+    if (D == 2)
+      for (int i = 0; i < nx; ++i)
+        for (int G = 0; G <= ny; ++G)
+          GSIGY(&g, i, G) = sigy_new[((size_t)i + HALO) * (g.NY + 1) + G + HALO];
+    t += dt;
+    ++steps;
+    if (state_bad(P, &g)) { status = 4; break; }
+  }
+
+  for (int v = 0; v < nv; ++v)
+    for (int j = 0; j < ny; ++j)
+      for (int i = 0; i < nx; ++i) {
+        avg[((size_t)v * ny + j) * nx + i] = g.avg[idx_state(&g, v, j, i)];
+        for (int l = 0; l < m; ++l) {
+          sx[(((size_t)v * m + l) * ny + j) * nx + i] = GSX(&g, v, l, j, i);
+          if (D == 2) sy[(((size_t)v * m + l) * ny + j) * nx + i] = GSY(&g, v, l, j, i);
+        }
+      }
+  for (int j = 0; j < ny; ++j)
+    for (int F = 0; F <= nx; ++F) sigx[(size_t)j * (nx + 1) + F] = GSIGX(&g, j, F);
+  if (D == 2)
+    for (int G = 0; G <= ny; ++G)
+      for (int i = 0; i < nx; ++i) sigy[(size_t)G * nx + i] = GSIGY(&g, i, G);
+  *t_io = t;
+  if (stats) {
+    stats[0] = cnt.fallback; stats[1] = cnt.ao; stats[2] = cnt.linear5; stats[3] = cnt.linear7;
+    stats[4] = cnt.linear9; stats[5] = steps;
+  }
+  free(g.avg); free(g.sx); free(g.sy); free(g.sigx); free(g.sigy);
+  free(sigx_new); free(sigy_new);
+  free(gs.avg); free(gs.sx); free(gs.sy);
+  free(X1); free(X2); free(Y1); free(Y2);
+  return status;
+}
