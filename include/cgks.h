@@ -1,0 +1,149 @@
+/*
+ * cgks.h -- C ABI of libcgks.so: the ASE-DFF compact gas-kinetic scheme
+ * (Mu, Zhang, Ji, Zhang, Chen, Xu, "Very high-order compact gas-kinetic
+ * scheme with discontinuity feedback factor", arXiv 2508.13705) on one AMD
+ * MI355X (gfx950).
+ *
+ * The library advances the compressible Euler / Navier-Stokes equations
+ * W_t = -div F(W) (Sec. 2.2) on a uniform 1-D or 2-D Cartesian grid.  Its
+ * state is the set of cell averages plus, per cell, the cell-averaged slope
+ * (1-D) or the line-averaged slopes on the Gauss lines (2-D, Sec. 3.3); one
+ * call of cgks_step is one two-stage fourth-order step (Eq. 2.13-2.23, 2.25,
+ * 2.29, 2.30) with ASE-DFF reconstruction (Sec. 3, Algorithm 1) and the
+ * gas-kinetic interface flux (Eq. 2.6-2.8).
+ *
+ * Conventions (all functions):
+ *  - C99, no exceptions cross the boundary; every function returns a
+ *    cgks_status.  CGKS_EINVAL is returned before anything is enqueued.
+ *    Detail of the last failure on the calling thread: cgks_last_error().
+ *  - Device buffers (d_state, d_work) are allocated and freed by the caller,
+ *    sized by cgks_plan_sizes; the library never allocates or frees them.
+ *    Host arrays are caller-owned and only read/written during the call.
+ *  - `stream` is a hipStream_t passed as void* (NULL: the default stream).
+ *    cgks_init_state and cgks_step only enqueue work (no host sync, no
+ *    allocation); cgks_read_state and cgks_query_health synchronise `stream`.
+ *  - A plan is immutable after creation: steps of different states on
+ *    different streams may share it.  Calls on the same state must be ordered
+ *    on one stream.
+ *  - Units are those of the problem (the paper's tests are dimensionless).
+ */
+#ifndef CGKS_H
+#define CGKS_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  CGKS_OK = 0,
+  CGKS_EINVAL = 1,          /* bad argument or shape; nothing was enqueued */
+  CGKS_ENOMEM = 2,          /* host allocation failed */
+  CGKS_EHIP = 3,            /* a HIP runtime call failed (see cgks_last_error) */
+  CGKS_ENONPHYSICAL = 4,    /* a cell average reached rho <= 0 or p <= 0 (sticky, per state) */
+  CGKS_ESTATE = 5,          /* the work buffer does not hold an initialised state */
+  CGKS_EBUDGET = 6          /* batch: the job does not fit the memory budget or the slot table */
+} cgks_status;
+
+enum { CGKS_BC_PERIODIC = 0, CGKS_BC_TRANSMISSIVE = 1, CGKS_BC_REFLECTIVE = 2 };
+enum { CGKS_TAU_ZERO = 0, CGKS_TAU_INVISCID = 1, CGKS_TAU_VISCOUS = 2 };
+enum { CGKS_FP64 = 0, CGKS_FP32_FLUX = 1 };
+
+/* Uniform grid.  dim = 1: ny must be 1 and bc[2], bc[3] are ignored.
+ * nx, ny >= 5 (the widest stencil); a periodic direction must be periodic on
+ * both ends.  Transmissive and reflective ghosts mirror the interior cells
+ * (reflective walls also negate the normal momentum). */
+typedef struct {
+  int dim;                  /* 1 or 2 */
+  int nx, ny;               /* cells per direction */
+  double x0, x1, y0, y1;    /* domain [x0, x1] x [y0, y1] */
+  int bc[4];                /* x-lo, x-hi, y-lo, y-hi: CGKS_BC_* */
+} cgks_grid_desc;
+
+/* Scheme parameters (Sec. 3.1, 3.2 and 4).  order 5, 7, 9 uses m = 2, 3, 4
+ * Gauss points per face.  Collision time: CGKS_TAU_ZERO (tau = 0),
+ * CGKS_TAU_INVISCID (tau = c1 dt + c2 |pl-pr|/(pl+pr) dt) or
+ * CGKS_TAU_VISCOUS (tau = mu/p + c2 |pl-pr|/(pl+pr) dt).  prandtl must be 1.
+ * sigma_thres: the DFF threshold (1 for compact stencils); gamma_hi, gamma_lo:
+ * linear weights of the AO(5,3) reconstruction; weno_eps: its epsilon.
+ * precision: CGKS_FP64, or CGKS_FP32_FLUX (reconstruction and flux moments in
+ * FP32; cell-average accumulation, conservation sums and the exponential
+ * time coefficients in FP64). */
+typedef struct {
+  int order;
+  double gamma;
+  int tau_model;
+  double c1, c2, mu, prandtl;
+  double sigma_thres, gamma_hi, gamma_lo, weno_eps;
+  int precision;
+} cgks_scheme_desc;
+
+typedef struct cgks_plan cgks_plan;
+
+/* Counters accumulated on the device since cgks_init_state. */
+typedef struct {
+  long long nonphysical;        /* cell averages found with rho <= 0 or p <= 0 */
+  long long fallbacks;          /* Gauss-point states replaced by the cell average (rho or p <= 0) */
+  long long steps;              /* completed steps */
+} cgks_health;
+
+/* Validate the descriptors and build a plan (host metadata only).
+ * Errors: CGKS_EINVAL (order not 5/7/9, gamma <= 1, nx/ny < 5, dim not 1/2,
+ * inconsistent periodic ends, prandtl != 1, NULL pointers). */
+cgks_status cgks_plan_create(const cgks_grid_desc* grid, const cgks_scheme_desc* scheme, cgks_plan** out);
+
+/* Bytes of the caller-owned device buffers.  d_state holds the conserved
+ * cell averages and slopes with a ghost halo; d_work holds the stage state,
+ * the stage accumulator, the interface strengths (Eq. 3.1), reconstruction
+ * intermediates, and a 256-byte header (time, step, dt, counters). */
+cgks_status cgks_plan_sizes(const cgks_plan* plan, size_t* state_bytes, size_t* work_bytes);
+
+/* Copy an initial state to the device (enqueued on `stream`, host arrays are
+ * staged synchronously, so they may be freed on return).  Layouts, FP64,
+ * C order:
+ *   h_avg      [nv][ny][nx]      conservative cell averages (nv = 3 in 1-D: rho,
+ *                                 rho u, rho E; nv = 4 in 2-D: rho, rho u, rho v, rho E)
+ *   h_slope_x  1-D: [3][nx] cell-averaged d/dx;  2-D: [4][m][ny][nx] d/dx averaged
+ *              along the horizontal Gauss line y_j + x_l dy of each cell
+ *   h_slope_y  2-D: [4][m][ny][nx] d/dy averaged along the vertical Gauss line
+ *              x_i + x_l dx (ignored in 1-D; may be NULL there)
+ *   h_sigma_x, h_sigma_y: interface strengths of a previous step ([ny][nx+1]
+ *              and [ny+1][nx]; 1-D: [nx+1]) to resume a run, or NULL to start
+ *              from the strengths of the piecewise-constant states (Eq. 3.2).
+ *   t0: the time of the state.  Resets the step count and health counters. */
+cgks_status cgks_init_state(const cgks_plan* plan, void* d_state, void* d_work, const double* h_avg,
+                            const double* h_slope_x, const double* h_slope_y, const double* h_sigma_x,
+                            const double* h_sigma_y, double t0, void* stream);
+
+/* Enqueue one two-stage step.  dt > 0: fixed step; dt <= 0: dt = cfl *
+ * min(h / max(|U| + c), h^2 min(rho) / (4 mu)) from the cell averages at the
+ * start of the step, computed on the device.  t_end > 0: the step is clipped
+ * so the time does not pass t_end (a step at t >= t_end does nothing).  No
+ * host synchronisation and no allocation: the call can be captured in a
+ * hipGraph.  Errors: CGKS_EINVAL (cfl not in (0, 1] when dt <= 0). */
+cgks_status cgks_step(const cgks_plan* plan, void* d_state, void* d_work, double dt, double cfl, double t_end,
+                      void* stream);
+
+/* Copy the state back (synchronises `stream`).  Any pointer may be NULL.
+ * Layouts as in cgks_init_state; h_time, h_steps: scalars.  Returns
+ * CGKS_ENONPHYSICAL (after copying) if a nonphysical cell average was seen. */
+cgks_status cgks_read_state(const cgks_plan* plan, const void* d_state, const void* d_work, double* h_avg,
+                            double* h_slope_x, double* h_slope_y, double* h_sigma_x, double* h_sigma_y,
+                            double* h_time, long long* h_steps, void* stream);
+
+/* Device counters (synchronises `stream`); returns CGKS_ENONPHYSICAL when
+ * nonphysical > 0. */
+cgks_status cgks_query_health(const cgks_plan* plan, const void* d_work, cgks_health* out, void* stream);
+
+/* Free the plan's host memory. */
+cgks_status cgks_plan_destroy(cgks_plan* plan);
+
+/* Static strings; cgks_last_error is per thread. */
+const char* cgks_status_string(cgks_status s);
+const char* cgks_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CGKS_H */

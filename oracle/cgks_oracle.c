@@ -886,9 +886,11 @@ static void faces_1d(const orc_params* P, grid_t* g, double dt, double* out, cou
 }
 
 /* Weights of the first and second derivative, at Gauss point l of the middle
- * row, of the polynomial of degree 3m-1 interpolating values at the m Gauss
- * points of rows -1, 0, +1 (node r*m+q at xi = r-1+x_q).  Built once by a
- * long-double Vandermonde inverse.  Units: derivatives in xi. */
+ * row, of the least-squares polynomial of degree q-1 = min(3m-1, 8) through
+ * the values at the m Gauss points of rows -1, 0, +1 (node r*m+q' at
+ * xi = r-1+x_q'); for m = 2, 3 it is the interpolant (A22).  Built once, in
+ * long double, from the normal equations in the scaled variable xi/1.5.
+ * Units: derivatives in xi. */
 typedef struct { int m; double d1[4][12], d2[4][12]; } tanw_t;
 static tanw_t g_tw[5];
 static int g_tw_ready[5];
@@ -899,35 +901,46 @@ static const tanw_t* tangential_weights(int m) {
   if (!g_tw_ready[m]) {
     double xg[4], wg[4];
     orc_gauss_legendre(m, xg, wg);
-    int n = 3 * m;
-    long double A[12][24], X[12];
-    for (int r = 0; r < 3; ++r) for (int q = 0; q < m; ++q) X[r * m + q] = (long double)(r - 1) + (long double)xg[q];
-    for (int a = 0; a < n; ++a) {
-      for (int k = 0; k < n; ++k) A[a][k] = powl(X[a], k);
-      for (int k = 0; k < n; ++k) A[a][n + k] = (a == k) ? 1.0L : 0.0L;
+    const int n = 3 * m;
+    const int q = (n < 9) ? n : 9;
+    const long double sc = 1.5L;
+    long double X[12], B[9][18];
+    for (int r = 0; r < 3; ++r) for (int k = 0; k < m; ++k) X[r * m + k] = ((long double)(r - 1) + (long double)xg[k]) / sc;
+    /* normal matrix (V^T V) with V[a][k] = X_a^k, augmented with the identity */
+    for (int r = 0; r < q; ++r) {
+      for (int k = 0; k < q; ++k) {
+        long double s = 0.0L;
+        for (int a = 0; a < n; ++a) s += powl(X[a], r) * powl(X[a], k);
+        B[r][k] = s;
+      }
+      for (int k = 0; k < q; ++k) B[r][q + k] = (r == k) ? 1.0L : 0.0L;
     }
-    for (int c = 0; c < n; ++c) {
+    for (int c = 0; c < q; ++c) {
       int piv = c;
-      for (int r = c + 1; r < n; ++r) if (fabsl(A[r][c]) > fabsl(A[piv][c])) piv = r;
-      if (piv != c) for (int k = 0; k < 2 * n; ++k) { long double t = A[c][k]; A[c][k] = A[piv][k]; A[piv][k] = t; }
-      long double d = A[c][c];
-      for (int k = 0; k < 2 * n; ++k) A[c][k] /= d;
-      for (int r = 0; r < n; ++r) {
+      for (int r = c + 1; r < q; ++r) if (fabsl(B[r][c]) > fabsl(B[piv][c])) piv = r;
+      if (piv != c) for (int k = 0; k < 2 * q; ++k) { long double t = B[c][k]; B[c][k] = B[piv][k]; B[piv][k] = t; }
+      long double d = B[c][c];
+      for (int k = 0; k < 2 * q; ++k) B[c][k] /= d;
+      for (int r = 0; r < q; ++r) {
         if (r == c) continue;
-        long double f = A[r][c];
-        if (f != 0.0L) for (int k = 0; k < 2 * n; ++k) A[r][k] -= f * A[c][k];
+        long double f = B[r][c];
+        if (f != 0.0L) for (int k = 0; k < 2 * q; ++k) B[r][k] -= f * B[c][k];
       }
     }
-    /* coefficient k of the interpolant = sum_a inv[k][a] y_a */
+    /* coefficient k (scaled variable) per datum a: sum_r (V^T V)^-1[k][r] X_a^r */
     tanw_t* t = &g_tw[m];
     t->m = m;
     for (int l = 0; l < m; ++l)
       for (int a = 0; a < n; ++a) {
-        long double s1 = 0.0L, s2 = 0.0L, x0 = (long double)xg[l];
-        for (int k = 1; k < n; ++k) s1 += (long double)k * A[k][n + a] * powl(x0, k - 1);
-        for (int k = 2; k < n; ++k) s2 += (long double)(k * (k - 1)) * A[k][n + a] * powl(x0, k - 2);
-        t->d1[l][a] = (double)s1;
-        t->d2[l][a] = (double)s2;
+        long double s1 = 0.0L, s2 = 0.0L, x0 = (long double)xg[l] / sc;
+        for (int k = 1; k < q; ++k) {
+          long double ck = 0.0L;
+          for (int r = 0; r < q; ++r) ck += B[k][q + r] * powl(X[a], r);
+          s1 += (long double)k * ck * powl(x0, k - 1);
+          if (k >= 2) s2 += (long double)(k * (k - 1)) * ck * powl(x0, k - 2);
+        }
+        t->d1[l][a] = (double)(s1 / sc);
+        t->d2[l][a] = (double)(s2 / (sc * sc));
       }
     g_tw_ready[m] = 1;
   }
@@ -1025,8 +1038,9 @@ static void xfaces_2d(const orc_params* P, grid_t* g, double dt, double* out, co
             Wk[side][0][v] = RA(s, 0, v, l, j, i);
             Wk[side][1][v] = RA(s, 1, v, l, j, i);
             Wk[side][3][v] = RA(s, 2, v, l, j, i);
-            /* tangential derivatives: the interpolant through the values at
-             * all Gauss points of this face in rows j-1, j, j+1 (A22) */
+            /* tangential derivatives: the least-squares polynomial through
+             * the values at all Gauss points of this face in rows j-1, j, j+1
+             * (A22) */
             double d1 = 0.0, d2 = 0.0, dx1 = 0.0;
             for (int r = 0; r < 3; ++r)
               for (int q = 0; q < m; ++q) {
@@ -1158,7 +1172,8 @@ static size_t idx_state(const grid_t* g, int v, int j, int i) {
  * strengths of the previous step.  dt_fixed > 0 fixes the step; else CFL.
  * t_end > 0 clips the last step and stops there.  nsteps < 0: until t_end.
  * stats[0] fallbacks, [1] AO branches, [2..4] linear 5/7/9, [5] steps.
- * Returns 0, or 4 when a cell average becomes nonphysical. */
+ * Returns 0, or 4 when a cell average becomes nonphysical; the step in which
+ * that happens is completed and the run stops after it. */
 int orc_run(const orc_params* P, double* avg, double* sx, double* sy, double* sigx, double* sigy,
             int init_sig, int nsteps, double dt_fixed, double t_end, double* t_io, long* stats) {
   stencils_init();
@@ -1260,7 +1275,8 @@ int orc_run(const orc_params* P, double* avg, double* sx, double* sy, double* si
           for (int l = 0; l < m; ++l) s += Y1[(((size_t)i * (ny + 1) + G) * m + l) * NOUT + 20];
           sigy_new[((size_t)i + HALO) * (g.NY + 1) + G + HALO] = s / m;
         }
-    if (state_bad(P, &gs)) { status = 4; break; }
+    /* a nonphysical stage state ends the run after this step (the step completes) */
+    if (state_bad(P, &gs)) status = 4;
 
     /* stage 2 on W* with the same dt and the old strengths (A28) */
     stage_faces(P, &gs, dt, X2, Y2, &cnt);
@@ -1330,7 +1346,7 @@ int orc_run(const orc_params* P, double* avg, double* sx, double* sy, double* si
           GSIGY(&g, i, G) = sigy_new[((size_t)i + HALO) * (g.NY + 1) + G + HALO];
     t += dt;
     ++steps;
-    if (state_bad(P, &g)) { status = 4; break; }
+    if (status == 4 || state_bad(P, &g)) { status = 4; break; }
   }
 
   for (int v = 0; v < nv; ++v)

@@ -1,0 +1,225 @@
+"""Thin ctypes binding of libcgks.so (C ABI in include/cgks.h).
+
+Argument marshalling only: every step of the scheme runs in the HIP kernels
+of the library.  PyTorch provides the device buffers and the stream.  There
+is no fallback: without the built library (or without a GPU) every call
+raises.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libcgks.so")
+
+OK, EINVAL, ENOMEM, EHIP, ENONPHYSICAL, ESTATE, EBUDGET = range(7)
+BC = {"periodic": 0, "transmissive": 1, "reflective": 2}
+TAU = {"zero": 0, "inviscid": 1, "viscous": 2}
+PRECISION = {"fp64": 0, "fp32_flux": 1}
+GAUSS_M = {5: 2, 7: 3, 9: 4}
+
+# every symbol include/cgks.h declares
+EXPORTS = ["cgks_plan_create", "cgks_plan_sizes", "cgks_init_state", "cgks_step", "cgks_read_state",
+           "cgks_query_health", "cgks_plan_destroy", "cgks_status_string", "cgks_last_error"]
+
+
+class CgksError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"cgks status {status}: {msg}")
+        self.status = status
+
+
+class GridDesc(ctypes.Structure):
+    _fields_ = [("dim", ctypes.c_int), ("nx", ctypes.c_int), ("ny", ctypes.c_int),
+                ("x0", ctypes.c_double), ("x1", ctypes.c_double), ("y0", ctypes.c_double), ("y1", ctypes.c_double),
+                ("bc", ctypes.c_int * 4)]
+
+
+class SchemeDesc(ctypes.Structure):
+    _fields_ = [("order", ctypes.c_int), ("gamma", ctypes.c_double), ("tau_model", ctypes.c_int),
+                ("c1", ctypes.c_double), ("c2", ctypes.c_double), ("mu", ctypes.c_double),
+                ("prandtl", ctypes.c_double), ("sigma_thres", ctypes.c_double), ("gamma_hi", ctypes.c_double),
+                ("gamma_lo", ctypes.c_double), ("weno_eps", ctypes.c_double), ("precision", ctypes.c_int)]
+
+
+class Health(ctypes.Structure):
+    _fields_ = [("nonphysical", ctypes.c_longlong), ("fallbacks", ctypes.c_longlong), ("steps", ctypes.c_longlong)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libcgks.so from the package directory (raises if it is not built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built; run __graft_entry__.build()")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, dp = ctypes.c_void_p, ctypes.POINTER(ctypes.c_double)
+        L.cgks_plan_create.argtypes = [ctypes.POINTER(GridDesc), ctypes.POINTER(SchemeDesc), ctypes.POINTER(vp)]
+        L.cgks_plan_sizes.argtypes = [vp, ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_size_t)]
+        L.cgks_init_state.argtypes = [vp, vp, vp, dp, dp, dp, dp, dp, ctypes.c_double, vp]
+        L.cgks_step.argtypes = [vp, vp, vp, ctypes.c_double, ctypes.c_double, ctypes.c_double, vp]
+        L.cgks_read_state.argtypes = [vp, vp, vp, dp, dp, dp, dp, dp, dp, ctypes.POINTER(ctypes.c_longlong), vp]
+        L.cgks_query_health.argtypes = [vp, vp, ctypes.POINTER(Health), vp]
+        L.cgks_plan_destroy.argtypes = [vp]
+        L.cgks_status_string.restype = ctypes.c_char_p
+        L.cgks_status_string.argtypes = [ctypes.c_int]
+        L.cgks_last_error.restype = ctypes.c_char_p
+        for name in EXPORTS:
+            if name not in ("cgks_status_string", "cgks_last_error"):
+                getattr(L, name).restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def check(status):
+    if status != OK:
+        raise CgksError(status, lib().cgks_last_error().decode())
+    return status
+
+
+def _dptr(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) if a is not None else None
+
+
+def descriptors(problem, precision="fp64"):
+    """C descriptors of a workload dict (see paper_2508_13705_amd.workloads)."""
+    g, s = problem["grid"], problem["scheme"]
+    gd = GridDesc()
+    gd.dim = g["dim"]
+    gd.nx = g["nx"]
+    gd.ny = g.get("ny", 1) if g["dim"] == 2 else 1
+    gd.x0, gd.x1 = g["x0"], g["x1"]
+    gd.y0, gd.y1 = g.get("y0", 0.0), g.get("y1", 1.0)
+    for k in range(4):
+        gd.bc[k] = BC[g["bc"][k]] if k < len(g["bc"]) else 0
+    sd = SchemeDesc()
+    sd.order = s["order"]
+    sd.gamma = s.get("gamma", 1.4)
+    sd.tau_model = TAU[s.get("tau", "zero")]
+    sd.c1, sd.c2, sd.mu = s.get("c1", 0.05), s.get("c2", 1.0), s.get("mu", 0.0)
+    sd.prandtl = s.get("prandtl", 1.0)
+    sd.sigma_thres = s.get("sigma_thres", 1.0)
+    sd.gamma_hi, sd.gamma_lo = s.get("gamma_hi", 0.85), s.get("gamma_lo", 0.6)
+    sd.weno_eps = s.get("weno_eps", 1e-8)
+    sd.precision = PRECISION[precision]
+    return gd, sd
+
+
+class Plan:
+    def __init__(self, problem, precision="fp64"):
+        self.problem = problem
+        self.precision = precision
+        self.gd, self.sd = descriptors(problem, precision)
+        h = ctypes.c_void_p()
+        check(lib().cgks_plan_create(ctypes.byref(self.gd), ctypes.byref(self.sd), ctypes.byref(h)))
+        self.handle = h
+        sb, wb = ctypes.c_size_t(), ctypes.c_size_t()
+        check(lib().cgks_plan_sizes(h, ctypes.byref(sb), ctypes.byref(wb)))
+        self.state_bytes, self.work_bytes = sb.value, wb.value
+
+    def __del__(self):
+        if getattr(self, "handle", None) is not None and _lib is not None:
+            _lib.cgks_plan_destroy(self.handle)
+            self.handle = None
+
+
+def _stream_handle(stream):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+class Solver:
+    """One grid's state on the GPU: torch-owned device buffers, library kernels."""
+
+    def __init__(self, problem, precision="fp64", device="cuda:0", stream=None, sigma=None, t0=0.0):
+        import torch
+        self.torch = torch
+        self.plan = Plan(problem, precision)
+        self.problem = problem
+        self.device = torch.device(device)
+        self.stream = stream
+        self.state = torch.empty(self.plan.state_bytes // 8, dtype=torch.float64, device=self.device)
+        self.work = torch.empty(self.plan.work_bytes // 8, dtype=torch.float64, device=self.device)
+        self.init(problem["state"], sigma=sigma, t0=t0)
+
+    @property
+    def dims(self):
+        g = self.problem["grid"]
+        return g["dim"], g["nx"], (g.get("ny", 1) if g["dim"] == 2 else 1), \
+            (GAUSS_M[self.problem["scheme"]["order"]] if g["dim"] == 2 else 1)
+
+    def init(self, state, sigma=None, t0=0.0):
+        dim, nx, ny, m = self.dims
+        avg = np.ascontiguousarray(state["avg"], dtype=np.float64)
+        sx = np.ascontiguousarray(state["sx"], dtype=np.float64)
+        sy = np.ascontiguousarray(state["sy"], dtype=np.float64) if dim == 2 else None
+        sgx = sgy = None
+        if sigma is not None:
+            sgx = np.ascontiguousarray(sigma[0], dtype=np.float64)
+            sgy = np.ascontiguousarray(sigma[1], dtype=np.float64) if dim == 2 else None
+        with self.torch.cuda.device(self.device):
+            check(lib().cgks_init_state(self.plan.handle, ctypes.c_void_p(self.state.data_ptr()),
+                                        ctypes.c_void_p(self.work.data_ptr()), _dptr(avg), _dptr(sx), _dptr(sy),
+                                        _dptr(sgx), _dptr(sgy), float(t0), _stream_handle(self.stream)))
+
+    def step(self, n=1, dt=0.0, cfl=None, t_end=0.0):
+        """Enqueue n steps (asynchronous)."""
+        if cfl is None:
+            cfl = self.problem["scheme"].get("cfl", 0.5)
+        st = _stream_handle(self.stream)
+        L = lib()
+        sp, wp = ctypes.c_void_p(self.state.data_ptr()), ctypes.c_void_p(self.work.data_ptr())
+        for _ in range(n):
+            check(L.cgks_step(self.plan.handle, sp, wp, float(dt), float(cfl), float(t_end), st))
+
+    def run(self, nsteps=None, dt=None, t_end=None):
+        """Advance as the problem's run block says (nsteps, fixed dt or CFL, t_end)."""
+        r = self.problem.get("run", {})
+        nsteps = r.get("nsteps", -1) if nsteps is None else nsteps
+        dt = r.get("dt", 0.0) if dt is None else dt
+        t_end = r.get("t_end", 0.0) if t_end is None else t_end
+        if nsteps is None or nsteps < 0:
+            # until t_end: poll the device time every few hundred steps
+            while self.read(sync_only=True)["t"] < t_end * (1 - 1e-15):
+                self.step(256, dt=dt, t_end=t_end)
+        else:
+            self.step(nsteps, dt=dt, t_end=t_end)
+
+    def read(self, sync_only=False):
+        dim, nx, ny, m = self.dims
+        nv = dim + 2
+        t = ctypes.c_double()
+        steps = ctypes.c_longlong()
+        if sync_only:
+            st = lib().cgks_read_state(self.plan.handle, ctypes.c_void_p(self.state.data_ptr()),
+                                       ctypes.c_void_p(self.work.data_ptr()), None, None, None, None, None,
+                                       ctypes.byref(t), ctypes.byref(steps), _stream_handle(self.stream))
+            if st not in (OK, ENONPHYSICAL):
+                check(st)
+            return {"t": t.value, "steps": steps.value, "status": st}
+        avg = np.zeros((nv, ny, nx) if dim == 2 else (nv, nx))
+        sx = np.zeros((nv, m, ny, nx) if dim == 2 else (nv, nx))
+        sy = np.zeros((nv, m, ny, nx)) if dim == 2 else None
+        sgx = np.zeros((ny, nx + 1) if dim == 2 else (nx + 1,))
+        sgy = np.zeros((ny + 1, nx)) if dim == 2 else None
+        st = lib().cgks_read_state(self.plan.handle, ctypes.c_void_p(self.state.data_ptr()),
+                                   ctypes.c_void_p(self.work.data_ptr()), _dptr(avg), _dptr(sx), _dptr(sy),
+                                   _dptr(sgx), _dptr(sgy), ctypes.byref(t), ctypes.byref(steps),
+                                   _stream_handle(self.stream))
+        if st not in (OK, ENONPHYSICAL):
+            check(st)
+        return {"avg": avg, "sx": sx, "sy": sy, "sigx": sgx, "sigy": sgy, "t": t.value, "steps": steps.value,
+                "status": st}
+
+    def health(self):
+        h = Health()
+        st = lib().cgks_query_health(self.plan.handle, ctypes.c_void_p(self.work.data_ptr()), ctypes.byref(h),
+                                     _stream_handle(self.stream))
+        if st not in (OK, ENONPHYSICAL):
+            check(st)
+        return {"nonphysical": h.nonphysical, "fallbacks": h.fallbacks, "steps": h.steps, "status": st}

@@ -1,0 +1,501 @@
+// Device arithmetic of the ASE-DFF compact gas-kinetic scheme for gfx950:
+// Maxwellian moments, micro-coefficients and the interface flux (Sec. 2.1,
+// Eq. 2.6-2.8, 2.11-2.15), the discontinuity feedback factor (Eq. 3.1-3.4)
+// and the adaptive-stencil-extension reconstruction (Eq. 3.5-3.19,
+// Algorithm 1).  Templated on the arithmetic type T (double, or float for the
+// FP32-flux variant) and the dimension D; time coefficients stay in double.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#ifndef CGKS_HD
+#define CGKS_HD __host__ __device__
+#endif
+
+namespace cgks {
+
+#include "cgks_tables.inc"
+
+struct Consts {
+  double gamma, Kd;          // Kd = 2/(gamma-1) = K + D (K internal degrees of freedom)
+  double c1, c2, mu;
+  double thres, ghi, glo, eps;
+  double dx, dy;
+  int tau_model, order, m;
+};
+
+template <typename T> CGKS_HD T dev_erfc(T x);
+template <> CGKS_HD __forceinline__ double dev_erfc<double>(double x) { return erfc(x); }
+template <> CGKS_HD __forceinline__ float dev_erfc<float>(float x) { return erfcf(x); }
+template <typename T> CGKS_HD T dev_exp(T x);
+template <> CGKS_HD __forceinline__ double dev_exp<double>(double x) { return exp(x); }
+template <> CGKS_HD __forceinline__ float dev_exp<float>(float x) { return expf(x); }
+template <typename T> CGKS_HD T dev_sqrt(T x);
+template <> CGKS_HD __forceinline__ double dev_sqrt<double>(double x) { return sqrt(x); }
+template <> CGKS_HD __forceinline__ float dev_sqrt<float>(float x) { return sqrtf(x); }
+
+// ---------------------------------------------------------------------------
+// Moments of a normalised Maxwellian: <u^n> (full space or one half space),
+// <v^n> (full), <xi^2>, <xi^4>.  <u^(n+2)> = U <u^(n+1)> + (n+1)/(2 lam) <u^n>.
+// ---------------------------------------------------------------------------
+template <typename T> struct Mom {
+  T u[7];
+  T v[6];
+  T x2, x4;
+};
+
+template <typename T, int D>
+CGKS_HD __forceinline__ void moments(T U, T V, T lam, T K, int region, Mom<T>& M) {
+  const T h = T(0.5) / lam;
+  if (region == 0) {
+    M.u[0] = T(1);
+    M.u[1] = U;
+  } else {
+    const T s = dev_sqrt<T>(lam);
+    const T sg = T(region);
+    M.u[0] = T(0.5) * dev_erfc<T>(-sg * s * U);
+    M.u[1] = U * M.u[0] + sg * T(0.5) * dev_exp<T>(-lam * U * U) / (s * T(1.7724538509055160273));
+  }
+#pragma unroll
+  for (int n = 2; n < 7; ++n) M.u[n] = U * M.u[n - 1] + T(n - 1) * h * M.u[n - 2];
+  if (D == 2) {
+    M.v[0] = T(1);
+    M.v[1] = V;
+#pragma unroll
+    for (int n = 2; n < 6; ++n) M.v[n] = V * M.v[n - 1] + T(n - 1) * h * M.v[n - 2];
+  }
+  M.x2 = K * h;
+  M.x4 = (K + T(2)) * h * M.x2;
+}
+
+// <a u^AL v^BE>, a = a0 + a1 u + a2 v + a3 (u^2+v^2+xi^2)/2 (2-D), or
+// a0 + a1 u + a2 (u^2+xi^2)/2 (1-D)
+template <typename T, int D, int AL, int BE>
+CGKS_HD __forceinline__ T mS(const T* a, const Mom<T>& M) {
+  if (D == 2) {
+    const T g = M.u[AL] * M.v[BE];
+    return a[0] * g + a[1] * M.u[AL + 1] * M.v[BE] + a[2] * M.u[AL] * M.v[BE + 1] +
+           T(0.5) * a[3] * (M.u[AL + 2] * M.v[BE] + M.u[AL] * M.v[BE + 2] + g * M.x2);
+  } else {
+    return a[0] * M.u[AL] + a[1] * M.u[AL + 1] + T(0.5) * a[2] * (M.u[AL + 2] + M.u[AL] * M.x2);
+  }
+}
+
+// <a u^AL v^BE xi^2>
+template <typename T, int D, int AL, int BE>
+CGKS_HD __forceinline__ T mSx(const T* a, const Mom<T>& M) {
+  if (D == 2) {
+    const T g = M.u[AL] * M.v[BE];
+    return M.x2 * (a[0] * g + a[1] * M.u[AL + 1] * M.v[BE] + a[2] * M.u[AL] * M.v[BE + 1] +
+                   T(0.5) * a[3] * (M.u[AL + 2] * M.v[BE] + M.u[AL] * M.v[BE + 2])) +
+           T(0.5) * a[3] * g * M.x4;
+  } else {
+    return M.x2 * (a[0] * M.u[AL] + a[1] * M.u[AL + 1] + T(0.5) * a[2] * M.u[AL + 2]) +
+           T(0.5) * a[2] * M.u[AL] * M.x4;
+  }
+}
+
+// psi-moment vector <a u^AL v^BE psi> (normalised, no rho)
+template <typename T, int D, int AL, int BE>
+CGKS_HD __forceinline__ void mauv(const T* a, const Mom<T>& M, T* out) {
+  if (D == 2) {
+    out[0] = mS<T, D, AL, BE>(a, M);
+    out[1] = mS<T, D, AL + 1, BE>(a, M);
+    out[2] = mS<T, D, AL, BE + 1>(a, M);
+    out[3] = T(0.5) * (mS<T, D, AL + 2, BE>(a, M) + mS<T, D, AL, BE + 2>(a, M) + mSx<T, D, AL, BE>(a, M));
+  } else {
+    out[0] = mS<T, D, AL, 0>(a, M);
+    out[1] = mS<T, D, AL + 1, 0>(a, M);
+    out[2] = T(0.5) * (mS<T, D, AL + 2, 0>(a, M) + mSx<T, D, AL, 0>(a, M));
+  }
+}
+
+// micro-coefficients a with <a psi> = b (normalised moments of g): closed-form
+// inverse of the Maxwellian moment matrix.
+template <typename T, int D>
+CGKS_HD __forceinline__ void micro(const T* b, T U, T V, T lam, T Kd, T* a) {
+  if (D == 2) {
+    const T q = U * U + V * V + Kd / (T(2) * lam);
+    const T R2 = b[1] - U * b[0], R3 = b[2] - V * b[0], R4 = T(2) * b[3] - q * b[0];
+    a[3] = T(4) * lam * lam / Kd * (R4 - T(2) * U * R2 - T(2) * V * R3);
+    a[2] = T(2) * lam * R3 - V * a[3];
+    a[1] = T(2) * lam * R2 - U * a[3];
+    a[0] = b[0] - U * a[1] - V * a[2] - T(0.5) * a[3] * q;
+  } else {
+    const T q = U * U + Kd / (T(2) * lam);
+    const T R2 = b[1] - U * b[0], R3 = T(2) * b[2] - q * b[0];
+    a[2] = T(4) * lam * lam / Kd * (R3 - T(2) * U * R2);
+    a[1] = T(2) * lam * R2 - U * a[2];
+    a[0] = b[0] - U * a[1] - T(0.5) * a[2] * q;
+    a[3] = T(0);
+  }
+}
+
+template <typename T, int D>
+CGKS_HD __forceinline__ void primitive(const T* W, T gm1, T& rho, T& U, T& V, T& p) {
+  rho = W[0];
+  U = W[1] / rho;
+  V = (D == 2) ? W[2] / rho : T(0);
+  const T ke = T(0.5) * rho * (U * U + V * V);
+  p = gm1 * (W[D + 1] - ke);
+}
+
+// Results of one Gauss point, in double.
+struct FaceOut {
+  double Fh[4], F1[4];     // time integrals of the flux over [0, dt/2] and [0, dt]
+  double W0[4], Wh[4], W1[4];  // interface values at 0, dt/2, dt
+  double sigma;            // discontinuity strength, Eq. 3.2
+};
+
+// Interface flux at one Gauss point (normal = local x).  Wk[d][v]: d = 0 value,
+// 1 d/dn, 2 d/dt, 3 d2/dn2, 4 d2/dndt, 5 d2/dt2; components in the face frame
+// (rho, rho u_n, [rho u_t,] rho E).
+template <typename T, int D>
+CGKS_HD void gks_flux(const T (&Wl)[6][4], const T (&Wr)[6][4], double dt, const Consts& C, FaceOut& o) {
+  constexpr int NV = D + 2;
+  const T gm1 = T(C.gamma - 1.0), Kd = T(C.Kd), K = T(C.Kd - D);
+  T Q0[4] = {0, 0, 0, 0}, dQ[5][4], NF0[4] = {0, 0, 0, 0}, NF1[4] = {0, 0, 0, 0}, NW1[4] = {0, 0, 0, 0};
+#pragma unroll
+  for (int q = 0; q < 5; ++q)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) dQ[q][v] = T(0);
+  T pside[2], cside[2], un[2], ut[2];
+
+#pragma unroll
+  for (int side = 0; side < 2; ++side) {
+    const T(&Wk)[6][4] = side == 0 ? Wl : Wr;
+    T rho, U, V, p;
+    primitive<T, D>(Wk[0], gm1, rho, U, V, p);
+    const T lam = rho / (T(2) * p);
+    pside[side] = p;
+    cside[side] = dev_sqrt<T>(T(C.gamma) * p / rho);
+    un[side] = U;
+    ut[side] = V;
+    Mom<T> M;
+    moments<T, D>(U, V, lam, K, side == 0 ? 1 : -1, M);
+    const T ir = T(1) / rho;
+    T e0[4] = {1, 0, 0, 0}, t4[4];
+    mauv<T, D, 0, 0>(e0, M, t4);
+#pragma unroll
+    for (int v = 0; v < NV; ++v) Q0[v] += rho * t4[v];
+    mauv<T, D, 1, 0>(e0, M, t4);
+#pragma unroll
+    for (int v = 0; v < NV; ++v) NF0[v] += rho * t4[v];
+    // derivative sources: 1 n, 2 t, 3 nn, 4 nt, 5 tt (1-D: n, nn)
+    constexpr int NDER = (D == 2) ? 5 : 2;
+#pragma unroll
+    for (int q = 0; q < NDER; ++q) {
+      const int d = (D == 2) ? q + 1 : (q == 0 ? 1 : 3);
+      T b[4], a[4];
+#pragma unroll
+      for (int v = 0; v < 4; ++v) b[v] = (v < NV) ? Wk[d][v] * ir : T(0);
+      micro<T, D>(b, U, V, lam, Kd, a);
+      mauv<T, D, 0, 0>(a, M, t4);
+#pragma unroll
+      for (int v = 0; v < NV; ++v) dQ[q][v] += rho * t4[v];
+      if (q == 0) {
+        mauv<T, D, 2, 0>(a, M, t4);
+#pragma unroll
+        for (int v = 0; v < NV; ++v) NF1[v] += rho * t4[v];
+        mauv<T, D, 1, 0>(a, M, t4);
+#pragma unroll
+        for (int v = 0; v < NV; ++v) NW1[v] += rho * t4[v];
+      }
+      if (D == 2 && q == 1) {
+        mauv<T, D, 1, 1>(a, M, t4);
+#pragma unroll
+        for (int v = 0; v < NV; ++v) NF1[v] += rho * t4[v];
+        mauv<T, D, 0, 1>(a, M, t4);
+#pragma unroll
+        for (int v = 0; v < NV; ++v) NW1[v] += rho * t4[v];
+      }
+    }
+  }
+
+  // equilibrium state at the interface (kinetic weighting, Eq. 2.7)
+  T rho0, U0, V0, p0;
+  primitive<T, D>(Q0, gm1, rho0, U0, V0, p0);
+  const T lam0 = rho0 / (T(2) * p0);
+  Mom<T> M0;
+  moments<T, D>(U0, V0, lam0, K, 0, M0);
+  const T ir0 = T(1) / rho0;
+  T ab[5][4];
+  constexpr int NDER = (D == 2) ? 5 : 2;
+#pragma unroll
+  for (int q = 0; q < NDER; ++q) {
+    T b[4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) b[v] = (v < NV) ? dQ[q][v] * ir0 : T(0);
+    micro<T, D>(b, U0, V0, lam0, Kd, ab[q]);
+  }
+  // ab index: 2-D 0 n, 1 t, 2 nn, 3 nt, 4 tt; 1-D 0 n, 1 nn
+  const T* an = ab[0];
+  const T* ann = (D == 2) ? ab[2] : ab[1];
+  T bA[4], AT[4], b1[4], anT[4], atT[4], bTT[4], ATT[4], t4[4];
+  // <an u + at v + A> = 0
+  mauv<T, D, 1, 0>(an, M0, bA);
+  if (D == 2) {
+    mauv<T, D, 0, 1>(ab[1], M0, t4);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) bA[v] += t4[v];
+  }
+#pragma unroll
+  for (int v = 0; v < 4; ++v) bA[v] = -bA[v];
+  micro<T, D>(bA, U0, V0, lam0, Kd, AT);
+  // <ann u + ant v + anT> = 0, <ant u + att v + atT> = 0
+  mauv<T, D, 1, 0>(ann, M0, b1);
+  if (D == 2) {
+    mauv<T, D, 0, 1>(ab[3], M0, t4);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) b1[v] += t4[v];
+  }
+#pragma unroll
+  for (int v = 0; v < 4; ++v) b1[v] = -b1[v];
+  micro<T, D>(b1, U0, V0, lam0, Kd, anT);
+  if (D == 2) {
+    mauv<T, D, 1, 0>(ab[3], M0, b1);
+    mauv<T, D, 0, 1>(ab[4], M0, t4);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) b1[v] = -(b1[v] + t4[v]);
+    micro<T, D>(b1, U0, V0, lam0, Kd, atT);
+  } else {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) atT[v] = T(0);
+  }
+  // <anT u + atT v + ATT> = 0
+  mauv<T, D, 1, 0>(anT, M0, bTT);
+  if (D == 2) {
+    mauv<T, D, 0, 1>(atT, M0, t4);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) bTT[v] += t4[v];
+  }
+#pragma unroll
+  for (int v = 0; v < 4; ++v) bTT[v] = -bTT[v];
+  micro<T, D>(bTT, U0, V0, lam0, Kd, ATT);
+
+  // flux moments of the equilibrium part (normalised)
+  T e0[4] = {1, 0, 0, 0}, F0[4], FA[4], F1[4], Ft[4];
+  mauv<T, D, 1, 0>(e0, M0, F0);
+  mauv<T, D, 1, 0>(AT, M0, FA);
+  mauv<T, D, 2, 0>(an, M0, F1);
+  mauv<T, D, 2, 0>(anT, M0, Ft);
+  if (D == 2) {
+    mauv<T, D, 1, 1>(ab[1], M0, t4);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) F1[v] += t4[v];
+    mauv<T, D, 1, 1>(atT, M0, t4);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) Ft[v] += t4[v];
+  }
+  mauv<T, D, 1, 0>(ATT, M0, t4);
+#pragma unroll
+  for (int v = 0; v < 4; ++v) Ft[v] += t4[v];
+
+  // collision time (Sec. 4)
+  const double pl = double(pside[0]), pr = double(pside[1]);
+  const double jump = fabs((pl - pr) / (pl + pr));
+  double tau = 0.0;
+  if (C.tau_model == 1) tau = C.c1 * dt + C.c2 * jump * dt;
+  else if (C.tau_model == 2) tau = C.mu / double(p0) + C.c2 * jump * dt;
+
+  // time integrals (the flux keeps the terms up to first order in t of the
+  // equilibrium part; interface values keep the full quadratic)
+  const double r0 = double(rho0);
+#pragma unroll
+  for (int w = 0; w < 2; ++w) {
+    const double d = w == 0 ? 0.5 * dt : dt;
+    double E0 = 0.0, E1 = 0.0;
+    if (tau > 0.0) {
+      const double x = d / tau;
+      const double e = exp(-x);
+      E0 = -tau * expm1(-x);
+      E1 = tau * tau - tau * (tau + d) * e;
+    }
+    double* Fo = w == 0 ? o.Fh : o.F1;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      if (v >= NV) { Fo[v] = 0.0; continue; }
+      const double f1 = double(F1[v]), fa = double(FA[v]);
+      Fo[v] = r0 * (double(F0[v]) * (d - E0) + fa * 0.5 * d * d - tau * ((f1 + fa) * d + double(Ft[v]) * 0.5 * d * d) +
+                    f1 * E1) +
+              double(NF0[v]) * E0 - double(NF1[v]) * E1;
+    }
+  }
+#pragma unroll
+  for (int w = 0; w < 3; ++w) {
+    const double t = w == 0 ? 0.0 : (w == 1 ? 0.5 * dt : dt);
+    const double e = (t == 0.0) ? 1.0 : (tau > 0.0 ? exp(-t / tau) : 0.0);
+    double* Wo = w == 0 ? o.W0 : (w == 1 ? o.Wh : o.W1);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      if (v >= NV) { Wo[v] = 0.0; continue; }
+      Wo[v] = double(Q0[v]) + r0 * double(bA[v]) * t * (1.0 - e) + 0.5 * r0 * double(bTT[v]) * t * t -
+              t * e * double(NW1[v]);
+    }
+  }
+  // discontinuity strength (Eq. 3.2)
+  {
+    const double dp = fabs(pl - pr);
+    const double mn = double(un[0]) / double(cside[0]) - double(un[1]) / double(cside[1]);
+    const double mt = (D == 2) ? double(ut[0]) / double(cside[0]) - double(ut[1]) / double(cside[1]) : 0.0;
+    o.sigma = dp / pl + dp / pr + mn * mn + mt * mt;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Discontinuity feedback factor and the stencil cascade (Eq. 3.3, 3.4,
+// Algorithm 1).  s[f], f = 0..5: strengths of faces -5/2 .. +5/2 around the
+// cell (face -5/2 at index 0).  eta = 2 on the faces of cells whose gradient
+// the stencil uses.
+// ---------------------------------------------------------------------------
+struct Cascade {
+  int branch;          // 0: AO(5,3); 5, 7, 9: linear stencil of that order
+  double al[4];        // AO: DFF of S0, S1, S2 and of the 5th-order stencil
+};
+
+CGKS_HD __forceinline__ double dff_of(double A, double thres) { return (A < thres) ? 1.0 : thres / A; }
+
+CGKS_HD __forceinline__ Cascade cascade(const double* s, int order, double thres) {
+  Cascade c;
+  const double A5 = 2.0 * s[1] + 2.0 * s[2] + 2.0 * s[3] + 2.0 * s[4];
+  const double a5 = dff_of(A5, thres);
+  if (a5 < 1.0) {
+    c.branch = 0;
+    c.al[0] = dff_of(2.0 * s[1] + 2.0 * s[2] + s[3], thres);
+    c.al[1] = dff_of(s[2] + 2.0 * s[3] + 2.0 * s[4], thres);
+    c.al[2] = dff_of(s[1] + s[2] + s[3] + s[4], thres);
+    c.al[3] = a5;
+    return c;
+  }
+  if (order == 5) { c.branch = 5; return c; }
+  const double A7 = s[0] + 2.0 * s[1] + 2.0 * s[2] + 2.0 * s[3] + 2.0 * s[4] + s[5];
+  if (dff_of(A7, thres) < 1.0) { c.branch = 5; return c; }
+  if (order == 7) { c.branch = 7; return c; }
+  const double A9 = 2.0 * s[0] + 2.0 * s[1] + 2.0 * s[2] + 2.0 * s[3] + 2.0 * s[4] + 2.0 * s[5];
+  c.branch = (dff_of(A9, thres) < 1.0) ? 7 : 9;
+  return c;
+}
+
+// AO(5,3) with DFF-scaled members (Eq. 3.11-3.17, 3.19) collapsed into one
+// quartic in xi: P = Q0 (1 - sum w_k al_k) + sum w_k al_k p_k, with
+// w_3 = omega_3/g_3 and w_k = omega_k - omega_3 g_k/g_3.
+template <typename T>
+CGKS_HD __forceinline__ void ao_poly(const T* d, const Cascade& cs, const Consts& C, T* P) {
+  T c0[3], c1[3], c2[3], c3[5];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    T a = 0, b = 0, e = 0;
+#pragma unroll
+    for (int s = 0; s < 9; ++s) {
+      a += T(kC_S0[k][s]) * d[s];
+      b += T(kC_S1[k][s]) * d[s];
+      e += T(kC_S2[k][s]) * d[s];
+    }
+    c0[k] = a; c1[k] = b; c2[k] = e;
+  }
+#pragma unroll
+  for (int k = 0; k < 5; ++k) {
+    T a = 0;
+#pragma unroll
+    for (int s = 0; s < 9; ++s) a += T(kC_R5[k][s]) * d[s];
+    c3[k] = a;
+  }
+  // smoothness indicators (Eq. 3.13 in xi units) of the unscaled members
+  const T b0 = c0[1] * c0[1] + T(13.0 / 3.0) * c0[2] * c0[2];
+  const T b1 = c1[1] * c1[1] + T(13.0 / 3.0) * c1[2] * c1[2];
+  const T b2 = c2[1] * c2[1] + T(13.0 / 3.0) * c2[2] * c2[2];
+  const T q1 = c3[1], q2 = c3[2], q3 = c3[3], q4 = c3[4];
+  const T b3 = q1 * q1 + (T(4) * q2 * q2 + T(6) * q1 * q3) / T(12) + (T(9) * q3 * q3 + T(16) * q2 * q4) / T(80) +
+               T(16) * q4 * q4 / T(448) + T(4) * q2 * q2 + (T(36) * q3 * q3 + T(48) * q2 * q4) / T(12) +
+               T(144) * q4 * q4 / T(80) + T(36) * q3 * q3 + T(48) * q4 * q4 + T(576) * q4 * q4;
+  // the DFF scaling of a member scales its indicator by alpha^2
+  const T al0 = T(cs.al[0]), al1 = T(cs.al[1]), al2 = T(cs.al[2]), al3 = T(cs.al[3]);
+  const T B0 = al0 * al0 * b0, B1 = al1 * al1 * b1, B2 = al2 * al2 * b2, B3 = al3 * al3 * b3;
+  const T g3 = T(C.ghi), g0 = T((1.0 - C.ghi) * (1.0 - C.glo) / 2.0), g2 = T((1.0 - C.ghi) * C.glo);
+  const T tz = (fabs(B3 - B0) + fabs(B3 - B1) + fabs(B3 - B2)) / T(3);
+  const T eps = T(C.eps);
+  T r;
+  r = tz / (B0 + eps); const T w0 = g0 * (T(1) + r * r);
+  r = tz / (B1 + eps); const T w1 = g0 * (T(1) + r * r);
+  r = tz / (B2 + eps); const T w2 = g2 * (T(1) + r * r);
+  r = tz / (B3 + eps); const T w3 = g3 * (T(1) + r * r);
+  const T ws = T(1) / (w0 + w1 + w2 + w3);
+  const T o0 = w0 * ws, o1 = w1 * ws, o2 = w2 * ws, o3 = w3 * ws;
+  const T k3 = o3 / g3;
+  const T k0 = (o0 - k3 * g0) * al0, k1 = (o1 - k3 * g0) * al1, k2 = (o2 - k3 * g2) * al2, kk3 = k3 * al3;
+  P[0] = d[2] * (T(1) - k0 - k1 - k2 - kk3) + k0 * c0[0] + k1 * c1[0] + k2 * c2[0] + kk3 * c3[0];
+  P[1] = k0 * c0[1] + k1 * c1[1] + k2 * c2[1] + kk3 * c3[1];
+  P[2] = k0 * c0[2] + k1 * c1[2] + k2 * c2[2] + kk3 * c3[2];
+  P[3] = kk3 * c3[3];
+  P[4] = kk3 * c3[4];
+}
+
+template <typename T>
+CGKS_HD __forceinline__ T poly4(const T* P, T x, int deriv) {
+  if (deriv == 0) return P[0] + x * (P[1] + x * (P[2] + x * (P[3] + x * P[4])));
+  if (deriv == 1) return P[1] + x * (T(2) * P[2] + x * (T(3) * P[3] + x * T(4) * P[4]));
+  return T(2) * P[2] + x * (T(6) * P[3] + x * T(12) * P[4]);
+}
+
+// value, d/dxi and d2/dxi2 at xi = +1/2 (side 0) and xi = -1/2 (side 1) of
+// every component; d[v][9] are the stencil data of component v.
+template <typename T, int NVAR>
+CGKS_HD __forceinline__ void recon_faces(const T (&d)[NVAR][9], const Cascade& cs, const Consts& C,
+                                            T (&out)[2][3][NVAR]) {
+  if (cs.branch == 0) {
+#pragma unroll
+    for (int v = 0; v < NVAR; ++v) {
+      T P[5];
+      ao_poly<T>(d[v], cs, C, P);
+#pragma unroll
+      for (int dd = 0; dd < 3; ++dd) {
+        out[0][dd][v] = poly4<T>(P, T(0.5), dd);
+        out[1][dd][v] = poly4<T>(P, T(-0.5), dd);
+      }
+    }
+    return;
+  }
+  const double(*F)[3][9] = cs.branch == 5 ? kF_R5 : (cs.branch == 7 ? kF_R7 : kF_R9);
+#pragma unroll
+  for (int v = 0; v < NVAR; ++v)
+#pragma unroll
+    for (int sd = 0; sd < 2; ++sd)
+#pragma unroll
+      for (int dd = 0; dd < 3; ++dd) {
+        T a = 0;
+#pragma unroll
+        for (int s = 0; s < 9; ++s) a += T(F[sd][dd][s]) * d[v][s];
+        out[sd][dd][v] = a;
+      }
+}
+
+// values at the m Gauss points of the cell
+template <typename T, int NVAR>
+CGKS_HD __forceinline__ void recon_nodes(const T (&d)[NVAR][9], const Cascade& cs, const Consts& C,
+                                            T (&out)[4][NVAR]) {
+  const int m = C.m;
+  if (cs.branch == 0) {
+#pragma unroll
+    for (int v = 0; v < NVAR; ++v) {
+      T P[5];
+      ao_poly<T>(d[v], cs, C, P);
+#pragma unroll
+      for (int l = 0; l < 4; ++l)
+        if (l < m) out[l][v] = poly4<T>(P, T(kGx[m][l]), 0);
+    }
+    return;
+  }
+  const double(*N)[4][9] = cs.branch == 5 ? kN_R5 : (cs.branch == 7 ? kN_R7 : kN_R9);
+#pragma unroll
+  for (int v = 0; v < NVAR; ++v)
+#pragma unroll
+    for (int l = 0; l < 4; ++l) {
+      if (l >= m) continue;
+      T a = 0;
+#pragma unroll
+      for (int s = 0; s < 9; ++s) a += T(N[m][l][s]) * d[v][s];
+      out[l][v] = a;
+    }
+}
+
+}  // namespace cgks

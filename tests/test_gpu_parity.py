@@ -1,0 +1,168 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 CPU oracle on the
+same seeded inputs.  FP64: relative L1 <= 1e-10 per conserved variable, for
+cell averages and slopes; FP32-flux: <= 1e-5 on smooth data."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2508_13705_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-10
+
+
+def rel_l1(a, b, axes):
+    return np.abs(a - b).sum(axis=axes) / np.maximum(np.abs(b).sum(axis=axes), 1e-300)
+
+
+def run_both(pb, precision="fp64", **kw):
+    from paper_2508_13705_amd import cgks
+    print(f"\n[parity] {pb['name']} {pb['grid']['nx']}x{pb['grid'].get('ny', 1)} order {pb['scheme']['order']} "
+          f"{precision}", flush=True)
+    s = cgks.Solver(pb, precision=precision)
+    s.run(**kw)
+    got = s.read()
+    ref = oracle.run(pb, **kw)
+    return got, ref, s
+
+
+def errors(got, ref, dim, h):
+    """Relative L1 per conserved variable (max over variables).  Slopes are
+    compared as h * slope relative to the cell averages: the reconstruction
+    consumes them in that form, and their rounding noise scales as |W| / h."""
+    ax = (1, 2) if dim == 2 else (1,)
+    norm = np.abs(ref["avg"]).sum(axis=ax)
+    e = {"avg": (np.abs(got["avg"] - ref["avg"]).sum(axis=ax) / norm).max()}
+    axs = (1, 2, 3) if dim == 2 else (1,)
+    m = ref["sx"].shape[1] if dim == 2 else 1
+    e["sx"] = (h * np.abs(got["sx"] - ref["sx"]).sum(axis=axs) / (m * norm)).max()
+    if dim == 2:
+        e["sy"] = (h * np.abs(got["sy"] - ref["sy"]).sum(axis=axs) / (m * norm)).max()
+    return e
+
+
+def cell(pb):
+    g = pb["grid"]
+    return (g["x1"] - g["x0"]) / g["nx"]
+
+
+def assert_parity(got, ref, dim, tol=TOL64, slope_tol=None, h=1.0):
+    assert got["status"] == ref["status"]
+    assert abs(got["t"] - ref["t"]) <= 1e-13 * max(1.0, abs(ref["t"]))
+    assert got["steps"] == ref["stats"]["steps"]
+    if ref["status"] != 0:
+        return   # both stopped after the same step; the states hold nonphysical values
+    e = errors(got, ref, dim, h)
+    print("[parity] errors", e, flush=True)
+    assert e["avg"] <= tol, e
+    st = tol if slope_tol is None else slope_tol
+    for k in ("sx", "sy"):
+        if k in e:
+            assert e[k] <= st, e
+
+
+def test_fourier_1d_order5():
+    pb = W.fourier_1d()          # 256 cells, order 5, CFL 0.5, 100 steps
+    got, ref, _ = run_both(pb)
+    assert_parity(got, ref, 1, h=cell(pb))
+
+
+@pytest.mark.parametrize("order", [5, 7, 9])
+def test_shock_tube_1d(order):
+    pb = W.shock_tube("sod", 100, order)
+    got, ref, s = run_both(pb)
+    assert_parity(got, ref, 1, h=cell(pb))
+    assert np.abs(got["sigx"] - ref["sigx"]).max() <= 1e-9 * max(1.0, np.abs(ref["sigx"]).max())
+
+
+def test_riemann_batch_members_1d():
+    """Members of the 1-D Riemann batch (cell counts cut to keep the oracle fast)."""
+    probs = W.riemann_batch(seed=2, count=6)
+    for pb in probs:
+        n = pb["grid"]["nx"] // 10 + 40
+        L, R = pb["riemann"]["left"], pb["riemann"]["right"]
+        small = W.riemann_1d(L, R, n, 9, 0.15, xs=(n // 2) / n)
+        got, ref, _ = run_both(small, nsteps=30)
+        assert_parity(got, ref, 1, h=cell(small))
+
+
+@pytest.mark.parametrize("order", [5, 7, 9])
+def test_advection_2d(order):
+    pb = W.advection_2d(order, 10)
+    pb["run"]["nsteps"] = 6
+    got, ref, _ = run_both(pb)
+    assert_parity(got, ref, 2, h=cell(pb))
+
+
+@pytest.mark.parametrize("order,n,ny", [(7, 24, 24), (9, 37, 23), (5, 19, 31)])
+def test_quadrant_2d_ragged(order, n, ny):
+    pb = W.quadrant_2d(W.random_quadrants(3), n, order, nsteps=6)
+    pb["grid"]["ny"] = ny
+    pb["state"] = W.quadrant_2d(W.random_quadrants(3), max(n, ny), order)["state"]
+    pb["state"] = {k: v[..., :ny, :n] for k, v in pb["state"].items()}
+    got, ref, _ = run_both(pb)
+    assert_parity(got, ref, 2, h=cell(pb))
+
+
+def test_config3_reflective_2d():
+    pb = W.quadrant_2d(W.CONFIG3, 20, 9, nsteps=5, bc="reflective")
+    got, ref, _ = run_both(pb)
+    assert_parity(got, ref, 2, h=cell(pb))
+
+
+def test_turbulence_viscous_2d():
+    pb = W.turbulence_2d(seed=4, n=24, order=9, nsteps=4, kmax=4, prandtl=1.0, mu=1e-3)
+    got, ref, _ = run_both(pb)
+    assert_parity(got, ref, 2, h=cell(pb))
+
+
+def test_fourier_2d_periodic():
+    pb = W.fourier_2d(5, 20, 7, nsteps=8)
+    got, ref, _ = run_both(pb)
+    assert_parity(got, ref, 2, h=cell(pb))
+
+
+def test_resume_equals_uninterrupted():
+    """The state plus the interface strengths is a checkpoint."""
+    from paper_2508_13705_amd import cgks
+    pb = W.quadrant_2d(W.CONFIG3, 16, 7, nsteps=6)
+    a = cgks.Solver(pb)
+    a.step(6)
+    ra = a.read()
+    b = cgks.Solver(pb)
+    b.step(3)
+    mid = b.read()
+    c = cgks.Solver(dict(pb, state={"avg": mid["avg"], "sx": mid["sx"], "sy": mid["sy"]}),
+                    sigma=(mid["sigx"], mid["sigy"]), t0=mid["t"])
+    c.step(3)
+    rc = c.read()
+    assert np.array_equal(ra["avg"], rc["avg"]) and np.array_equal(ra["sx"], rc["sx"])
+    assert ra["t"] == rc["t"]
+
+
+def test_fp32_flux_smooth_1d():
+    pb = W.fourier_1d()
+    got, ref, _ = run_both(pb, precision="fp32_flux")
+    e = errors(got, ref, 1, cell(pb))
+    print("[parity fp32]", e, flush=True)
+    assert e["avg"] <= 1e-5
+
+
+def test_fp32_flux_smooth_2d():
+    pb = W.fourier_2d(5, 20, 9, nsteps=8)
+    got, ref, _ = run_both(pb, precision="fp32_flux")
+    e = errors(got, ref, 2, cell(pb))
+    print("[parity fp32]", e, flush=True)
+    assert e["avg"] <= 1e-5
+
+
+def test_nonphysical_state_is_reported():
+    from paper_2508_13705_amd import cgks
+    pb = W.quadrant_2d(W.CONFIG3, 12, 5, nsteps=1)
+    pb["state"]["avg"][3, 5, 5] = -1.0   # negative energy: p < 0
+    s = cgks.Solver(pb)
+    h = s.health()
+    assert h["status"] == cgks.ENONPHYSICAL and h["nonphysical"] >= 1
