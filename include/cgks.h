@@ -125,6 +125,17 @@ cgks_status cgks_init_state(const cgks_plan* plan, void* d_state, void* d_work, 
 cgks_status cgks_step(const cgks_plan* plan, void* d_state, void* d_work, double dt, double cfl, double t_end,
                       void* stream);
 
+/* Profiling variant of cgks_step: the same launches, with a HIP event
+ * recorded on `stream` around every kernel launch.  Synchronises `stream`,
+ * then writes the duration (ms) of each launch in launch order to
+ * kernel_ms[0..*count-1] (*count <= 16; kernel_ms must hold 16 entries).
+ * Names of the launches: cgks_kernel_name. */
+cgks_status cgks_step_timed(const cgks_plan* plan, void* d_state, void* d_work, double dt, double cfl,
+                            double t_end, void* stream, double* kernel_ms, int* count);
+
+/* Name of launch `index` of a step of this plan ("" when out of range). */
+const char* cgks_kernel_name(const cgks_plan* plan, int index);
+
 /* Copy the state back (synchronises `stream`).  Any pointer may be NULL.
  * Layouts as in cgks_init_state; h_time, h_steps: scalars.  Returns
  * CGKS_ENONPHYSICAL (after copying) if a nonphysical cell average was seen. */

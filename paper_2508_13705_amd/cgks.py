@@ -20,8 +20,9 @@ PRECISION = {"fp64": 0, "fp32_flux": 1}
 GAUSS_M = {5: 2, 7: 3, 9: 4}
 
 # every symbol include/cgks.h declares
-EXPORTS = ["cgks_plan_create", "cgks_plan_sizes", "cgks_init_state", "cgks_step", "cgks_read_state",
-           "cgks_query_health", "cgks_plan_destroy", "cgks_status_string", "cgks_last_error"]
+EXPORTS = ["cgks_plan_create", "cgks_plan_sizes", "cgks_init_state", "cgks_step", "cgks_step_timed",
+           "cgks_kernel_name", "cgks_read_state", "cgks_query_health", "cgks_plan_destroy", "cgks_status_string",
+           "cgks_last_error"]
 
 
 class CgksError(RuntimeError):
@@ -62,6 +63,10 @@ def lib():
         L.cgks_plan_sizes.argtypes = [vp, ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_size_t)]
         L.cgks_init_state.argtypes = [vp, vp, vp, dp, dp, dp, dp, dp, ctypes.c_double, vp]
         L.cgks_step.argtypes = [vp, vp, vp, ctypes.c_double, ctypes.c_double, ctypes.c_double, vp]
+        L.cgks_step_timed.argtypes = [vp, vp, vp, ctypes.c_double, ctypes.c_double, ctypes.c_double, vp, dp,
+                                      ctypes.POINTER(ctypes.c_int)]
+        L.cgks_kernel_name.restype = ctypes.c_char_p
+        L.cgks_kernel_name.argtypes = [vp, ctypes.c_int]
         L.cgks_read_state.argtypes = [vp, vp, vp, dp, dp, dp, dp, dp, dp, ctypes.POINTER(ctypes.c_longlong), vp]
         L.cgks_query_health.argtypes = [vp, vp, ctypes.POINTER(Health), vp]
         L.cgks_plan_destroy.argtypes = [vp]
@@ -69,7 +74,7 @@ def lib():
         L.cgks_status_string.argtypes = [ctypes.c_int]
         L.cgks_last_error.restype = ctypes.c_char_p
         for name in EXPORTS:
-            if name not in ("cgks_status_string", "cgks_last_error"):
+            if name not in ("cgks_status_string", "cgks_last_error", "cgks_kernel_name"):
                 getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -176,6 +181,17 @@ class Solver:
         sp, wp = ctypes.c_void_p(self.state.data_ptr()), ctypes.c_void_p(self.work.data_ptr())
         for _ in range(n):
             check(L.cgks_step(self.plan.handle, sp, wp, float(dt), float(cfl), float(t_end), st))
+
+    def step_timed(self, dt=0.0, cfl=None, t_end=0.0):
+        """One step with per-launch HIP event timing; returns [(name, ms), ...]."""
+        if cfl is None:
+            cfl = self.problem["scheme"].get("cfl", 0.5)
+        ms = (ctypes.c_double * 16)()
+        n = ctypes.c_int()
+        check(lib().cgks_step_timed(self.plan.handle, ctypes.c_void_p(self.state.data_ptr()),
+                                    ctypes.c_void_p(self.work.data_ptr()), float(dt), float(cfl), float(t_end),
+                                    _stream_handle(self.stream), ms, ctypes.byref(n)))
+        return [(lib().cgks_kernel_name(self.plan.handle, k).decode(), ms[k]) for k in range(n.value)]
 
     def run(self, nsteps=None, dt=None, t_end=None):
         """Advance as the problem's run block says (nsteps, fixed dt or CFL, t_end)."""

@@ -738,14 +738,27 @@ __global__ __launch_bounds__(256) void k_stage1d(Geo g, Consts C, Bufs B) {
 // ---------------------------------------------------------------------------
 // host-side launch helpers
 // ---------------------------------------------------------------------------
-hipError_t launch_bc_state(const cgks_plan* p, double* U, hipStream_t st) {
+// Optional per-launch event marks (cgks_step_timed): mark k is recorded on
+// the launch stream after launch k-1 and before launch k.
+struct Marks {
+  hipEvent_t ev[17];
+  int n = 0;
+  void tick(hipStream_t st) {
+    if (n < 17) hipEventRecord(ev[n++], st);
+  }
+};
+static inline void tick(Marks* mk, hipStream_t st) {
+  if (mk) mk->tick(st);
+}
+hipError_t launch_bc_state(const cgks_plan* p, double* U, hipStream_t st, Marks* mk = nullptr) {
   const Geo& g = p->g;
   dim3 grid((g.NX + 255) / 256, g.NY);
   hipLaunchKernelGGL(k_bc_state, grid, dim3(256), 0, st, g, U);
+  tick(mk, st);
   return hipGetLastError();
 }
 
-hipError_t launch_bc_sigma(const cgks_plan* p, const Bufs& b, hipStream_t st) {
+hipError_t launch_bc_sigma(const cgks_plan* p, const Bufs& b, hipStream_t st, Marks* mk = nullptr) {
   const Geo& g = p->g;
   dim3 gx((g.NX + 1 + 255) / 256, g.NY);
   hipLaunchKernelGGL(k_bc_sigma, gx, dim3(256), 0, st, g, 0, b.sxn, b.sxo, b.syn, b.syo);
@@ -753,46 +766,76 @@ hipError_t launch_bc_sigma(const cgks_plan* p, const Bufs& b, hipStream_t st) {
     dim3 gy((g.NY + 1 + 255) / 256, g.NX);
     hipLaunchKernelGGL(k_bc_sigma, gy, dim3(256), 0, st, g, 1, b.sxn, b.sxo, b.syn, b.syo);
   }
+  tick(mk, st);
   return hipGetLastError();
 }
 
 template <int M, typename T>
-hipError_t launch_stage2d(const cgks_plan* p, const Bufs& b, int stage, hipStream_t st) {
+hipError_t launch_stage2d(const cgks_plan* p, const Bufs& b, int stage, hipStream_t st, Marks* mk) {
   const Geo& g = p->g;
   using TL = Tile<M>;
   const double* Uin = stage == 1 ? b.U : b.S;
   {
     dim3 grid((g.NX + 255) / 256, g.NY);
     hipLaunchKernelGGL(k_lines<M>, grid, dim3(256), 0, st, g, p->C, Uin, b.sxo, b.syo, b.lvx, b.lvy, b.hdr);
+    tick(mk, st);
   }
   const size_t lds = Lds<M, T>::total;
   dim3 gx((g.nx + TL::NF - 2) / (TL::NF - 1), (g.ny + TL::NT - 1) / TL::NT);
   dim3 gy((g.ny + TL::NF - 2) / (TL::NF - 1), (g.nx + TL::NT - 1) / TL::NT);
   if (stage == 1) {
     hipLaunchKernelGGL((k_face2d<0, 1, M, T>), gx, dim3(256), lds, st, g, p->C, b);
+    tick(mk, st);
     hipLaunchKernelGGL((k_face2d<1, 1, M, T>), gy, dim3(256), lds, st, g, p->C, b);
+    tick(mk, st);
   } else {
     hipLaunchKernelGGL((k_face2d<0, 2, M, T>), gx, dim3(256), lds, st, g, p->C, b);
+    tick(mk, st);
     hipLaunchKernelGGL((k_face2d<1, 2, M, T>), gy, dim3(256), lds, st, g, p->C, b);
+    tick(mk, st);
   }
   return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_stage(const cgks_plan* p, const Bufs& b, int stage, hipStream_t st) {
+hipError_t launch_stage(const cgks_plan* p, const Bufs& b, int stage, hipStream_t st, Marks* mk) {
   const Geo& g = p->g;
   if (g.dim == 1) {
     dim3 grid((g.nx + 254) / 255);
     if (stage == 1) hipLaunchKernelGGL((k_stage1d<1, T>), grid, dim3(256), 0, st, g, p->C, b);
     else hipLaunchKernelGGL((k_stage1d<2, T>), grid, dim3(256), 0, st, g, p->C, b);
+    tick(mk, st);
     return hipGetLastError();
   }
   switch (g.m) {
-    case 2: return launch_stage2d<2, T>(p, b, stage, st);
-    case 3: return launch_stage2d<3, T>(p, b, stage, st);
-    default: return launch_stage2d<4, T>(p, b, stage, st);
+    case 2: return launch_stage2d<2, T>(p, b, stage, st, mk);
+    case 3: return launch_stage2d<3, T>(p, b, stage, st, mk);
+    default: return launch_stage2d<4, T>(p, b, stage, st, mk);
   }
 }
+
+// One step: dt, strengths, ghosts, stage 1, ghosts of U*, stage 2.
+hipError_t enqueue_step(const cgks_plan* p, const Bufs& b, double dt, double cfl, double t_end, hipStream_t st,
+                        Marks* mk) {
+  const Geo& g = p->g;
+  const double h = g.dim == 2 ? fmin(p->dx, p->dy) : p->dx;
+  tick(mk, st);
+  hipLaunchKernelGGL(k_dt, dim3(1), dim3(64), 0, st, b.hdr, dt, cfl, t_end, h, p->C.mu,
+                     p->C.tau_model == CGKS_TAU_VISCOUS ? 1 : 0);
+  tick(mk, st);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  if ((e = launch_bc_sigma(p, b, st, mk)) != hipSuccess) return e;
+  if ((e = launch_bc_state(p, b.U, st, mk)) != hipSuccess) return e;
+  e = p->precision == CGKS_FP64 ? launch_stage<double>(p, b, 1, st, mk) : launch_stage<float>(p, b, 1, st, mk);
+  if (e != hipSuccess) return e;
+  if ((e = launch_bc_state(p, b.S, st, mk)) != hipSuccess) return e;
+  return p->precision == CGKS_FP64 ? launch_stage<double>(p, b, 2, st, mk) : launch_stage<float>(p, b, 2, st, mk);
+}
+
+const char* kKernels1d[] = {"dt", "bc_sigma", "bc_state", "stage1_1d", "bc_state", "stage2_1d"};
+const char* kKernels2d[] = {"dt", "bc_sigma", "bc_state", "lines", "face_x_stage1", "face_y_stage1",
+                            "bc_state", "lines", "face_x_stage2", "face_y_stage2"};
 
 template <int M, typename T>
 hipError_t set_lds_attr() {
@@ -996,21 +1039,37 @@ cgks_status cgks_step(const cgks_plan* p, void* d_state, void* d_work, double dt
                       void* stream) {
   if (!p || !d_state || !d_work) return fail(CGKS_EINVAL, "NULL argument");
   if (!(dt > 0.0) && !(cfl > 0.0 && cfl <= 1.0)) return fail(CGKS_EINVAL, "cfl must lie in (0, 1]");
-  hipStream_t st = (hipStream_t)stream;
-  const Geo& g = p->g;
   Bufs b = bufs(p, d_state, d_work);
-  const double h = g.dim == 2 ? fmin(p->dx, p->dy) : p->dx;
-  hipLaunchKernelGGL(k_dt, dim3(1), dim3(64), 0, st, b.hdr, dt, cfl, t_end, h, p->C.mu,
-                     p->C.tau_model == CGKS_TAU_VISCOUS ? 1 : 0);
-  HIP_TRY(hipGetLastError());
-  HIP_TRY(launch_bc_sigma(p, b, st));
-  HIP_TRY(launch_bc_state(p, b.U, st));
-  if (p->precision == CGKS_FP64) HIP_TRY(launch_stage<double>(p, b, 1, st));
-  else HIP_TRY(launch_stage<float>(p, b, 1, st));
-  HIP_TRY(launch_bc_state(p, b.S, st));
-  if (p->precision == CGKS_FP64) HIP_TRY(launch_stage<double>(p, b, 2, st));
-  else HIP_TRY(launch_stage<float>(p, b, 2, st));
+  HIP_TRY(enqueue_step(p, b, dt, cfl, t_end, (hipStream_t)stream, nullptr));
   return CGKS_OK;
+}
+
+cgks_status cgks_step_timed(const cgks_plan* p, void* d_state, void* d_work, double dt, double cfl, double t_end,
+                            void* stream, double* kernel_ms, int* count) {
+  if (!p || !d_state || !d_work || !kernel_ms || !count) return fail(CGKS_EINVAL, "NULL argument");
+  if (!(dt > 0.0) && !(cfl > 0.0 && cfl <= 1.0)) return fail(CGKS_EINVAL, "cfl must lie in (0, 1]");
+  hipStream_t st = (hipStream_t)stream;
+  Marks mk;
+  for (int k = 0; k < 17; ++k) HIP_TRY(hipEventCreate(&mk.ev[k]));
+  Bufs b = bufs(p, d_state, d_work);
+  hipError_t e = enqueue_step(p, b, dt, cfl, t_end, st, &mk);
+  if (e == hipSuccess) e = hipEventSynchronize(mk.ev[mk.n - 1]);
+  const int n = mk.n - 1;
+  for (int k = 0; k < n && e == hipSuccess; ++k) {
+    float ms = 0.0f;
+    e = hipEventElapsedTime(&ms, mk.ev[k], mk.ev[k + 1]);
+    kernel_ms[k] = ms;
+  }
+  for (int k = 0; k < 17; ++k) hipEventDestroy(mk.ev[k]);
+  if (e != hipSuccess) return fail(CGKS_EHIP, std::string("timed step: ") + hipGetErrorString(e));
+  *count = n;
+  return CGKS_OK;
+}
+
+const char* cgks_kernel_name(const cgks_plan* p, int index) {
+  if (!p || index < 0) return "";
+  if (p->g.dim == 1) return index < 6 ? kKernels1d[index] : "";
+  return index < 10 ? kKernels2d[index] : "";
 }
 
 cgks_status cgks_read_state(const cgks_plan* p, const void* d_state, const void* d_work, double* h_avg,
