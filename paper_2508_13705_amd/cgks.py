@@ -11,7 +11,7 @@ import os
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libcgks.so")
+LIB_PATH = os.environ.get("CGKS_LIB", os.path.join(_HERE, "libcgks.so"))
 
 OK, EINVAL, ENOMEM, EHIP, ENONPHYSICAL, ESTATE, EBUDGET = range(7)
 BC = {"periodic": 0, "transmissive": 1, "reflective": 2}

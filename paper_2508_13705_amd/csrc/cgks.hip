@@ -57,7 +57,8 @@ struct Header {
   unsigned long long fallbacks;
   unsigned long long magic;
   int active;
-  int pad[15];
+  int nparts;      // per-block speed partials written by the last reduction
+  int pad[14];
 };
 static_assert(sizeof(Header) <= 256, "header");
 constexpr unsigned long long kMagic = 0x43474b5331ull;
@@ -92,6 +93,7 @@ struct Bufs {
   double* syn;
   double* lvx;
   double* lvy;
+  double* part;   // per-block [max(|U|+c), min(rho)] of the last reduction
   Header* hdr;
 };
 
@@ -103,7 +105,8 @@ struct cgks_plan {
   int precision;
   double dx, dy;
   size_t state_words, sig_x_words, sig_y_words;
-  size_t off_S, off_A, off_sxo, off_sxn, off_syo, off_syn, off_lvx, off_lvy, off_hdr, work_words;
+  size_t off_S, off_A, off_sxo, off_sxn, off_syo, off_syn, off_lvx, off_lvy, off_part, off_hdr, work_words;
+  size_t max_parts;
 };
 
 namespace {
@@ -120,6 +123,7 @@ Bufs bufs(const cgks_plan* p, void* d_state, void* d_work) {
   b.syn = w + p->off_syn;
   b.lvx = w + p->off_lvx;
   b.lvy = w + p->off_lvy;
+  b.part = w + p->off_part;
   b.hdr = (Header*)(w + p->off_hdr);
   return b;
 }
@@ -240,19 +244,25 @@ __global__ void k_init_sigma(Geo g, int which, double gam, const double* U, doub
 // ---------------------------------------------------------------------------
 // time step (Sec. 4): reduction of max(|U| + c) and min(rho), then dt
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ void reduce_speed(Header* hdr, double s, double r, bool valid) {
-  // wave-level max/min, one atomic per wave (positive doubles order as integers)
-  unsigned long long sb = valid ? __double_as_longlong(s) : 0ull;
-  unsigned long long rb = valid ? __double_as_longlong(r) : 0x7ff0000000000000ull;
+// Block-level max(|U| + c) and min(rho); thread 0 writes the block's partial
+// (reduced by k_dt before the next step).  Called by every thread of the block.
+__device__ __forceinline__ void reduce_speed(Bufs B, double s, double r, bool valid) {
+  __shared__ double red[2][16];
+  double sm = valid ? s : 0.0;
+  double rm = valid ? r : INFINITY;
   for (int off = 32; off > 0; off >>= 1) {
-    unsigned long long so = __shfl_xor(sb, off, 64);
-    unsigned long long ro = __shfl_xor(rb, off, 64);
-    sb = so > sb ? so : sb;
-    rb = ro < rb ? ro : rb;
+    sm = fmax(sm, __shfl_xor(sm, off, 64));
+    rm = fmin(rm, __shfl_xor(rm, off, 64));
   }
-  if ((threadIdx.x & 63) == 0) {
-    atomicMax(&hdr->smax_bits, sb);
-    atomicMin(&hdr->rmin_bits, rb);
+  const int w = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
+  if ((threadIdx.x & 63) == 0) { red[0][w] = sm; red[1][w] = rm; }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int k = 1; k < nw; ++k) { sm = fmax(sm, red[0][k]); rm = fmin(rm, red[1][k]); }
+    const int bid = blockIdx.x + gridDim.x * blockIdx.y;
+    B.part[2 * bid] = sm;
+    B.part[2 * bid + 1] = rm;
+    if (bid == 0) B.hdr->nparts = gridDim.x * gridDim.y;
   }
 }
 
@@ -265,7 +275,8 @@ __device__ __forceinline__ bool cell_speed(const double* W, int D, double gam, d
   return ok;
 }
 
-__global__ void k_reduce(Geo g, double gam, const double* U, Header* hdr) {
+__global__ void k_reduce(Geo g, double gam, const double* U, Bufs B) {
+  Header* hdr = B.hdr;
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   const int j = blockIdx.y;
   bool valid = i < g.nx;
@@ -279,18 +290,34 @@ __global__ void k_reduce(Geo g, double gam, const double* U, Header* hdr) {
       valid = false;
     }
   }
-  reduce_speed(hdr, s, r, valid);
+  reduce_speed(B, s, r, valid);
 }
 
-__global__ void k_dt(Header* hdr, double dt_fixed, double cfl, double t_end, double h, double mu, int viscous) {
+__global__ void k_dt(Header* hdr, const double* part, double dt_fixed, double cfl, double t_end, double h, double mu,
+                     int viscous) {
+  __shared__ double red[2][256];
+  const int np = hdr->nparts;
+  double sm = 0.0, rm = INFINITY;
+  for (int k = threadIdx.x; k < np; k += blockDim.x) {
+    sm = fmax(sm, part[2 * k]);
+    rm = fmin(rm, part[2 * k + 1]);
+  }
+  red[0][threadIdx.x] = sm;
+  red[1][threadIdx.x] = rm;
+  __syncthreads();
+  for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) {
+      red[0][threadIdx.x] = fmax(red[0][threadIdx.x], red[0][threadIdx.x + w]);
+      red[1][threadIdx.x] = fmin(red[1][threadIdx.x], red[1][threadIdx.x + w]);
+    }
+    __syncthreads();
+  }
   if (threadIdx.x != 0) return;
   double dt = dt_fixed;
   if (!(dt > 0.0)) {
-    const double smax = __longlong_as_double(hdr->smax_bits);
-    dt = cfl * h / smax;
+    dt = cfl * h / red[0][0];
     if (viscous && mu > 0.0) {
-      const double rmin = __longlong_as_double(hdr->rmin_bits);
-      const double dv = cfl * h * h * rmin / (4.0 * mu);
+      const double dv = cfl * h * h * red[1][0] / (4.0 * mu);
       if (dv < dt) dt = dv;
     }
   }
@@ -305,8 +332,6 @@ __global__ void k_dt(Header* hdr, double dt_fixed, double cfl, double t_end, dou
   if (active) {
     hdr->t += dt;
     hdr->steps += 1;
-    hdr->smax_bits = 0ull;
-    hdr->rmin_bits = 0x7ff0000000000000ull;
   }
 }
 
@@ -402,8 +427,12 @@ template <int M, typename T> struct Lds {
   static constexpr size_t total = main + fin;
 };
 
+#ifndef CGKS_FACE_WAVES
+#define CGKS_FACE_WAVES 2   // minimum waves per SIMD the face kernels are compiled for
+#endif
+
 template <int DIR, int STAGE, int M, typename T>
-__global__ __launch_bounds__(256, 2) void k_face2d(Geo g, Consts C, Bufs B) {
+__global__ __launch_bounds__(256, CGKS_FACE_WAVES) void k_face2d(Geo g, Consts C, Bufs B) {
   using TL = Tile<M>;
   constexpr int NF = TL::NF, NT = TL::NT, NC = TL::NC, NR = TL::NR;
   const Header* hdr = B.hdr;
@@ -625,7 +654,7 @@ __global__ __launch_bounds__(256, 2) void k_face2d(Geo g, Consts C, Bufs B) {
         if (!valid) atomicAdd((unsigned long long*)&B.hdr->nonphysical, 1ull);
       }
     }
-    if (STAGE == 2) reduce_speed(B.hdr, s, rr, valid);
+    if (STAGE == 2) reduce_speed(B, s, rr, valid);
   }
 }
 
@@ -732,7 +761,7 @@ __global__ __launch_bounds__(256) void k_stage1d(Geo g, Consts C, Bufs B) {
     valid = cell_speed(W, 1, C.gamma, s);
     if (!valid) atomicAdd((unsigned long long*)&B.hdr->nonphysical, 1ull);
   }
-  if (STAGE == 2) reduce_speed(B.hdr, s, rr, valid);
+  if (STAGE == 2) reduce_speed(B, s, rr, valid);
 }
 
 // ---------------------------------------------------------------------------
@@ -820,7 +849,7 @@ hipError_t enqueue_step(const cgks_plan* p, const Bufs& b, double dt, double cfl
   const Geo& g = p->g;
   const double h = g.dim == 2 ? fmin(p->dx, p->dy) : p->dx;
   tick(mk, st);
-  hipLaunchKernelGGL(k_dt, dim3(1), dim3(64), 0, st, b.hdr, dt, cfl, t_end, h, p->C.mu,
+  hipLaunchKernelGGL(k_dt, dim3(1), dim3(256), 0, st, b.hdr, b.part, dt, cfl, t_end, h, p->C.mu,
                      p->C.tau_model == CGKS_TAU_VISCOUS ? 1 : 0);
   tick(mk, st);
   hipError_t e = hipGetLastError();
@@ -941,6 +970,18 @@ cgks_status cgks_plan_create(const cgks_grid_desc* gd, const cgks_scheme_desc* s
   p->off_syn = o; o += up(p->sig_y_words);
   p->off_lvx = o; o += g.dim == 2 ? up(nv * m * cells) : 0;
   p->off_lvy = o; o += g.dim == 2 ? up(nv * m * cells) : 0;
+  {
+    // partials: the initial reduction grid, the 1-D stage grid, the 2-D y-face grid
+    size_t a = (size_t)((g.nx + 255) / 256) * (g.dim == 2 ? g.ny : 1);
+    size_t b1 = (size_t)((g.nx + 254) / 255);
+    size_t c = 0;
+    if (g.dim == 2) {
+      const int NT = g.m == 2 ? 8 : (g.m == 3 ? 5 : 4);
+      c = (size_t)((g.ny + 14) / 15) * ((g.nx + NT - 1) / NT);
+    }
+    p->max_parts = a > b1 ? (a > c ? a : c) : (b1 > c ? b1 : c);
+  }
+  p->off_part = o; o += up(2 * p->max_parts);
   p->off_hdr = o; o += 32;
   p->work_words = o;
   *out = p;
@@ -1028,7 +1069,7 @@ cgks_status cgks_init_state(const cgks_plan* p, void* d_state, void* d_work, con
   }
   {
     dim3 grid((nx + 255) / 256, g.dim == 2 ? ny : 1);
-    hipLaunchKernelGGL(k_reduce, grid, dim3(256), 0, st, g, p->C.gamma, b.U, b.hdr);
+    hipLaunchKernelGGL(k_reduce, grid, dim3(256), 0, st, g, p->C.gamma, b.U, b);
     HIP_TRY(hipGetLastError());
   }
   HIP_TRY(hipStreamSynchronize(st));
