@@ -64,7 +64,10 @@ typedef struct {
 /* Scheme parameters (Sec. 3.1, 3.2 and 4).  order 5, 7, 9 uses m = 2, 3, 4
  * Gauss points per face.  Collision time: CGKS_TAU_ZERO (tau = 0),
  * CGKS_TAU_INVISCID (tau = c1 dt + c2 |pl-pr|/(pl+pr) dt) or
- * CGKS_TAU_VISCOUS (tau = mu/p + c2 |pl-pr|/(pl+pr) dt).  prandtl must be 1.
+ * CGKS_TAU_VISCOUS (tau = mu/p + c2 |pl-pr|/(pl+pr) dt).  prandtl != 1 adds
+ * the standard gas-kinetic Prandtl-number fix to the energy flux: (1/Pr - 1)
+ * times the time-integrated heat flux in the frame of the interface
+ * equilibrium velocity (not part of the paper).
  * sigma_thres: the DFF threshold (1 for compact stencils); gamma_hi, gamma_lo:
  * linear weights of the AO(5,3) reconstruction; weno_eps: its epsilon.
  * precision: CGKS_FP64, or CGKS_FP32_FLUX (reconstruction and flux moments in
@@ -90,7 +93,7 @@ typedef struct {
 
 /* Validate the descriptors and build a plan (host metadata only).
  * Errors: CGKS_EINVAL (order not 5/7/9, gamma <= 1, nx/ny < 5, dim not 1/2,
- * inconsistent periodic ends, prandtl != 1, NULL pointers). */
+ * inconsistent periodic ends, prandtl <= 0, NULL pointers). */
 cgks_status cgks_plan_create(const cgks_grid_desc* grid, const cgks_scheme_desc* scheme, cgks_plan** out);
 
 /* Bytes of the caller-owned device buffers.  d_state holds the conserved

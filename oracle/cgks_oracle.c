@@ -442,6 +442,38 @@ static void flux_point(const orc_params* P, int D, const double Wl[6][4], const 
     psi_moment(tp[k], tm[k], treg[k], mval[k]);
   }
 
+  /* Prandtl-number fix of the energy flux (not part of this paper; the
+   * standard gas-kinetic correction, A18): the time integral q of the heat
+   * flux int (u-U0)/2 ((u-U0)^2 + (v-V0)^2 + xi^2) f in the frame of the
+   * equilibrium velocity, with the flux's own terms and weights, enters the
+   * energy flux as (1/Pr - 1) q.  Parity unpinned beyond invariants. */
+  double mheat[10] = {0};
+  const int prandtl_fix = (P->prandtl != 1.0);
+  if (prandtl_fix) {
+    const double U0 = m0.g.U, V0 = (D == 2) ? m0.g.V : 0.0;
+    vpoly Phi;
+    vp_zero(&Phi);
+    vp_term(&Phi, 3, 0, 0, 0.5);
+    vp_term(&Phi, 2, 0, 0, -1.5 * U0);
+    vp_term(&Phi, 1, 0, 0, 1.5 * U0 * U0);
+    vp_term(&Phi, 0, 0, 0, -0.5 * U0 * U0 * U0);
+    vp_term(&Phi, 1, 0, 1, 0.5);
+    vp_term(&Phi, 0, 0, 1, -0.5 * U0);
+    if (D == 2) {
+      vp_term(&Phi, 1, 2, 0, 0.5);
+      vp_term(&Phi, 1, 1, 0, -V0);
+      vp_term(&Phi, 1, 0, 0, 0.5 * V0 * V0);
+      vp_term(&Phi, 0, 2, 0, -0.5 * U0);
+      vp_term(&Phi, 0, 1, 0, U0 * V0);
+      vp_term(&Phi, 0, 0, 0, -0.5 * U0 * V0 * V0);
+    }
+    for (int k = 0; k < 10; ++k) {
+      vpoly hp;
+      vp_mul(&hp, &Phi, tp[k]);
+      mheat[k] = vp_moment(&hp, tm[k], treg[k]);
+    }
+  }
+
   /* time weights: integral over [0, delta] for fluxes, value at t for W(t) */
   for (int which = 0; which < 2; ++which) {
     double d = (which == 0) ? 0.5 * dt : dt;
@@ -457,6 +489,11 @@ static void flux_point(const orc_params* P, int D, const double Wl[6][4], const 
       double sum = 0.0;
       for (int k = 0; k < 10; ++k) sum += w[k] * mflux[k][v];
       out[4 * which + v] = sum;
+    }
+    if (prandtl_fix) {
+      double q = 0.0;
+      for (int k = 0; k < 10; ++k) q += w[k] * mheat[k];
+      out[4 * which + nv - 1] += (1.0 / P->prandtl - 1.0) * q;
     }
   }
   for (int which = 0; which < 3; ++which) {

@@ -431,7 +431,7 @@ template <int M, typename T> struct Lds {
 #define CGKS_FACE_WAVES 2   // minimum waves per SIMD the face kernels are compiled for
 #endif
 
-template <int DIR, int STAGE, int M, typename T>
+template <int DIR, int STAGE, int M, typename T, bool PR>
 __global__ __launch_bounds__(256, CGKS_FACE_WAVES) void k_face2d(Geo g, Consts C, Bufs B) {
   using TL = Tile<M>;
   constexpr int NF = TL::NF, NT = TL::NT, NC = TL::NC, NR = TL::NR;
@@ -557,7 +557,7 @@ __global__ __launch_bounds__(256, CGKS_FACE_WAVES) void k_face2d(Geo g, Consts C
         atomicAdd((unsigned long long*)&B.hdr->fallbacks, 1ull);
       }
     }
-    gks_flux<T, 2>(Wk[0], Wk[1], dt, C, fo);
+    gks_flux<T, 2, PR>(Wk[0], Wk[1], dt, C, fo);
     have = true;
   }
   __syncthreads();
@@ -662,7 +662,7 @@ __global__ __launch_bounds__(256, CGKS_FACE_WAVES) void k_face2d(Geo g, Consts C
 // 1-D stage kernel: one thread per face; each reconstructs its two cells.
 // A block owns faces F0..F0+255 and updates cells F0..F0+254.
 // ---------------------------------------------------------------------------
-template <int STAGE, typename T>
+template <int STAGE, typename T, bool PR>
 __global__ __launch_bounds__(256) void k_stage1d(Geo g, Consts C, Bufs B) {
   const Header* hdr = B.hdr;
   if (!hdr->active) return;
@@ -720,7 +720,7 @@ __global__ __launch_bounds__(256) void k_stage1d(Geo g, Consts C, Bufs B) {
       }
     }
     FaceOut fo;
-    gks_flux<T, 1>(Wk[0], Wk[1], dt, C, fo);
+    gks_flux<T, 1, PR>(Wk[0], Wk[1], dt, C, fo);
 #pragma unroll
     for (int v = 0; v < 3; ++v) {
       if (STAGE == 1) {
@@ -799,7 +799,7 @@ hipError_t launch_bc_sigma(const cgks_plan* p, const Bufs& b, hipStream_t st, Ma
   return hipGetLastError();
 }
 
-template <int M, typename T>
+template <int M, typename T, bool PR>
 hipError_t launch_stage2d(const cgks_plan* p, const Bufs& b, int stage, hipStream_t st, Marks* mk) {
   const Geo& g = p->g;
   using TL = Tile<M>;
@@ -813,34 +813,40 @@ hipError_t launch_stage2d(const cgks_plan* p, const Bufs& b, int stage, hipStrea
   dim3 gx((g.nx + TL::NF - 2) / (TL::NF - 1), (g.ny + TL::NT - 1) / TL::NT);
   dim3 gy((g.ny + TL::NF - 2) / (TL::NF - 1), (g.nx + TL::NT - 1) / TL::NT);
   if (stage == 1) {
-    hipLaunchKernelGGL((k_face2d<0, 1, M, T>), gx, dim3(256), lds, st, g, p->C, b);
+    hipLaunchKernelGGL((k_face2d<0, 1, M, T, PR>), gx, dim3(256), lds, st, g, p->C, b);
     tick(mk, st);
-    hipLaunchKernelGGL((k_face2d<1, 1, M, T>), gy, dim3(256), lds, st, g, p->C, b);
+    hipLaunchKernelGGL((k_face2d<1, 1, M, T, PR>), gy, dim3(256), lds, st, g, p->C, b);
     tick(mk, st);
   } else {
-    hipLaunchKernelGGL((k_face2d<0, 2, M, T>), gx, dim3(256), lds, st, g, p->C, b);
+    hipLaunchKernelGGL((k_face2d<0, 2, M, T, PR>), gx, dim3(256), lds, st, g, p->C, b);
     tick(mk, st);
-    hipLaunchKernelGGL((k_face2d<1, 2, M, T>), gy, dim3(256), lds, st, g, p->C, b);
+    hipLaunchKernelGGL((k_face2d<1, 2, M, T, PR>), gy, dim3(256), lds, st, g, p->C, b);
     tick(mk, st);
   }
   return hipGetLastError();
 }
 
-template <typename T>
-hipError_t launch_stage(const cgks_plan* p, const Bufs& b, int stage, hipStream_t st, Marks* mk) {
+template <typename T, bool PR>
+hipError_t launch_stage_pr(const cgks_plan* p, const Bufs& b, int stage, hipStream_t st, Marks* mk) {
   const Geo& g = p->g;
   if (g.dim == 1) {
     dim3 grid((g.nx + 254) / 255);
-    if (stage == 1) hipLaunchKernelGGL((k_stage1d<1, T>), grid, dim3(256), 0, st, g, p->C, b);
-    else hipLaunchKernelGGL((k_stage1d<2, T>), grid, dim3(256), 0, st, g, p->C, b);
+    if (stage == 1) hipLaunchKernelGGL((k_stage1d<1, T, PR>), grid, dim3(256), 0, st, g, p->C, b);
+    else hipLaunchKernelGGL((k_stage1d<2, T, PR>), grid, dim3(256), 0, st, g, p->C, b);
     tick(mk, st);
     return hipGetLastError();
   }
   switch (g.m) {
-    case 2: return launch_stage2d<2, T>(p, b, stage, st, mk);
-    case 3: return launch_stage2d<3, T>(p, b, stage, st, mk);
-    default: return launch_stage2d<4, T>(p, b, stage, st, mk);
+    case 2: return launch_stage2d<2, T, PR>(p, b, stage, st, mk);
+    case 3: return launch_stage2d<3, T, PR>(p, b, stage, st, mk);
+    default: return launch_stage2d<4, T, PR>(p, b, stage, st, mk);
   }
+}
+
+template <typename T>
+hipError_t launch_stage(const cgks_plan* p, const Bufs& b, int stage, hipStream_t st, Marks* mk) {
+  return p->C.prandtl != 1.0 ? launch_stage_pr<T, true>(p, b, stage, st, mk)
+                             : launch_stage_pr<T, false>(p, b, stage, st, mk);
 }
 
 // One step: dt, strengths, ghosts, stage 1, ghosts of U*, stage 2.
@@ -866,17 +872,23 @@ const char* kKernels1d[] = {"dt", "bc_sigma", "bc_state", "stage1_1d", "bc_state
 const char* kKernels2d[] = {"dt", "bc_sigma", "bc_state", "lines", "face_x_stage1", "face_y_stage1",
                             "bc_state", "lines", "face_x_stage2", "face_y_stage2"};
 
-template <int M, typename T>
-hipError_t set_lds_attr() {
+template <int M, typename T, bool PR>
+hipError_t set_lds_attr_pr() {
   hipError_t e = hipSuccess;
   const int lds = (int)Lds<M, T>::total;
-  e = hipFuncSetAttribute((const void*)k_face2d<0, 1, M, T>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+  e = hipFuncSetAttribute((const void*)k_face2d<0, 1, M, T, PR>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
   if (e != hipSuccess) return e;
-  e = hipFuncSetAttribute((const void*)k_face2d<1, 1, M, T>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+  e = hipFuncSetAttribute((const void*)k_face2d<1, 1, M, T, PR>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
   if (e != hipSuccess) return e;
-  e = hipFuncSetAttribute((const void*)k_face2d<0, 2, M, T>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+  e = hipFuncSetAttribute((const void*)k_face2d<0, 2, M, T, PR>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
   if (e != hipSuccess) return e;
-  return hipFuncSetAttribute((const void*)k_face2d<1, 2, M, T>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+  return hipFuncSetAttribute((const void*)k_face2d<1, 2, M, T, PR>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+}
+
+template <int M, typename T>
+hipError_t set_lds_attr() {
+  hipError_t e = set_lds_attr_pr<M, T, false>();
+  return e != hipSuccess ? e : set_lds_attr_pr<M, T, true>();
 }
 
 }  // namespace
@@ -917,7 +929,7 @@ cgks_status cgks_plan_create(const cgks_grid_desc* gd, const cgks_scheme_desc* s
   if (gd->dim == 2 && (gd->bc[2] == CGKS_BC_PERIODIC) != (gd->bc[3] == CGKS_BC_PERIODIC))
     return fail(CGKS_EINVAL, "periodic y needs both ends periodic");
   if (sd->tau_model < 0 || sd->tau_model > 2) return fail(CGKS_EINVAL, "unknown tau model");
-  if (sd->prandtl != 1.0) return fail(CGKS_EINVAL, "only prandtl = 1 is supported");
+  if (!(sd->prandtl > 0.0)) return fail(CGKS_EINVAL, "prandtl must be > 0");
   if (sd->tau_model == CGKS_TAU_VISCOUS && !(sd->mu >= 0.0)) return fail(CGKS_EINVAL, "mu must be >= 0");
   if (!(sd->sigma_thres > 0.0)) return fail(CGKS_EINVAL, "sigma_thres must be > 0");
   if (!(sd->gamma_hi > 0.0 && sd->gamma_hi < 1.0 && sd->gamma_lo > 0.0 && sd->gamma_lo < 1.0))
@@ -946,6 +958,7 @@ cgks_status cgks_plan_create(const cgks_grid_desc* gd, const cgks_scheme_desc* s
   C.c1 = sd->c1;
   C.c2 = sd->c2;
   C.mu = sd->mu;
+  C.prandtl = sd->prandtl;
   C.thres = sd->sigma_thres;
   C.ghi = sd->gamma_hi;
   C.glo = sd->gamma_lo;

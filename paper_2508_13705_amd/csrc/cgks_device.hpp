@@ -18,7 +18,7 @@ namespace cgks {
 
 struct Consts {
   double gamma, Kd;          // Kd = 2/(gamma-1) = K + D (K internal degrees of freedom)
-  double c1, c2, mu;
+  double c1, c2, mu, prandtl;
   double thres, ghi, glo, eps;
   double dx, dy;
   int tau_model, order, m;
@@ -131,6 +131,34 @@ CGKS_HD __forceinline__ void micro(const T* b, T U, T V, T lam, T Kd, T* a) {
   }
 }
 
+// Raw moments of X = a u^AL v^BE that the heat flux needs:
+// [X u^3, X u^2, X u, X, X u v^2, X u v, X v^2, X v, X u xi^2, X xi^2]
+template <typename T, int D, int AL, int BE>
+CGKS_HD __forceinline__ void qraw(const T* a, const Mom<T>& M, T* r) {
+  r[0] = mS<T, D, AL + 3, BE>(a, M);
+  r[1] = mS<T, D, AL + 2, BE>(a, M);
+  r[2] = mS<T, D, AL + 1, BE>(a, M);
+  r[3] = mS<T, D, AL, BE>(a, M);
+  if (D == 2) {
+    r[4] = mS<T, D, AL + 1, BE + 2>(a, M);
+    r[5] = mS<T, D, AL + 1, BE + 1>(a, M);
+    r[6] = mS<T, D, AL, BE + 2>(a, M);
+    r[7] = mS<T, D, AL, BE + 1>(a, M);
+  } else {
+    r[4] = r[5] = r[6] = r[7] = T(0);
+  }
+  r[8] = mSx<T, D, AL + 1, BE>(a, M);
+  r[9] = mSx<T, D, AL, BE>(a, M);
+}
+
+// <X (u-U0)/2 ((u-U0)^2 + (v-V0)^2 + xi^2)> from the raw moments of X
+template <typename T, int D>
+CGKS_HD __forceinline__ T qcomb(const T* r, T U0, T V0) {
+  T q = r[0] - T(3) * U0 * r[1] + T(3) * U0 * U0 * r[2] - U0 * U0 * U0 * r[3] + r[8] - U0 * r[9];
+  if (D == 2) q += r[4] - T(2) * V0 * r[5] + V0 * V0 * r[2] - U0 * r[6] + T(2) * U0 * V0 * r[7] - U0 * V0 * V0 * r[3];
+  return T(0.5) * q;
+}
+
 template <typename T, int D>
 CGKS_HD __forceinline__ void primitive(const T* W, T gm1, T& rho, T& U, T& V, T& p) {
   rho = W[0];
@@ -149,8 +177,11 @@ struct FaceOut {
 
 // Interface flux at one Gauss point (normal = local x).  Wk[d][v]: d = 0 value,
 // 1 d/dn, 2 d/dt, 3 d2/dn2, 4 d2/dndt, 5 d2/dt2; components in the face frame
-// (rho, rho u_n, [rho u_t,] rho E).
-template <typename T, int D>
+// (rho, rho u_n, [rho u_t,] rho E).  PR: apply the Prandtl-number fix of the
+// energy flux, (1/Pr - 1) times the time-integrated heat flux in the frame of
+// the equilibrium velocity (the standard gas-kinetic correction; not part of
+// the paper).
+template <typename T, int D, bool PR = false>
 CGKS_HD void gks_flux(const T (&Wl)[6][4], const T (&Wr)[6][4], double dt, const Consts& C, FaceOut& o) {
   constexpr int NV = D + 2;
   const T gm1 = T(C.gamma - 1.0), Kd = T(C.Kd), K = T(C.Kd - D);
@@ -160,6 +191,11 @@ CGKS_HD void gks_flux(const T (&Wl)[6][4], const T (&Wr)[6][4], double dt, const
 #pragma unroll
     for (int v = 0; v < 4; ++v) dQ[q][v] = T(0);
   T pside[2], cside[2], un[2], ut[2];
+  T QR0[10], QR1[10];
+  if (PR) {
+#pragma unroll
+    for (int k = 0; k < 10; ++k) QR0[k] = QR1[k] = T(0);
+  }
 
 #pragma unroll
   for (int side = 0; side < 2; ++side) {
@@ -181,6 +217,12 @@ CGKS_HD void gks_flux(const T (&Wl)[6][4], const T (&Wr)[6][4], double dt, const
     mauv<T, D, 1, 0>(e0, M, t4);
 #pragma unroll
     for (int v = 0; v < NV; ++v) NF0[v] += rho * t4[v];
+    if (PR) {
+      T r10[10];
+      qraw<T, D, 0, 0>(e0, M, r10);
+#pragma unroll
+      for (int k = 0; k < 10; ++k) QR0[k] += rho * r10[k];
+    }
     // derivative sources: 1 n, 2 t, 3 nn, 4 nt, 5 tt (1-D: n, nn)
     constexpr int NDER = (D == 2) ? 5 : 2;
 #pragma unroll
@@ -200,6 +242,12 @@ CGKS_HD void gks_flux(const T (&Wl)[6][4], const T (&Wr)[6][4], double dt, const
         mauv<T, D, 1, 0>(a, M, t4);
 #pragma unroll
         for (int v = 0; v < NV; ++v) NW1[v] += rho * t4[v];
+        if (PR) {
+          T r10[10];
+          qraw<T, D, 1, 0>(a, M, r10);
+#pragma unroll
+          for (int k = 0; k < 10; ++k) QR1[k] += rho * r10[k];
+        }
       }
       if (D == 2 && q == 1) {
         mauv<T, D, 1, 1>(a, M, t4);
@@ -208,6 +256,12 @@ CGKS_HD void gks_flux(const T (&Wl)[6][4], const T (&Wr)[6][4], double dt, const
         mauv<T, D, 0, 1>(a, M, t4);
 #pragma unroll
         for (int v = 0; v < NV; ++v) NW1[v] += rho * t4[v];
+        if (PR) {
+          T r10[10];
+          qraw<T, D, 0, 1>(a, M, r10);
+#pragma unroll
+          for (int k = 0; k < 10; ++k) QR1[k] += rho * r10[k];
+        }
       }
     }
   }
@@ -291,6 +345,33 @@ CGKS_HD void gks_flux(const T (&Wl)[6][4], const T (&Wr)[6][4], double dt, const
 #pragma unroll
   for (int v = 0; v < 4; ++v) Ft[v] += t4[v];
 
+  // heat-flux moments of the Prandtl fix
+  T hA = T(0), hP1 = T(0), hPt = T(0), hN0 = T(0), hN1 = T(0);
+  if (PR) {
+    T ra[10], rb[10];
+    qraw<T, D, 0, 0>(AT, M0, ra);
+    hA = qcomb<T, D>(ra, U0, V0);
+    qraw<T, D, 1, 0>(an, M0, ra);
+    if (D == 2) {
+      qraw<T, D, 0, 1>(ab[1], M0, rb);
+#pragma unroll
+      for (int k = 0; k < 10; ++k) ra[k] += rb[k];
+    }
+    hP1 = qcomb<T, D>(ra, U0, V0);
+    qraw<T, D, 1, 0>(anT, M0, ra);
+    qraw<T, D, 0, 0>(ATT, M0, rb);
+#pragma unroll
+    for (int k = 0; k < 10; ++k) ra[k] += rb[k];
+    if (D == 2) {
+      qraw<T, D, 0, 1>(atT, M0, rb);
+#pragma unroll
+      for (int k = 0; k < 10; ++k) ra[k] += rb[k];
+    }
+    hPt = qcomb<T, D>(ra, U0, V0);
+    hN0 = qcomb<T, D>(QR0, U0, V0);
+    hN1 = qcomb<T, D>(QR1, U0, V0);
+  }
+
   // collision time (Sec. 4)
   const double pl = double(pside[0]), pr = double(pside[1]);
   const double jump = fabs((pl - pr) / (pl + pr));
@@ -319,6 +400,12 @@ CGKS_HD void gks_flux(const T (&Wl)[6][4], const T (&Wr)[6][4], double dt, const
       Fo[v] = r0 * (double(F0[v]) * (d - E0) + fa * 0.5 * d * d - tau * ((f1 + fa) * d + double(Ft[v]) * 0.5 * d * d) +
                     f1 * E1) +
               double(NF0[v]) * E0 - double(NF1[v]) * E1;
+    }
+    if (PR) {
+      const double ha = double(hA), hp = double(hP1);
+      const double q = r0 * (ha * 0.5 * d * d - tau * ((hp + ha) * d + double(hPt) * 0.5 * d * d) + hp * E1) +
+                       double(hN0) * E0 - double(hN1) * E1;
+      Fo[NV - 1] += (1.0 / C.prandtl - 1.0) * q;
     }
   }
 #pragma unroll

@@ -60,12 +60,17 @@ int main() {
     for (int d = 1; d < 6; ++d) { Wl[d][v] = 0.01 * (d + v); Wr[d][v] = 0.011 * (d + v); }
   }
   FaceOut o;
+  C.prandtl = 1.0;
   reset();
-  gks_flux<Fl, 2>(Wl, Wr, 1e-4, C, o);
+  gks_flux<Fl, 2, false>(Wl, Wr, 1e-4, C, o);
+  printf("flux2d (Pr = 1) flops %lld\n", flops());
+  C.prandtl = 0.72;
+  reset();
+  gks_flux<Fl, 2, true>(Wl, Wr, 1e-4, C, o);
   // the time combination in double: 2 flux integrals x 4 components x ~14 ops,
   // 3 interface values x 4 x ~8 ops, strength ~20, tau ~8
   const long long comb2 = 2 * 4 * 14 + 3 * 4 * 8 + 20 + 8;
-  printf("flux2d  flops %lld (+%lld double-side) div %lld transcendental %lld\n", flops(), comb2, fc::dv, fc::tr);
+  printf("flux2d (Pr fix) flops %lld (+%lld double-side) div %lld transcendental %lld\n", flops(), comb2, fc::dv, fc::tr);
   const long long flux2 = flops() + comb2;
   reset();
   C.m = 1;

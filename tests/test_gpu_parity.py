@@ -119,6 +119,20 @@ def test_turbulence_viscous_2d():
     assert_parity(got, ref, 2, h=cell(pb))
 
 
+def test_turbulence_prandtl_2d():
+    """Viscous turbulence at Pr = 0.72 (Prandtl fix of the energy flux)."""
+    pb = W.turbulence_2d(seed=4, n=24, order=9, nsteps=4, kmax=4, prandtl=0.72, mu=1e-3)
+    got, ref, _ = run_both(pb)
+    assert_parity(got, ref, 2, h=cell(pb))
+
+
+def test_viscous_shock_tube_prandtl_1d():
+    pb = W.shock_tube("sod", 80, 7, tau="viscous", mu=2e-3, prandtl=0.72)
+    pb["run"]["t_end"] = 0.05
+    got, ref, _ = run_both(pb)
+    assert_parity(got, ref, 1, h=cell(pb))
+
+
 def test_fourier_2d_periodic():
     pb = W.fourier_2d(5, 20, 7, nsteps=8)
     got, ref, _ = run_both(pb)

@@ -48,7 +48,7 @@ def test_plan_sizes_match_layout():
     (lambda g, s: s.update(gamma=1.0), "gamma"),
     (lambda g, s: g.update(nx=4), "5 cells"),
     (lambda g, s: g.update(bc=["periodic", "transmissive", "periodic", "periodic"]), "periodic"),
-    (lambda g, s: s.update(prandtl=0.72), "prandtl"),
+    (lambda g, s: s.update(prandtl=0.0), "prandtl"),
     (lambda g, s: s.update(sigma_thres=0.0), "sigma_thres"),
 ])
 def test_plan_rejects_bad_descriptors(mutate, frag):

@@ -175,3 +175,25 @@ def test_tau_models():
     assert abs(r["tau"] - (0.05 * dt + (0.5 / 1.5) * dt)) < 1e-15
     r = oracle.flux_point(dict(tau="zero"), 1, Wl, Wr, dt)
     assert r["tau"] == 0.0
+
+
+def test_prandtl_fix_invariants():
+    """Prandtl fix of the energy flux (not in the paper, parity unpinned):
+    no effect at Pr = 1 or in a uniform state, only the energy flux changes,
+    and the change is proportional to (1/Pr - 1)."""
+    rng = np.random.default_rng(4)
+    Wl = np.zeros((6, 4)); Wr = np.zeros((6, 4))
+    Wl[0] = cons2(1.0, 0.2, 0.1, 0.7); Wr[0] = cons2(1.02, 0.21, 0.09, 0.71)
+    Wl[1:] = rng.normal(scale=0.2, size=(5, 4)); Wr[1:] = rng.normal(scale=0.2, size=(5, 4))
+    base = dict(tau="viscous", mu=1e-3, c2=1.0)
+    a = oracle.flux_point(dict(base, prandtl=1.0), 2, Wl, Wr, 0.01)
+    b = oracle.flux_point(dict(base, prandtl=0.72), 2, Wl, Wr, 0.01)
+    c = oracle.flux_point(dict(base, prandtl=0.5), 2, Wl, Wr, 0.01)
+    assert np.array_equal(a["F1"][:3], b["F1"][:3]) and np.array_equal(a["W1"], b["W1"])
+    db, dc = b["F1"][3] - a["F1"][3], c["F1"][3] - a["F1"][3]
+    assert db != 0.0
+    assert abs(db / dc - (1 / 0.72 - 1) / (1 / 0.5 - 1)) < 1e-9
+    U = np.zeros((6, 4)); U[0] = Wl[0]
+    u1 = oracle.flux_point(dict(base, prandtl=1.0), 2, U, U, 0.01)
+    u2 = oracle.flux_point(dict(base, prandtl=0.72), 2, U, U, 0.01)
+    assert abs(u2["F1"][3] - u1["F1"][3]) < 1e-15
