@@ -157,6 +157,106 @@ cgks_status cgks_plan_destroy(cgks_plan* plan);
 const char* cgks_status_string(cgks_status s);
 const char* cgks_last_error(void);
 
+/* ------------------------------------------------------------------------
+ * Batches: many independent states of one dimension and precision advanced
+ * together.  Each phase of the step (dt, ghosts, Step 1 line values, x-face
+ * and y-face reconstruction + flux + update, per stage; Sec. 2.2, 3.3) is one
+ * persistent launch over the tiles of every job, computed by the same device
+ * code and with the same tiles as cgks_step: a job's result in a batch equals
+ * its result stepped alone.  Jobs may differ in grid size, order, boundary
+ * conditions, scheme parameters, dt/CFL, t_end and step limit; batched
+ * kernels take prandtl = 1 only.
+ *
+ * Life cycle: create -> add/remove jobs -> commit (uploads the job table,
+ * synchronises the stream) -> step or capture + launch -> poll -> read each
+ * job's state with cgks_read_state on its own plan and buffers -> remove ->
+ * commit ...  The job buffers stay caller-owned and must outlive the job's
+ * membership.  A batch is not thread-safe; its launches must be ordered on
+ * one stream at a time.
+ * ------------------------------------------------------------------------ */
+typedef struct cgks_batch cgks_batch;
+
+/* Progress of one job slot (cgks_batch_poll). */
+typedef struct {
+  double t;                 /* time reached */
+  double dt;                /* last step size (0 once stopped) */
+  long long steps;          /* completed steps */
+  int status;               /* 0 running, 1 finished (t_end or max_steps), 2 nonphysical */
+  int in_use;               /* 1 if the slot holds a job */
+} cgks_job_status;
+
+/* Launch shape of the persistent kernels: grid = (resident blocks per CU) x
+ * CUs x grid_mult; xcd_remap != 0 gives consecutive tiles to blocks of one
+ * XCD.  ms_per_step: the time measured by cgks_batch_tune (else 0). */
+typedef struct {
+  int grid_mult;
+  int xcd_remap;
+  float ms_per_step;
+} cgks_batch_tuning;
+
+/* Create an empty batch of up to max_jobs jobs (1..2^20).  hbm_budget_bytes
+ * bounds the sum of the jobs' state + work bytes (0: no bound).  Allocates
+ * the device job table (about 400 bytes per slot) on the current device.
+ * Errors: CGKS_EINVAL, CGKS_ENOMEM, CGKS_EHIP. */
+cgks_status cgks_batch_create(int dim, int precision, int max_jobs, size_t hbm_budget_bytes, cgks_batch** out);
+
+/* Release the table and any captured graph (not the jobs' buffers). */
+cgks_status cgks_batch_destroy(cgks_batch* batch);
+
+/* Admit a state initialised by cgks_init_state (reads its header
+ * synchronously).  The job runs until it has taken max_steps steps (> 0) or
+ * reached t_end (> 0), whichever comes first; dt > 0 fixes the step, else dt
+ * comes from cfl as in cgks_step.  Takes effect at the next commit; *slot
+ * receives the job's slot.  Errors: CGKS_EINVAL (dimension or precision
+ * differs from the batch, prandtl != 1, no stopping rule, bad cfl),
+ * CGKS_ESTATE (uninitialised work buffer), CGKS_EBUDGET (the budget or the
+ * slot table is full; nothing changed). */
+cgks_status cgks_batch_add(cgks_batch* batch, const cgks_plan* plan, void* d_state, void* d_work,
+                           long long max_steps, double dt, double cfl, double t_end, int* slot);
+
+/* Retire the job in `slot` (takes effect at the next commit; its buffers are
+ * the caller's again after that commit).  Errors: CGKS_EINVAL (empty slot). */
+cgks_status cgks_batch_remove(cgks_batch* batch, int slot);
+
+/* Upload the job table on `stream` and synchronise it.  Must follow any
+ * add/remove before the next step, launch or tune (else CGKS_ESTATE). */
+cgks_status cgks_batch_commit(cgks_batch* batch, void* stream);
+
+/* Enqueue nsteps steps of every committed job (no host synchronisation, no
+ * allocation, no copies).  Jobs that have stopped are skipped. */
+cgks_status cgks_batch_step(cgks_batch* batch, int nsteps, void* stream);
+
+/* Capture nsteps batch steps into a hipGraph held by the batch (replacing the
+ * previous one).  The graph reads the job table from device memory, so it
+ * stays valid across commits; cgks_batch_set_tuning / cgks_batch_tune drop
+ * it.  Errors: CGKS_EHIP. */
+cgks_status cgks_batch_capture(cgks_batch* batch, int nsteps);
+
+/* Launch the captured graph on `stream`.  Errors: CGKS_ESTATE (no graph, or
+ * the batch changed since the last commit). */
+cgks_status cgks_batch_launch(cgks_batch* batch, void* stream);
+
+/* Progress of every slot: out[0..max_jobs-1] (synchronises `stream`). */
+cgks_status cgks_batch_poll(cgks_batch* batch, cgks_job_status* out, void* stream);
+
+/* Jobs held, their state + work bytes, the device table bytes, and the grid
+ * of the persistent face (2-D) or stage (1-D) launch.  Any pointer may be NULL. */
+cgks_status cgks_batch_info(const cgks_batch* batch, int* njobs, size_t* bytes_used, size_t* table_bytes,
+                            int* grid_face);
+
+/* Set / read the launch shape (set drops a captured graph).
+ * Errors: CGKS_EINVAL (grid_mult outside 1..16). */
+cgks_status cgks_batch_set_tuning(cgks_batch* batch, const cgks_batch_tuning* tuning);
+cgks_status cgks_batch_get_tuning(const cgks_batch* batch, cgks_batch_tuning* tuning);
+
+/* Autotune the launch shape on the committed jobs: every candidate
+ * (grid_mult 1, 2, 4 x xcd_remap 0, 1) runs steps_per_trial real steps, timed
+ * with HIP events on `stream`; the fastest is kept and written to *chosen
+ * (may be NULL).  All candidates compute the same result, so the trial steps
+ * advance the jobs like ordinary steps.  Synchronises `stream`; drops a
+ * captured graph. */
+cgks_status cgks_batch_tune(cgks_batch* batch, int steps_per_trial, void* stream, cgks_batch_tuning* chosen);
+
 #ifdef __cplusplus
 }
 #endif

@@ -22,7 +22,10 @@ GAUSS_M = {5: 2, 7: 3, 9: 4}
 # every symbol include/cgks.h declares
 EXPORTS = ["cgks_plan_create", "cgks_plan_sizes", "cgks_init_state", "cgks_step", "cgks_step_timed",
            "cgks_kernel_name", "cgks_read_state", "cgks_query_health", "cgks_plan_destroy", "cgks_status_string",
-           "cgks_last_error"]
+           "cgks_last_error",
+           "cgks_batch_create", "cgks_batch_destroy", "cgks_batch_add", "cgks_batch_remove", "cgks_batch_commit",
+           "cgks_batch_step", "cgks_batch_capture", "cgks_batch_launch", "cgks_batch_poll", "cgks_batch_info",
+           "cgks_batch_set_tuning", "cgks_batch_get_tuning", "cgks_batch_tune"]
 
 
 class CgksError(RuntimeError):
@@ -48,6 +51,15 @@ class Health(ctypes.Structure):
     _fields_ = [("nonphysical", ctypes.c_longlong), ("fallbacks", ctypes.c_longlong), ("steps", ctypes.c_longlong)]
 
 
+class JobStatus(ctypes.Structure):
+    _fields_ = [("t", ctypes.c_double), ("dt", ctypes.c_double), ("steps", ctypes.c_longlong),
+                ("status", ctypes.c_int), ("in_use", ctypes.c_int)]
+
+
+class BatchTuning(ctypes.Structure):
+    _fields_ = [("grid_mult", ctypes.c_int), ("xcd_remap", ctypes.c_int), ("ms_per_step", ctypes.c_float)]
+
+
 _lib = None
 
 
@@ -70,6 +82,21 @@ def lib():
         L.cgks_read_state.argtypes = [vp, vp, vp, dp, dp, dp, dp, dp, dp, ctypes.POINTER(ctypes.c_longlong), vp]
         L.cgks_query_health.argtypes = [vp, vp, ctypes.POINTER(Health), vp]
         L.cgks_plan_destroy.argtypes = [vp]
+        L.cgks_batch_create.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_size_t, ctypes.POINTER(vp)]
+        L.cgks_batch_destroy.argtypes = [vp]
+        L.cgks_batch_add.argtypes = [vp, vp, vp, vp, ctypes.c_longlong, ctypes.c_double, ctypes.c_double,
+                                     ctypes.c_double, ctypes.POINTER(ctypes.c_int)]
+        L.cgks_batch_remove.argtypes = [vp, ctypes.c_int]
+        L.cgks_batch_commit.argtypes = [vp, vp]
+        L.cgks_batch_step.argtypes = [vp, ctypes.c_int, vp]
+        L.cgks_batch_capture.argtypes = [vp, ctypes.c_int]
+        L.cgks_batch_launch.argtypes = [vp, vp]
+        L.cgks_batch_poll.argtypes = [vp, ctypes.POINTER(JobStatus), vp]
+        L.cgks_batch_info.argtypes = [vp, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_size_t),
+                                      ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_int)]
+        L.cgks_batch_set_tuning.argtypes = [vp, ctypes.POINTER(BatchTuning)]
+        L.cgks_batch_get_tuning.argtypes = [vp, ctypes.POINTER(BatchTuning)]
+        L.cgks_batch_tune.argtypes = [vp, ctypes.c_int, vp, ctypes.POINTER(BatchTuning)]
         L.cgks_status_string.restype = ctypes.c_char_p
         L.cgks_status_string.argtypes = [ctypes.c_int]
         L.cgks_last_error.restype = ctypes.c_char_p
@@ -239,3 +266,89 @@ class Solver:
         if st not in (OK, ENONPHYSICAL):
             check(st)
         return {"nonphysical": h.nonphysical, "fallbacks": h.fallbacks, "steps": h.steps, "status": st}
+
+
+class Batch:
+    """Many Solver states of one dimension and precision advanced together by
+    the library's persistent batched kernels (include/cgks.h, cgks_batch_*).
+
+    Jobs are Solver objects (their plan and torch-owned buffers); the batch
+    keeps a reference to each job until it is removed and committed."""
+
+    def __init__(self, dim, precision="fp64", max_jobs=64, hbm_budget=0, stream=None):
+        import torch
+        self.torch = torch
+        self.dim = dim
+        self.precision = precision
+        self.max_jobs = max_jobs
+        self.stream = stream
+        h = ctypes.c_void_p()
+        check(lib().cgks_batch_create(dim, PRECISION[precision], max_jobs, int(hbm_budget), ctypes.byref(h)))
+        self.handle = h
+        self.jobs = {}
+        self._status = (JobStatus * max_jobs)()
+
+    def __del__(self):
+        if getattr(self, "handle", None) is not None and _lib is not None:
+            _lib.cgks_batch_destroy(self.handle)
+            self.handle = None
+
+    def add(self, solver, max_steps=0, dt=0.0, cfl=None, t_end=0.0):
+        """Admit a Solver (takes effect at commit); returns its slot.  Raises
+        CgksError with status EBUDGET when the budget or slot table is full."""
+        if cfl is None:
+            cfl = solver.problem["scheme"].get("cfl", 0.5)
+        slot = ctypes.c_int(-1)
+        check(lib().cgks_batch_add(self.handle, solver.plan.handle, ctypes.c_void_p(solver.state.data_ptr()),
+                                   ctypes.c_void_p(solver.work.data_ptr()), int(max_steps), float(dt), float(cfl),
+                                   float(t_end), ctypes.byref(slot)))
+        self.jobs[slot.value] = solver
+        return slot.value
+
+    def remove(self, slot):
+        check(lib().cgks_batch_remove(self.handle, int(slot)))
+        return self.jobs.pop(slot)
+
+    def commit(self):
+        check(lib().cgks_batch_commit(self.handle, _stream_handle(self.stream)))
+
+    def step(self, n=1):
+        check(lib().cgks_batch_step(self.handle, int(n), _stream_handle(self.stream)))
+
+    def capture(self, n):
+        check(lib().cgks_batch_capture(self.handle, int(n)))
+
+    def launch(self):
+        check(lib().cgks_batch_launch(self.handle, _stream_handle(self.stream)))
+
+    def poll(self):
+        """{slot: {t, dt, steps, status}} of the jobs held (synchronises)."""
+        check(lib().cgks_batch_poll(self.handle, self._status, _stream_handle(self.stream)))
+        out = {}
+        for k in range(self.max_jobs):
+            s = self._status[k]
+            if s.in_use:
+                out[k] = {"t": s.t, "dt": s.dt, "steps": s.steps, "status": s.status}
+        return out
+
+    def info(self):
+        n, used, tb, gf = ctypes.c_int(), ctypes.c_size_t(), ctypes.c_size_t(), ctypes.c_int()
+        check(lib().cgks_batch_info(self.handle, ctypes.byref(n), ctypes.byref(used), ctypes.byref(tb),
+                                    ctypes.byref(gf)))
+        return {"njobs": n.value, "bytes_used": used.value, "table_bytes": tb.value, "grid_face": gf.value}
+
+    def tuning(self):
+        t = BatchTuning()
+        check(lib().cgks_batch_get_tuning(self.handle, ctypes.byref(t)))
+        return {"grid_mult": t.grid_mult, "xcd_remap": t.xcd_remap, "ms_per_step": t.ms_per_step}
+
+    def set_tuning(self, grid_mult=1, xcd_remap=1):
+        t = BatchTuning(int(grid_mult), int(xcd_remap), 0.0)
+        check(lib().cgks_batch_set_tuning(self.handle, ctypes.byref(t)))
+
+    def tune(self, steps_per_trial=1):
+        """Autotune the launch shape on the committed jobs (runs 6 x
+        steps_per_trial real steps); returns the chosen shape."""
+        t = BatchTuning()
+        check(lib().cgks_batch_tune(self.handle, int(steps_per_trial), _stream_handle(self.stream), ctypes.byref(t)))
+        return {"grid_mult": t.grid_mult, "xcd_remap": t.xcd_remap, "ms_per_step": t.ms_per_step}

@@ -1,227 +1,17 @@
-// libcgks.so: kernels and C ABI of the ASE-DFF compact gas-kinetic scheme on
-// one MI355X (gfx950).  The C ABI is declared in include/cgks.h.
-//
-// Data layout (FP64, structure of arrays, ghost halo of H = 3 cells):
-//   state  = [avg: nv][NY][NX] [sx: nv][m][NY][NX] [sy: nv][m][NY][NX] (2-D)
-//            1-D: NY = 1, m = 1, no sy.  Cell (i, j) sits at (j+H)*NX + i+H.
-//   work   = [stage state U*][accumulator][sigx old/new][sigy old/new]
-//            [line values LVx, LVy: nv][m][NY][NX] (2-D)][header]
-//   sigx: [NY][NX+1], face F of row j at (j+H)*(NX+1) + F+H (1-D: one row)
-//   sigy: [NX][NY+1], face G of column i at (i+H)*(NY+1) + G+H
-//
-// One step (Sec. 2.2): dt -> strengths commit + ghosts -> stage 1 (Eq. 2.21,
-// slopes from W(dt/2)) -> ghosts of U* -> stage 2 (Eq. 2.22, 2.23; slopes from
-// Eq. 2.25, 2.29, 2.30).  The stage-1 kernels also write the accumulator
-//   Acc = W^n - (1/h) sum_l w_l [(8/3) F(dt/2) - (1/3) F(dt)],
-//   Acc_slope = [-(4/3) W(0) + (8/3) W(dt/2) - (1/3) W(dt)] / h,
-// so that stage 2 adds (4/3)[F*(dt) - 2 F*(dt/2)] and (4/3)[W*(0) - 2 W*(dt/2) + W*(dt)],
-// which is Eq. 2.19-2.23 and 2.25/2.29 combined.
-#include <hip/hip_runtime.h>
+// libcgks.so: single-grid kernels and the plan/state C ABI of the ASE-DFF
+// compact gas-kinetic scheme on one MI355X (gfx950).  The C ABI is declared in
+// include/cgks.h; the batched kernels live in cgks_batch.hip, the shared types
+// and per-tile device bodies in cgks_internal.hpp.
+#define CGKS_UNIT single
+#include "cgks_internal.hpp"
 
-#include <math.h>
-#include <stdio.h>
-#include <string.h>
-
-#include <string>
-#include <vector>
-
-#include "../../include/cgks.h"
-#include "cgks_device.hpp"
-
-using namespace cgks;
-
-#define H 3
+thread_local std::string cgks_g_err;
 
 namespace {
 
-thread_local std::string g_err;
-
-cgks_status fail(cgks_status s, const std::string& msg) {
-  g_err = msg;
-  return s;
-}
-
-#define HIP_TRY(expr)                                                                   \
-  do {                                                                                  \
-    hipError_t e_ = (expr);                                                             \
-    if (e_ != hipSuccess) return fail(CGKS_EHIP, std::string(#expr ": ") + hipGetErrorString(e_)); \
-  } while (0)
-
-struct Header {
-  double t;
-  double dt;
-  unsigned long long smax_bits;
-  unsigned long long rmin_bits;
-  unsigned long long steps;
-  unsigned long long nonphysical;
-  unsigned long long fallbacks;
-  unsigned long long magic;
-  int active;
-  int nparts;      // per-block speed partials written by the last reduction
-  int pad[14];
-};
-static_assert(sizeof(Header) <= 256, "header");
-constexpr unsigned long long kMagic = 0x43474b5331ull;
-
-// Geometry passed by value to every kernel.
-struct Geo {
-  int dim, nx, ny, NX, NY, m, nv;
-  int bc[4];
-  size_t cells;
-  __host__ __device__ size_t cell(int i, int j) const {
-    return (size_t)(dim == 2 ? j + H : 0) * NX + (i + H);
-  }
-  __host__ __device__ size_t avg(int v, int i, int j) const { return (size_t)v * cells + cell(i, j); }
-  __host__ __device__ size_t sx(int v, int l, int i, int j) const {
-    return (size_t)nv * cells + ((size_t)v * m + l) * cells + cell(i, j);
-  }
-  __host__ __device__ size_t sy(int v, int l, int i, int j) const {
-    return (size_t)nv * cells + (size_t)nv * m * cells + ((size_t)v * m + l) * cells + cell(i, j);
-  }
-  __host__ __device__ size_t lv(int v, int l, int i, int j) const { return ((size_t)v * m + l) * cells + cell(i, j); }
-  __host__ __device__ size_t sgx(int j, int F) const { return (size_t)(dim == 2 ? j + H : 0) * (NX + 1) + F + H; }
-  __host__ __device__ size_t sgy(int i, int G) const { return (size_t)(i + H) * (NY + 1) + G + H; }
-};
-
-struct Bufs {
-  double* U;      // state (W^n, then W^{n+1})
-  double* S;      // stage state W*
-  double* A;      // accumulator
-  double* sxo;    // strengths in use (previous step)
-  double* sxn;    // strengths computed in this step
-  double* syo;
-  double* syn;
-  double* lvx;
-  double* lvy;
-  double* part;   // per-block [max(|U|+c), min(rho)] of the last reduction
-  Header* hdr;
-};
-
-}  // namespace
-
-struct cgks_plan {
-  Geo g;
-  Consts C;
-  int precision;
-  double dx, dy;
-  size_t state_words, sig_x_words, sig_y_words;
-  size_t off_S, off_A, off_sxo, off_sxn, off_syo, off_syn, off_lvx, off_lvy, off_part, off_hdr, work_words;
-  size_t max_parts;
-};
-
-namespace {
-
-Bufs bufs(const cgks_plan* p, void* d_state, void* d_work) {
-  Bufs b;
-  double* w = (double*)d_work;
-  b.U = (double*)d_state;
-  b.S = w + p->off_S;
-  b.A = w + p->off_A;
-  b.sxo = w + p->off_sxo;
-  b.sxn = w + p->off_sxn;
-  b.syo = w + p->off_syo;
-  b.syn = w + p->off_syn;
-  b.lvx = w + p->off_lvx;
-  b.lvy = w + p->off_lvy;
-  b.part = w + p->off_part;
-  b.hdr = (Header*)(w + p->off_hdr);
-  return b;
-}
-
 // ---------------------------------------------------------------------------
-// boundary conditions (ghost cells and ghost faces)
+// single-grid kernels: one launch per phase, one block per tile
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ int src_cell(int k, int n, int lo, int hi, int& mir) {
-  mir = 0;
-  if (k < 0) {
-    if (lo == CGKS_BC_PERIODIC) return k + n;
-    mir = 1;
-    return -k - 1;
-  }
-  if (k >= n) {
-    if (hi == CGKS_BC_PERIODIC) return k - n;
-    mir = 1;
-    return 2 * n - 1 - k;
-  }
-  return k;
-}
-
-__device__ __forceinline__ int src_face(int F, int n, int lo, int hi) {
-  if (F < 0) return lo == CGKS_BC_PERIODIC ? F + n : -F;
-  if (F > n) return hi == CGKS_BC_PERIODIC ? F - n : 2 * n - F;
-  return F;
-}
-
-// Ghost cells mirror interior cells (transmissive, reflective) or wrap
-// (periodic).  Mirrored: averages copied, the slope normal to the mirror
-// negated, slopes along Gauss lines crossing the mirror taken at the mirrored
-// Gauss point; a reflective wall also makes the normal momentum odd.
-__global__ void k_bc_state(Geo g, double* U) {
-  const int I = blockIdx.x * blockDim.x + threadIdx.x;
-  const int J = blockIdx.y;
-  if (I >= g.NX) return;
-  const int i = I - H, j = (g.dim == 2) ? J - H : 0;
-  const bool gx = (i < 0 || i >= g.nx), gy = (g.dim == 2) && (j < 0 || j >= g.ny);
-  if (!gx && !gy) return;
-  int mx, my = 0;
-  const int si = src_cell(i, g.nx, g.bc[0], g.bc[1], mx);
-  const int sj = (g.dim == 2) ? src_cell(j, g.ny, g.bc[2], g.bc[3], my) : 0;
-  const bool rx = mx && (g.bc[i < 0 ? 0 : 1] == CGKS_BC_REFLECTIVE);
-  const bool ry = my && (g.bc[j < 0 ? 2 : 3] == CGKS_BC_REFLECTIVE);
-  for (int v = 0; v < g.nv; ++v) {
-    double odd = 1.0;
-    if (rx && v == 1) odd = -odd;
-    if (ry && v == 2) odd = -odd;
-    U[g.avg(v, i, j)] = odd * U[g.avg(v, si, sj)];
-    for (int l = 0; l < g.m; ++l) {
-      const int lx = my ? g.m - 1 - l : l;   // x-slope lines are horizontal: mirrored by a y-mirror
-      U[g.sx(v, l, i, j)] = (mx ? -odd : odd) * U[g.sx(v, lx, si, sj)];
-      if (g.dim == 2) {
-        const int ly = mx ? g.m - 1 - l : l;
-        U[g.sy(v, l, i, j)] = (my ? -odd : odd) * U[g.sy(v, ly, si, sj)];
-      }
-    }
-  }
-}
-
-// Commit the strengths computed in the previous step (new -> old) and fill
-// the ghost faces and ghost rows/columns of the old set.
-__global__ void k_bc_sigma(Geo g, int which, const double* sxn, double* sxo, const double* syn, double* syo) {
-  const int a = blockIdx.x * blockDim.x + threadIdx.x;
-  const int b = blockIdx.y;
-  if (which == 0) {
-    // x-faces: a = F + H in [0, NX], b = row J
-    if (a > g.NX) return;
-    const int F = a - H, j = (g.dim == 2) ? b - H : 0;
-    int my = 0;
-    const int sj = (g.dim == 2) ? src_cell(j, g.ny, g.bc[2], g.bc[3], my) : 0;
-    const int sF = src_face(F, g.nx, g.bc[0], g.bc[1]);
-    sxo[g.sgx(j, F)] = sxn[g.sgx(sj, sF)];
-  } else {
-    // y-faces: a = G + H in [0, NY], b = column I
-    if (a > g.NY) return;
-    const int G = a - H, i = b - H;
-    int mx = 0;
-    const int si = src_cell(i, g.nx, g.bc[0], g.bc[1], mx);
-    const int sG = src_face(G, g.ny, g.bc[2], g.bc[3]);
-    syo[g.sgy(i, G)] = syn[g.sgy(si, sG)];
-  }
-}
-
-__device__ __forceinline__ double sigma_pair(const double* Wl, const double* Wr, int D, double gam) {
-  auto pr = [&](const double* W) {
-    double ke = 0.5 * W[1] * W[1] / W[0];
-    if (D == 2) ke += 0.5 * W[2] * W[2] / W[0];
-    return (gam - 1.0) * (W[D + 1] - ke);
-  };
-  const double pl = pr(Wl), pp = pr(Wr);
-  const double cl = sqrt(gam * pl / Wl[0]), cr = sqrt(gam * pp / Wr[0]);
-  const double dp = fabs(pl - pp);
-  const double mn = Wl[1] / Wl[0] / cl - Wr[1] / Wr[0] / cr;
-  const double mt = (D == 2) ? Wl[2] / Wl[0] / cl - Wr[2] / Wr[0] / cr : 0.0;
-  return dp / pl + dp / pp + mn * mn + mt * mt;
-}
-
 // Strengths of the first step from the piecewise-constant states.
 __global__ void k_init_sigma(Geo g, int which, double gam, const double* U, double* sxn, double* syn) {
   const int a = blockIdx.x * blockDim.x + threadIdx.x;
@@ -241,38 +31,36 @@ __global__ void k_init_sigma(Geo g, int which, double gam, const double* U, doub
   }
 }
 
-// ---------------------------------------------------------------------------
-// time step (Sec. 4): reduction of max(|U| + c) and min(rho), then dt
-// ---------------------------------------------------------------------------
-// Block-level max(|U| + c) and min(rho); thread 0 writes the block's partial
-// (reduced by k_dt before the next step).  Called by every thread of the block.
-__device__ __forceinline__ void reduce_speed(Bufs B, double s, double r, bool valid) {
-  __shared__ double red[2][16];
-  double sm = valid ? s : 0.0;
-  double rm = valid ? r : INFINITY;
-  for (int off = 32; off > 0; off >>= 1) {
-    sm = fmax(sm, __shfl_xor(sm, off, 64));
-    rm = fmin(rm, __shfl_xor(rm, off, 64));
-  }
-  const int w = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
-  if ((threadIdx.x & 63) == 0) { red[0][w] = sm; red[1][w] = rm; }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    for (int k = 1; k < nw; ++k) { sm = fmax(sm, red[0][k]); rm = fmin(rm, red[1][k]); }
-    const int bid = blockIdx.x + gridDim.x * blockIdx.y;
-    B.part[2 * bid] = sm;
-    B.part[2 * bid + 1] = rm;
-    if (bid == 0) B.hdr->nparts = gridDim.x * gridDim.y;
-  }
+__global__ void k_bc_state(Geo g, double* U) {
+  bc_state_at(g, U, blockIdx.x * blockDim.x + threadIdx.x, blockIdx.y);
 }
 
-__device__ __forceinline__ bool cell_speed(const double* W, int D, double gam, double& s) {
-  const double r = W[0];
-  const double U = W[1] / r, V = (D == 2) ? W[2] / r : 0.0;
-  const double p = (gam - 1.0) * (W[D + 1] - 0.5 * r * (U * U + V * V));
-  const bool ok = (r > 0.0) && (p > 0.0) && isfinite(W[D + 1]);
-  s = ok ? sqrt(U * U + V * V) + sqrt(gam * p / r) : 0.0;
-  return ok;
+__global__ void k_bc_sigma(Geo g, int which, const double* sxn, double* sxo, const double* syn, double* syo) {
+  bc_sigma_at(g, which, sxn, sxo, syn, syo, blockIdx.x * blockDim.x + threadIdx.x, blockIdx.y);
+}
+
+__global__ void k_dt(Header* hdr, const double* part, double dt_fixed, double cfl, double t_end, double h, double mu,
+                     int viscous) {
+  dt_block(hdr, part, dt_fixed, cfl, t_end, h, mu, viscous, 0, nullptr);
+}
+
+template <int M>
+__global__ __launch_bounds__(256) void k_lines(Geo g, Consts C, const double* U, const double* sxo,
+                                               const double* syo, double* lvx, double* lvy, const Header* hdr) {
+  if (!hdr->active) return;
+  lines_at<M>(g, C, U, sxo, syo, lvx, lvy, blockIdx.x * blockDim.x + threadIdx.x, blockIdx.y);
+}
+
+template <int DIR, int STAGE, int M, typename T, bool PR>
+__global__ __launch_bounds__(256, FaceWaves<T>::value) void k_face2d(Geo g, Consts C, Bufs B) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  face2d_tile<DIR, STAGE, M, T, PR>(g, C, B, smem, blockIdx.x, blockIdx.y, gridDim.x, gridDim.y);
+}
+
+template <int STAGE, typename T, bool PR>
+__global__ __launch_bounds__(256) void k_stage1d(Geo g, Consts C, Bufs B) {
+  __shared__ double res[256][12];
+  stage1d_seg<STAGE, T, PR>(g, C, B, res, blockIdx.x, gridDim.x);
 }
 
 __global__ void k_reduce(Geo g, double gam, const double* U, Bufs B) {
@@ -290,478 +78,7 @@ __global__ void k_reduce(Geo g, double gam, const double* U, Bufs B) {
       valid = false;
     }
   }
-  reduce_speed(B, s, r, valid);
-}
-
-__global__ void k_dt(Header* hdr, const double* part, double dt_fixed, double cfl, double t_end, double h, double mu,
-                     int viscous) {
-  __shared__ double red[2][256];
-  const int np = hdr->nparts;
-  double sm = 0.0, rm = INFINITY;
-  for (int k = threadIdx.x; k < np; k += blockDim.x) {
-    sm = fmax(sm, part[2 * k]);
-    rm = fmin(rm, part[2 * k + 1]);
-  }
-  red[0][threadIdx.x] = sm;
-  red[1][threadIdx.x] = rm;
-  __syncthreads();
-  for (int w = blockDim.x / 2; w > 0; w >>= 1) {
-    if ((int)threadIdx.x < w) {
-      red[0][threadIdx.x] = fmax(red[0][threadIdx.x], red[0][threadIdx.x + w]);
-      red[1][threadIdx.x] = fmin(red[1][threadIdx.x], red[1][threadIdx.x + w]);
-    }
-    __syncthreads();
-  }
-  if (threadIdx.x != 0) return;
-  double dt = dt_fixed;
-  if (!(dt > 0.0)) {
-    dt = cfl * h / red[0][0];
-    if (viscous && mu > 0.0) {
-      const double dv = cfl * h * h * red[1][0] / (4.0 * mu);
-      if (dv < dt) dt = dv;
-    }
-  }
-  int active = 1;
-  if (hdr->nonphysical) { active = 0; dt = 0.0; }   // sticky: a nonphysical state stops the run
-  else if (t_end > 0.0) {
-    if (hdr->t >= t_end) { active = 0; dt = 0.0; }
-    else if (hdr->t + dt > t_end) dt = t_end - hdr->t;
-  }
-  hdr->dt = dt;
-  hdr->active = active;
-  if (active) {
-    hdr->t += dt;
-    hdr->steps += 1;
-  }
-}
-
-// ---------------------------------------------------------------------------
-// 2-D Step 1 (Sec. 3.3): tangential ASE-DFF in each column (row) gives the
-// line averages of the cell on the horizontal (vertical) Gauss lines.
-// ---------------------------------------------------------------------------
-template <int M>
-__global__ __launch_bounds__(256) void k_lines(Geo g, Consts C, const double* U, const double* sxo,
-                                               const double* syo, double* lvx, double* lvy, const Header* hdr) {
-  if (!hdr->active) return;
-  const int i = (int)(blockIdx.x * blockDim.x + threadIdx.x) - H;
-  const int j = (int)blockIdx.y - H;
-  if (i > g.nx + 2) return;
-  double wq[4];
-#pragma unroll
-  for (int l = 0; l < M; ++l) wq[l] = kGw[M][l];
-  // x-face line values: column i, rows j-2..j+2, needed for j in [-1, ny]
-  if (j >= -1 && j <= g.ny) {
-    double d[4][9], s[6];
-#pragma unroll
-    for (int f = 0; f < 6; ++f) s[f] = syo[g.sgy(i, j - 2 + f)];
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-#pragma unroll
-      for (int k = 0; k < 5; ++k) d[v][k] = U[g.avg(v, i, j + k - 2)];
-#pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        const int o = k < 2 ? k - 2 : k - 1;
-        double a = 0.0;
-#pragma unroll
-        for (int l = 0; l < M; ++l) a += wq[l] * U[g.sy(v, l, i, j + o)];
-        d[v][5 + k] = C.dy * a;
-      }
-    }
-    const Cascade cs = cascade(s, C.order, C.thres);
-    double out[4][4];
-    recon_nodes<double, 4>(d, cs, C, out);
-#pragma unroll
-    for (int l = 0; l < M; ++l)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) lvx[g.lv(v, l, i, j)] = out[l][v];
-  }
-  // y-face line values: row j, columns i-2..i+2, needed for i in [-1, nx]
-  if (i >= -1 && i <= g.nx && j >= -3 && j <= g.ny + 2) {
-    double d[4][9], s[6];
-#pragma unroll
-    for (int f = 0; f < 6; ++f) s[f] = sxo[g.sgx(j, i - 2 + f)];
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-#pragma unroll
-      for (int k = 0; k < 5; ++k) d[v][k] = U[g.avg(v, i + k - 2, j)];
-#pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        const int o = k < 2 ? k - 2 : k - 1;
-        double a = 0.0;
-#pragma unroll
-        for (int l = 0; l < M; ++l) a += wq[l] * U[g.sx(v, l, i + o, j)];
-        d[v][5 + k] = C.dx * a;
-      }
-    }
-    const Cascade cs = cascade(s, C.order, C.thres);
-    double out[4][4];
-    recon_nodes<double, 4>(d, cs, C, out);
-#pragma unroll
-    for (int l = 0; l < M; ++l)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) lvy[g.lv(v, l, i, j)] = out[l][v];
-  }
-}
-
-// ---------------------------------------------------------------------------
-// 2-D face kernel: Step 2 (normal ASE-DFF on every Gauss line), Step 3
-// (tangential derivatives), Step 4 (flux), and the cell update of one
-// direction.  DIR 0: x-faces (normal x), DIR 1: y-faces.
-// ---------------------------------------------------------------------------
-template <int M> struct Tile {
-  static constexpr int NF = 16;                               // faces along the normal
-  static constexpr int NT = M == 2 ? 8 : (M == 3 ? 5 : 4);    // lines along the tangential
-  static constexpr int NC = NF + 1;                           // reconstructed cells
-  static constexpr int NR = NT + 2;                           // reconstructed lines
-  static constexpr int RK1 = 17, RK2 = 8;                     // results per Gauss point (stage 1 / 2)
-};
-
-template <int M, typename T> struct Lds {
-  static constexpr size_t s2v = (size_t)Tile<M>::NR * Tile<M>::NC * M * 8 * sizeof(T);
-  static constexpr size_t s2d = s2v;
-  static constexpr size_t s2dd = (size_t)Tile<M>::NT * Tile<M>::NC * M * 8 * sizeof(T);
-  static constexpr size_t recon = s2v + s2d + s2dd;
-  static constexpr size_t res = (size_t)Tile<M>::NF * Tile<M>::NT * M * Tile<M>::RK1 * sizeof(double);
-  static constexpr size_t main = recon > res ? recon : res;
-  static constexpr size_t fin = (size_t)(Tile<M>::NF - 1) * Tile<M>::NT * 4 * sizeof(double);
-  static constexpr size_t total = main + fin;
-};
-
-#ifndef CGKS_FACE_WAVES
-#define CGKS_FACE_WAVES 2   // minimum waves per SIMD the face kernels are compiled for
-#endif
-
-template <int DIR, int STAGE, int M, typename T, bool PR>
-__global__ __launch_bounds__(256, CGKS_FACE_WAVES) void k_face2d(Geo g, Consts C, Bufs B) {
-  using TL = Tile<M>;
-  constexpr int NF = TL::NF, NT = TL::NT, NC = TL::NC, NR = TL::NR;
-  const Header* hdr = B.hdr;
-  if (!hdr->active) return;
-  const double dt = hdr->dt;
-  extern __shared__ __align__(16) unsigned char smem[];
-  T* s2v = (T*)smem;
-  T* s2d = (T*)(smem + Lds<M, T>::s2v);
-  T* s2dd = (T*)(smem + Lds<M, T>::s2v + Lds<M, T>::s2d);
-  double* res = (double*)smem;
-  double* fin = (double*)(smem + Lds<M, T>::main);
-  auto I2 = [&](int r, int c, int l, int sd, int v) { return (((r * NC + c) * M + l) * 2 + sd) * 4 + v; };
-
-  const int nmax = DIR == 0 ? g.nx : g.ny;   // cells along the normal
-  const int tmax = DIR == 0 ? g.ny : g.nx;   // cells along the tangential
-  const int F0 = blockIdx.x * (NF - 1);
-  const int T0 = blockIdx.y * NT;
-  const double hn = DIR == 0 ? C.dx : C.dy, ht = DIR == 0 ? C.dy : C.dx;
-  const double* Uin = STAGE == 1 ? B.U : B.S;
-  const double* LV = DIR == 0 ? B.lvx : B.lvy;
-  const double* sgN = DIR == 0 ? B.sxo : B.syo;   // normal-face strengths
-  const double* sgT = DIR == 0 ? B.syo : B.sxo;   // tangential-face strengths
-  const int gcomp[4] = {0, DIR == 0 ? 1 : 2, DIR == 0 ? 2 : 1, 3};
-  auto gi = [&](int n, int t) { return DIR == 0 ? n : t; };
-  auto gj = [&](int n, int t) { return DIR == 0 ? t : n; };
-  auto sN = [&](int v, int l, int n, int t) {  // normal slope on line l
-    return DIR == 0 ? g.sx(v, l, gi(n, t), gj(n, t)) : g.sy(v, l, gi(n, t), gj(n, t));
-  };
-  auto sgn_idx = [&](int t, int face) { return DIR == 0 ? g.sgx(t, face) : g.sgy(t, face); };
-  auto sgt_idx = [&](int n, int face) { return DIR == 0 ? g.sgy(n, face) : g.sgx(n, face); };
-
-  // ---- Step 2: normal reconstruction on each line, both faces of a cell ----
-  constexpr int NA = NC * NR * M;
-  for (int it = threadIdx.x; it < NA; it += blockDim.x) {
-    int c, r, l;
-    if (DIR == 0) { c = it % NC; r = (it / NC) % NR; l = it / (NC * NR); }
-    else { r = it % NR; c = (it / NR) % NC; l = it / (NC * NR); }
-    const int n = F0 - 1 + c, t = T0 - 1 + r;
-    if (n < -1 || n > nmax || t < -1 || t > tmax) continue;
-    double s[6];
-#pragma unroll
-    for (int f = 0; f < 6; ++f) s[f] = sgN[sgn_idx(t, n - 2 + f)];
-    const Cascade cs = cascade(s, C.order, C.thres);
-    T d[4][9];
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int gv = gcomp[v];
-#pragma unroll
-      for (int k = 0; k < 5; ++k) d[v][k] = T(LV[g.lv(gv, l, gi(n + k - 2, t), gj(n + k - 2, t))]);
-#pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        const int o = k < 2 ? k - 2 : k - 1;
-        d[v][5 + k] = T(hn * Uin[sN(gv, l, n + o, t)]);
-      }
-    }
-    T out[2][3][4];
-    recon_faces<T, 4>(d, cs, C, out);
-    const T ih = T(1.0 / hn), ih2 = T(1.0 / (hn * hn));
-#pragma unroll
-    for (int sd = 0; sd < 2; ++sd)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        s2v[I2(r, c, l, sd, v)] = out[sd][0][v];
-        s2d[I2(r, c, l, sd, v)] = out[sd][1][v] * ih;
-        if (r >= 1 && r <= NT) s2dd[I2(r - 1, c, l, sd, v)] = out[sd][2][v] * ih2;
-      }
-  }
-  __syncthreads();
-
-  // ---- Steps 3-4 at every face Gauss point ----
-  constexpr int NB = NF * NT * M;
-  FaceOut fo;
-  bool have = false;
-  int my_f = 0, my_r = 0, my_l = 0;
-  for (int it = threadIdx.x; it < NB; it += blockDim.x) {  // NB <= 256: one pass
-    int f, r, l;
-    if (DIR == 0) { f = it % NF; r = (it / NF) % NT; l = it / (NF * NT); }
-    else { r = it % NT; f = (it / NT) % NF; l = it / (NF * NT); }
-    my_f = f; my_r = r; my_l = l;
-    const int nf = F0 + f, t = T0 + r;
-    if (nf > nmax || t >= tmax) continue;
-    T Wk[2][6][4];
-#pragma unroll
-    for (int sd = 0; sd < 2; ++sd) {
-      const int c = sd == 0 ? f : f + 1;      // left state: cell nf-1 (its +1/2 face); right: cell nf
-      const int ncell = nf - 1 + sd;
-      double A = 0.0;
-#pragma unroll
-      for (int q = -1; q <= 2; ++q) A += sgT[sgt_idx(ncell, t + q)];
-      const T at = T(dff_of(A, C.thres));
-      const T it1 = at / T(ht), it2 = at / T(ht * ht);
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        Wk[sd][0][v] = s2v[I2(r + 1, c, l, sd, v)];
-        Wk[sd][1][v] = s2d[I2(r + 1, c, l, sd, v)];
-        Wk[sd][3][v] = s2dd[I2(r, c, l, sd, v)];
-        T a1 = 0, a2 = 0, ax = 0;
-#pragma unroll
-        for (int rr = 0; rr < 3; ++rr)
-#pragma unroll
-          for (int q = 0; q < M; ++q) {
-            const T w1 = T(kT1[M][l][rr * M + q]), w2 = T(kT2[M][l][rr * M + q]);
-            const T val = s2v[I2(r + rr, c, q, sd, v)];
-            a1 += w1 * val;
-            a2 += w2 * val;
-            ax += w1 * s2d[I2(r + rr, c, q, sd, v)];
-          }
-        Wk[sd][2][v] = it1 * a1;
-        Wk[sd][5][v] = it2 * a2;
-        Wk[sd][4][v] = it1 * ax;
-      }
-      // first order from the cell average where the state is nonphysical
-      T rho, U, V, p;
-      primitive<T, 2>(Wk[sd][0], T(C.gamma - 1.0), rho, U, V, p);
-      if (!(rho > T(0)) || !(p > T(0))) {
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          Wk[sd][0][v] = T(Uin[g.avg(gcomp[v], gi(ncell, t), gj(ncell, t))]);
-#pragma unroll
-          for (int dd = 1; dd < 6; ++dd) Wk[sd][dd][v] = T(0);
-        }
-        atomicAdd((unsigned long long*)&B.hdr->fallbacks, 1ull);
-      }
-    }
-    gks_flux<T, 2, PR>(Wk[0], Wk[1], dt, C, fo);
-    have = true;
-  }
-  __syncthreads();
-  // results to LDS (global component order)
-  if (have) {
-    double* rp = res + (((size_t)my_f * NT + my_r) * M + my_l) * (STAGE == 1 ? TL::RK1 : TL::RK2);
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int gv = gcomp[v];
-      if (STAGE == 1) {
-        rp[gv] = fo.Fh[v];
-        rp[4 + gv] = (8.0 / 3.0) * fo.Fh[v] - (1.0 / 3.0) * fo.F1[v];
-        rp[8 + gv] = fo.Wh[v];
-        rp[12 + gv] = -(4.0 / 3.0) * fo.W0[v] + (8.0 / 3.0) * fo.Wh[v] - (1.0 / 3.0) * fo.W1[v];
-      } else {
-        rp[gv] = (4.0 / 3.0) * (fo.F1[v] - 2.0 * fo.Fh[v]);
-        rp[4 + gv] = (4.0 / 3.0) * (fo.W0[v] - 2.0 * fo.Wh[v] + fo.W1[v]);
-      }
-    }
-    if (STAGE == 1) rp[16] = fo.sigma;
-  }
-  __syncthreads();
-
-  // ---- strengths of this step (stage 1): mean over the Gauss points ----
-  if (STAGE == 1) {
-    for (int it = threadIdx.x; it < NF * NT; it += blockDim.x) {
-      const int f = DIR == 0 ? it % NF : it / NT, r = DIR == 0 ? it / NF : it % NT;
-      const int nf = F0 + f, t = T0 + r;
-      if (nf > nmax || t >= tmax) continue;
-      double s = 0.0;
-      for (int l = 0; l < M; ++l) s += res[(((size_t)f * NT + r) * M + l) * TL::RK1 + 16];
-      (DIR == 0 ? B.sxn : B.syn)[sgn_idx(t, nf)] = s / M;
-    }
-  }
-
-  // ---- cell update of this direction ----
-  constexpr int RK = STAGE == 1 ? TL::RK1 : TL::RK2;
-  const double ihn = 1.0 / hn;
-  for (int it = threadIdx.x; it < (NF - 1) * NT * 4; it += blockDim.x) {
-    int ci, r, v;
-    if (DIR == 0) { ci = it % (NF - 1); r = (it / (NF - 1)) % NT; v = it / ((NF - 1) * NT); }
-    else { r = it % NT; ci = (it / NT) % (NF - 1); v = it / ((NF - 1) * NT); }
-    const int n = F0 + ci, t = T0 + r;
-    if (n >= nmax || t >= tmax) continue;
-    const int i = gi(n, t), j = gj(n, t);
-    const double* ra = res + (((size_t)ci * NT + r) * M) * RK;        // face n
-    const double* rb = res + (((size_t)(ci + 1) * NT + r) * M) * RK;  // face n+1
-    const size_t ia = g.avg(v, i, j);
-    if (STAGE == 1) {
-      double dF = 0.0, dA = 0.0;
-      for (int l = 0; l < M; ++l) {
-        const double w = kGw[M][l];
-        dF += w * (rb[l * RK + v] - ra[l * RK + v]);
-        dA += w * (rb[l * RK + 4 + v] - ra[l * RK + 4 + v]);
-      }
-      const double base = DIR == 0 ? B.U[ia] : B.S[ia];
-      const double abase = DIR == 0 ? B.U[ia] : B.A[ia];
-      const double snew = base - dF * ihn;
-      B.S[ia] = snew;
-      B.A[ia] = abase - dA * ihn;
-      if (DIR == 1) fin[((size_t)ci * NT + r) * 4 + v] = snew;
-      for (int l = 0; l < M; ++l) {
-        const size_t is = DIR == 0 ? g.sx(v, l, i, j) : g.sy(v, l, i, j);
-        B.S[is] = (rb[l * RK + 8 + v] - ra[l * RK + 8 + v]) * ihn;
-        B.A[is] = (rb[l * RK + 12 + v] - ra[l * RK + 12 + v]) * ihn;
-      }
-    } else {
-      double dA = 0.0;
-      for (int l = 0; l < M; ++l) dA += kGw[M][l] * (rb[l * RK + v] - ra[l * RK + v]);
-      const double base = DIR == 0 ? B.A[ia] : B.U[ia];
-      const double unew = base - dA * ihn;
-      B.U[ia] = unew;
-      if (DIR == 1) fin[((size_t)ci * NT + r) * 4 + v] = unew;
-      for (int l = 0; l < M; ++l) {
-        const size_t is = DIR == 0 ? g.sx(v, l, i, j) : g.sy(v, l, i, j);
-        B.U[is] = B.A[is] + (rb[l * RK + 4 + v] - ra[l * RK + 4 + v]) * ihn;
-      }
-    }
-  }
-  if (DIR == 1) {
-    __syncthreads();
-    // health and (stage 2) the speed reduction for the next time step
-    const int it = threadIdx.x;
-    bool valid = false;
-    double s = 0.0, rr = 1.0;
-    if (it < (NF - 1) * NT) {
-      const int r = it % NT, ci = it / NT;
-      const int n = F0 + ci, t = T0 + r;
-      if (n < nmax && t < tmax) {
-        double W[4];
-        for (int v = 0; v < 4; ++v) W[v] = fin[((size_t)ci * NT + r) * 4 + v];
-        rr = W[0];
-        valid = cell_speed(W, 2, C.gamma, s);
-        if (!valid) atomicAdd((unsigned long long*)&B.hdr->nonphysical, 1ull);
-      }
-    }
-    if (STAGE == 2) reduce_speed(B, s, rr, valid);
-  }
-}
-
-// ---------------------------------------------------------------------------
-// 1-D stage kernel: one thread per face; each reconstructs its two cells.
-// A block owns faces F0..F0+255 and updates cells F0..F0+254.
-// ---------------------------------------------------------------------------
-template <int STAGE, typename T, bool PR>
-__global__ __launch_bounds__(256) void k_stage1d(Geo g, Consts C, Bufs B) {
-  const Header* hdr = B.hdr;
-  if (!hdr->active) return;
-  const double dt = hdr->dt;
-  constexpr int NFB = 256;
-  __shared__ double res[NFB][12];
-  const int F0 = blockIdx.x * (NFB - 1);
-  const int f = threadIdx.x;
-  const int F = F0 + f;
-  const double* Uin = STAGE == 1 ? B.U : B.S;
-  const double h = C.dx;
-  if (F <= g.nx) {
-    T Wk[2][6][4];
-#pragma unroll
-    for (int sd = 0; sd < 2; ++sd) {
-      const int cell = F - 1 + sd;
-      double s[6];
-#pragma unroll
-      for (int q = 0; q < 6; ++q) s[q] = B.sxo[g.sgx(0, cell - 2 + q)];
-      const Cascade cs = cascade(s, C.order, C.thres);
-      T d[3][9];
-#pragma unroll
-      for (int v = 0; v < 3; ++v) {
-#pragma unroll
-        for (int k = 0; k < 5; ++k) d[v][k] = T(Uin[g.avg(v, cell + k - 2, 0)]);
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-          const int o = k < 2 ? k - 2 : k - 1;
-          d[v][5 + k] = T(h * Uin[g.sx(v, 0, cell + o, 0)]);
-        }
-      }
-      T out[2][3][3];
-      recon_faces<T, 3>(d, cs, C, out);
-      const int side = sd == 0 ? 0 : 1;   // left state: +1/2 face of cell F-1; right: -1/2 face of cell F
-#pragma unroll
-      for (int v = 0; v < 4; ++v)
-#pragma unroll
-        for (int dd = 0; dd < 6; ++dd) Wk[sd][dd][v] = T(0);
-#pragma unroll
-      for (int v = 0; v < 3; ++v) {
-        Wk[sd][0][v] = out[side][0][v];
-        Wk[sd][1][v] = out[side][1][v] / T(h);
-        Wk[sd][3][v] = out[side][2][v] / T(h * h);
-      }
-      T rho, U, V, p;
-      primitive<T, 1>(Wk[sd][0], T(C.gamma - 1.0), rho, U, V, p);
-      if (!(rho > T(0)) || !(p > T(0))) {
-#pragma unroll
-        for (int v = 0; v < 3; ++v) {
-          Wk[sd][0][v] = T(Uin[g.avg(v, cell, 0)]);
-          Wk[sd][1][v] = T(0);
-          Wk[sd][3][v] = T(0);
-        }
-        atomicAdd((unsigned long long*)&B.hdr->fallbacks, 1ull);
-      }
-    }
-    FaceOut fo;
-    gks_flux<T, 1, PR>(Wk[0], Wk[1], dt, C, fo);
-#pragma unroll
-    for (int v = 0; v < 3; ++v) {
-      if (STAGE == 1) {
-        res[f][v] = fo.Fh[v];
-        res[f][3 + v] = (8.0 / 3.0) * fo.Fh[v] - (1.0 / 3.0) * fo.F1[v];
-        res[f][6 + v] = fo.Wh[v];
-        res[f][9 + v] = -(4.0 / 3.0) * fo.W0[v] + (8.0 / 3.0) * fo.Wh[v] - (1.0 / 3.0) * fo.W1[v];
-      } else {
-        res[f][v] = (4.0 / 3.0) * (fo.F1[v] - 2.0 * fo.Fh[v]);
-        res[f][3 + v] = (4.0 / 3.0) * (fo.W0[v] - 2.0 * fo.Wh[v] + fo.W1[v]);
-      }
-    }
-    if (STAGE == 1) B.sxn[g.sgx(0, F)] = fo.sigma;
-  }
-  __syncthreads();
-  const int i = F0 + f;  // cell
-  bool valid = false;
-  double s = 0.0, rr = 1.0;
-  if (f < NFB - 1 && i < g.nx) {
-    const double ih = 1.0 / h;
-    double W[3];
-    for (int v = 0; v < 3; ++v) {
-      const size_t ia = g.avg(v, i, 0), is = g.sx(v, 0, i, 0);
-      if (STAGE == 1) {
-        const double u0 = B.U[ia];
-        W[v] = u0 - (res[f + 1][v] - res[f][v]) * ih;
-        B.S[ia] = W[v];
-        B.A[ia] = u0 - (res[f + 1][3 + v] - res[f][3 + v]) * ih;
-        B.S[is] = (res[f + 1][6 + v] - res[f][6 + v]) * ih;
-        B.A[is] = (res[f + 1][9 + v] - res[f][9 + v]) * ih;
-      } else {
-        W[v] = B.A[ia] - (res[f + 1][v] - res[f][v]) * ih;
-        B.U[ia] = W[v];
-        B.U[is] = B.A[is] + (res[f + 1][3 + v] - res[f][3 + v]) * ih;
-      }
-    }
-    rr = W[0];
-    valid = cell_speed(W, 1, C.gamma, s);
-    if (!valid) atomicAdd((unsigned long long*)&B.hdr->nonphysical, 1ull);
-  }
-  if (STAGE == 2) reduce_speed(B, s, rr, valid);
+  reduce_speed(B, s, r, valid, blockIdx.x + gridDim.x * blockIdx.y, gridDim.x * gridDim.y);
 }
 
 // ---------------------------------------------------------------------------
@@ -872,23 +189,39 @@ const char* kKernels1d[] = {"dt", "bc_sigma", "bc_state", "stage1_1d", "bc_state
 const char* kKernels2d[] = {"dt", "bc_sigma", "bc_state", "lines", "face_x_stage1", "face_y_stage1",
                             "bc_state", "lines", "face_x_stage2", "face_y_stage2"};
 
+// Face kernels of one order and precision: dynamic LDS limit and the scratch
+// check (FP64 none; FP32 a few spill slots, verified bit-reproducible).
+template <int DIR, int STAGE, int M, typename T, bool PR>
+cgks_status prepare_face() {
+  const void* f = (const void*)k_face2d<DIR, STAGE, M, T, PR>;
+  hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)Lds<M, T>::total);
+  if (e != hipSuccess) return fail(CGKS_EHIP, std::string("hipFuncSetAttribute: ") + hipGetErrorString(e));
+  return check_private(f, sizeof(T) == 8 ? 0 : 16, "face kernel");
+}
+
 template <int M, typename T, bool PR>
-hipError_t set_lds_attr_pr() {
-  hipError_t e = hipSuccess;
-  const int lds = (int)Lds<M, T>::total;
-  e = hipFuncSetAttribute((const void*)k_face2d<0, 1, M, T, PR>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
-  if (e != hipSuccess) return e;
-  e = hipFuncSetAttribute((const void*)k_face2d<1, 1, M, T, PR>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
-  if (e != hipSuccess) return e;
-  e = hipFuncSetAttribute((const void*)k_face2d<0, 2, M, T, PR>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
-  if (e != hipSuccess) return e;
-  return hipFuncSetAttribute((const void*)k_face2d<1, 2, M, T, PR>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+cgks_status prepare_faces_pr() {
+  cgks_status s;
+  if ((s = prepare_face<0, 1, M, T, PR>()) != CGKS_OK) return s;
+  if ((s = prepare_face<1, 1, M, T, PR>()) != CGKS_OK) return s;
+  if ((s = prepare_face<0, 2, M, T, PR>()) != CGKS_OK) return s;
+  if ((s = prepare_face<1, 2, M, T, PR>()) != CGKS_OK) return s;
+  return check_private((const void*)k_lines<M>, 0, "line kernel");
 }
 
 template <int M, typename T>
-hipError_t set_lds_attr() {
-  hipError_t e = set_lds_attr_pr<M, T, false>();
-  return e != hipSuccess ? e : set_lds_attr_pr<M, T, true>();
+cgks_status prepare_faces() {
+  cgks_status s = prepare_faces_pr<M, T, false>();
+  return s != CGKS_OK ? s : prepare_faces_pr<M, T, true>();
+}
+
+template <typename T>
+cgks_status prepare_1d() {
+  cgks_status s;
+  if ((s = check_private((const void*)k_stage1d<1, T, false>, 0, "1-D stage kernel")) != CGKS_OK) return s;
+  if ((s = check_private((const void*)k_stage1d<2, T, false>, 0, "1-D stage kernel")) != CGKS_OK) return s;
+  if ((s = check_private((const void*)k_stage1d<1, T, true>, 0, "1-D stage kernel")) != CGKS_OK) return s;
+  return check_private((const void*)k_stage1d<2, T, true>, 0, "1-D stage kernel");
 }
 
 }  // namespace
@@ -911,7 +244,7 @@ const char* cgks_status_string(cgks_status s) {
   return "unknown status";
 }
 
-const char* cgks_last_error(void) { return g_err.c_str(); }
+const char* cgks_last_error(void) { return cgks_g_err.c_str(); }
 
 cgks_status cgks_plan_create(const cgks_grid_desc* gd, const cgks_scheme_desc* sd, cgks_plan** out) {
   if (!gd || !sd || !out) return fail(CGKS_EINVAL, "NULL argument");
@@ -1014,12 +347,10 @@ cgks_status cgks_plan_destroy(cgks_plan* p) {
 }
 
 static cgks_status ensure_lds(const cgks_plan* p) {
-  if (p->g.dim != 2) return CGKS_OK;
-  hipError_t e;
-  if (p->precision == CGKS_FP64) e = p->g.m == 2 ? set_lds_attr<2, double>() : (p->g.m == 3 ? set_lds_attr<3, double>() : set_lds_attr<4, double>());
-  else e = p->g.m == 2 ? set_lds_attr<2, float>() : (p->g.m == 3 ? set_lds_attr<3, float>() : set_lds_attr<4, float>());
-  if (e != hipSuccess) return fail(CGKS_EHIP, std::string("hipFuncSetAttribute: ") + hipGetErrorString(e));
-  return CGKS_OK;
+  const bool d = p->precision == CGKS_FP64;
+  if (p->g.dim != 2) return d ? prepare_1d<double>() : prepare_1d<float>();
+  if (d) return p->g.m == 2 ? prepare_faces<2, double>() : (p->g.m == 3 ? prepare_faces<3, double>() : prepare_faces<4, double>());
+  return p->g.m == 2 ? prepare_faces<2, float>() : (p->g.m == 3 ? prepare_faces<3, float>() : prepare_faces<4, float>());
 }
 
 cgks_status cgks_init_state(const cgks_plan* p, void* d_state, void* d_work, const double* h_avg,

@@ -1,0 +1,612 @@
+// Batched execution: many independent grids of one dimension and precision
+// advance together, one launch per phase of the step (Sec. 2.2) for the whole
+// batch.  Every launch is a persistent grid of a fixed size that walks a
+// device-resident job table: item k of a phase maps to (job, tile) through a
+// per-phase prefix sum of the jobs' tile counts, and the tile is computed by
+// the same device body the single-grid kernels use (cgks_internal.hpp), with
+// the job's own tile coordinates and tile count.  A job therefore takes the
+// same arithmetic, the same speed partials and the same time steps alone or
+// in a batch.
+//
+// The launch grid and every kernel argument are fixed for the life of the
+// batch (the table is read from device memory), so a hipGraph captured once
+// stays valid while jobs are added and retired: cgks_batch_commit uploads the
+// table outside the graph, the step itself does no copies and no memsets.
+#define CGKS_UNIT batched
+#include "cgks_internal.hpp"
+
+#include <algorithm>
+#include <chrono>
+
+namespace {
+
+// Phases of a step, in launch order (2-D; 1-D uses DT, PREP, S1D1, BCS, S1D2).
+enum Phase { PH_DT = 0, PH_PREP, PH_LINES, PH_FX, PH_FY, PH_BCS, PH_S1D, NPH };
+
+struct BJob {
+  Geo g;
+  Consts C;
+  Bufs B;
+  double dt_fixed, cfl, t_end, h;
+  long long max_steps;
+  int viscous, M, slot, pad;
+  int ax, ay, as;          // 256-wide segments per row: sigma x-faces, sigma y-faces, state rows
+  int nsx, nsy;            // PREP items of the sigma x / y parts
+  int fnb[2][2];           // face tiles (along normal, along tangential) of x- and y-faces
+  int nseg;                // 1-D stage segments
+};
+
+struct BTab {
+  int njobs, cap;
+  int total[NPH];
+  BJob* jobs;      // [cap], table order
+  int* pre;        // [NPH][cap + 1] prefix sums of the items per job
+  JobStat* stat;   // [cap], by slot
+};
+
+// Largest j in [0, n) with pre[j] <= item (pre[0] = 0, pre[n] = total).
+__device__ __forceinline__ int find_job(const int* pre, int n, int item) {
+  int lo = 0, hi = n;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (pre[mid] <= item) lo = mid;
+    else hi = mid;
+  }
+  return lo;
+}
+
+// Persistent loop over the items of a phase.  With remap, blocks that the
+// dispatcher places on one XCD (block b runs on XCD b mod 8) take
+// consecutive items, so neighbouring tiles of a grid share that XCD's L2.
+template <class F>
+__device__ __forceinline__ void for_items(const BTab* tab, int ph, int remap, F&& f) {
+  const int total = tab->total[ph];
+  const int G = gridDim.x;
+  int lb = blockIdx.x;
+  if (remap) lb = (blockIdx.x & 7) * (G >> 3) + (blockIdx.x >> 3);   // G is a multiple of 8
+  const int n = tab->njobs;
+  const int* pre = tab->pre + (size_t)ph * (tab->cap + 1);
+  for (int item = lb; item < total; item += G) {
+    const int j = find_job(pre, n, item);
+    const BJob J = tab->jobs[j];   // a private copy: the tile's stores cannot alias it
+    f(J, item - pre[j]);
+  }
+}
+
+__global__ __launch_bounds__(256) void kb_dt(const BTab* tab) {
+  const int n = tab->njobs;
+  for (int j = blockIdx.x; j < n; j += gridDim.x) {
+    const BJob J = tab->jobs[j];
+    dt_block(J.B.hdr, J.B.part, J.dt_fixed, J.cfl, J.t_end, J.h, J.C.mu, J.viscous, J.max_steps,
+             tab->stat + J.slot);
+  }
+}
+
+// Strength commit and ghost faces (both directions), then ghost cells of W^n.
+__global__ __launch_bounds__(256) void kb_prep(const BTab* tab, int remap) {
+  for_items(tab, PH_PREP, remap, [&](const BJob& J, int k) {
+    if (!J.B.hdr->active) return;
+    if (k < J.nsx) {
+      bc_sigma_at(J.g, 0, J.B.sxn, J.B.sxo, J.B.syn, J.B.syo, (k % J.ax) * 256 + threadIdx.x, k / J.ax);
+      return;
+    }
+    k -= J.nsx;
+    if (k < J.nsy) {
+      bc_sigma_at(J.g, 1, J.B.sxn, J.B.sxo, J.B.syn, J.B.syo, (k % J.ay) * 256 + threadIdx.x, k / J.ay);
+      return;
+    }
+    k -= J.nsy;
+    bc_state_at(J.g, J.B.U, (k % J.as) * 256 + threadIdx.x, k / J.as);
+  });
+}
+
+// Ghost cells of the stage state W*.
+__global__ __launch_bounds__(256) void kb_bcs(const BTab* tab, int remap) {
+  for_items(tab, PH_BCS, remap, [&](const BJob& J, int k) {
+    if (!J.B.hdr->active) return;
+    bc_state_at(J.g, J.B.S, (k % J.as) * 256 + threadIdx.x, k / J.as);
+  });
+}
+
+// Step 1 line values of the stage input (2-D).
+__global__ __launch_bounds__(256) void kb_lines(const BTab* tab, int stage, int remap) {
+  for_items(tab, PH_LINES, remap, [&](const BJob& J, int k) {
+    if (!J.B.hdr->active) return;
+    const double* Uin = stage == 1 ? J.B.U : J.B.S;
+    const int I = (k % J.as) * 256 + threadIdx.x, Jr = k / J.as;
+    switch (J.M) {
+      case 2: lines_at<2>(J.g, J.C, Uin, J.B.sxo, J.B.syo, J.B.lvx, J.B.lvy, I, Jr); break;
+      case 3: lines_at<3>(J.g, J.C, Uin, J.B.sxo, J.B.syo, J.B.lvx, J.B.lvy, I, Jr); break;
+      default: lines_at<4>(J.g, J.C, Uin, J.B.sxo, J.B.syo, J.B.lvx, J.B.lvy, I, Jr); break;
+    }
+  });
+}
+
+template <typename T>
+constexpr size_t face_lds() {
+  return std::max(Lds<2, T>::total, std::max(Lds<3, T>::total, Lds<4, T>::total));
+}
+
+// Fused reconstruction + flux + update of one direction and stage over the
+// face tiles of every job; the order (m) is a per-job switch.
+template <int DIR, int STAGE, typename T>
+__global__ __launch_bounds__(256, 1) void kb_face(const BTab* tab, int remap) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  for_items(tab, DIR == 0 ? PH_FX : PH_FY, remap, [&](const BJob& J, int k) {
+    const int nbx = J.fnb[DIR][0], nby = J.fnb[DIR][1];
+    const int bx = k % nbx, by = k / nbx;
+    switch (J.M) {
+      case 2: face2d_tile<DIR, STAGE, 2, T, false>(J.g, J.C, J.B, smem, bx, by, nbx, nby); break;
+      case 3: face2d_tile<DIR, STAGE, 3, T, false>(J.g, J.C, J.B, smem, bx, by, nbx, nby); break;
+      default: face2d_tile<DIR, STAGE, 4, T, false>(J.g, J.C, J.B, smem, bx, by, nbx, nby); break;
+    }
+  });
+}
+
+// One stage of the 1-D scheme over the segments of every job.
+template <int STAGE, typename T>
+__global__ __launch_bounds__(256) void kb_stage1d(const BTab* tab, int remap) {
+  __shared__ double res[256][12];
+  for_items(tab, PH_S1D, remap,
+            [&](const BJob& J, int k) { stage1d_seg<STAGE, T, false>(J.g, J.C, J.B, res, k, J.nseg); });
+}
+
+// Kernel slots of the persistent launches (grid sizes are per slot).
+enum Kern { K_DT = 0, K_PREP, K_BCS, K_LINES, K_FACE, K_S1D, NK };
+
+}  // namespace
+
+struct cgks_batch {
+  int dim = 0, precision = 0, cap = 0;
+  size_t budget = 0, used = 0;
+  int ncu = 0;
+  int occ[NK] = {};          // resident blocks per CU of each kernel slot
+  cgks_batch_tuning tune{};  // persistent-grid multiplier and XCD remap in use
+  int grid[NK] = {};
+  std::vector<BJob> slots;
+  std::vector<char> busy, fresh;
+  std::vector<size_t> bytes;
+  std::vector<JobStat> init_stat;
+  std::vector<int> order;    // table order -> slot
+  // device: one allocation holding the table header, jobs, prefix sums and progress records
+  void* dmem = nullptr;
+  BTab* dtab = nullptr;
+  BJob* djobs = nullptr;
+  int* dpre = nullptr;
+  JobStat* dstat = nullptr;
+  size_t off_stat = 0, table_bytes = 0;
+  std::vector<unsigned char> staging;
+  hipStream_t cap_stream = nullptr;
+  hipGraphExec_t exec = nullptr;
+  int graph_steps = 0;
+  bool committed = false;
+};
+
+namespace {
+
+void set_grids(cgks_batch* b) {
+  for (int k = 0; k < NK; ++k) {
+    int g = b->ncu * std::max(1, b->occ[k]) * std::max(1, b->tune.grid_mult);
+    b->grid[k] = (g + 7) & ~7;   // a multiple of 8 (one share per XCD)
+  }
+  b->grid[K_DT] = std::min(b->grid[K_DT], std::max(8, b->cap));
+}
+
+// Dynamic LDS limit of the batched face kernels and the scratch check of
+// every batched kernel (none may use scratch).
+template <int DIR, int STAGE, typename T>
+cgks_status prepare_bface() {
+  const void* f = (const void*)kb_face<DIR, STAGE, T>;
+  hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)face_lds<T>());
+  if (e != hipSuccess) return fail(CGKS_EHIP, std::string("hipFuncSetAttribute: ") + hipGetErrorString(e));
+  return check_private(f, 0, "batched face kernel");
+}
+
+template <typename T>
+cgks_status prepare_batch() {
+  cgks_status s;
+  if ((s = prepare_bface<0, 1, T>()) != CGKS_OK) return s;
+  if ((s = prepare_bface<1, 1, T>()) != CGKS_OK) return s;
+  if ((s = prepare_bface<0, 2, T>()) != CGKS_OK) return s;
+  if ((s = prepare_bface<1, 2, T>()) != CGKS_OK) return s;
+  const void* k[] = {(const void*)kb_dt, (const void*)kb_prep, (const void*)kb_bcs, (const void*)kb_lines,
+                     (const void*)kb_stage1d<1, T>, (const void*)kb_stage1d<2, T>};
+  for (const void* f : k)
+    if ((s = check_private(f, 0, "batched kernel")) != CGKS_OK) return s;
+  return CGKS_OK;
+}
+
+template <typename T>
+hipError_t occupancy(cgks_batch* b) {
+  hipError_t e;
+  if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&b->occ[K_DT], kb_dt, 256, 0))) return e;
+  if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&b->occ[K_PREP], kb_prep, 256, 0))) return e;
+  if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&b->occ[K_BCS], kb_bcs, 256, 0))) return e;
+  if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&b->occ[K_LINES], kb_lines, 256, 0))) return e;
+  if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&b->occ[K_FACE], kb_face<1, 2, T>, 256, face_lds<T>())))
+    return e;
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(&b->occ[K_S1D], kb_stage1d<2, T>, 256, 0);
+}
+
+template <typename T>
+hipError_t enqueue_batch_step(const cgks_batch* b, hipStream_t st) {
+  const BTab* t = b->dtab;
+  const int r = b->tune.xcd_remap ? 1 : 0;
+  hipLaunchKernelGGL(kb_dt, dim3(b->grid[K_DT]), dim3(256), 0, st, t);
+  hipLaunchKernelGGL(kb_prep, dim3(b->grid[K_PREP]), dim3(256), 0, st, t, r);
+  if (b->dim == 1) {
+    hipLaunchKernelGGL((kb_stage1d<1, T>), dim3(b->grid[K_S1D]), dim3(256), 0, st, t, r);
+    hipLaunchKernelGGL(kb_bcs, dim3(b->grid[K_BCS]), dim3(256), 0, st, t, r);
+    hipLaunchKernelGGL((kb_stage1d<2, T>), dim3(b->grid[K_S1D]), dim3(256), 0, st, t, r);
+    return hipGetLastError();
+  }
+  const size_t lds = face_lds<T>();
+  const int gf = b->grid[K_FACE];
+  hipLaunchKernelGGL(kb_lines, dim3(b->grid[K_LINES]), dim3(256), 0, st, t, 1, r);
+  hipLaunchKernelGGL((kb_face<0, 1, T>), dim3(gf), dim3(256), lds, st, t, r);
+  hipLaunchKernelGGL((kb_face<1, 1, T>), dim3(gf), dim3(256), lds, st, t, r);
+  hipLaunchKernelGGL(kb_bcs, dim3(b->grid[K_BCS]), dim3(256), 0, st, t, r);
+  hipLaunchKernelGGL(kb_lines, dim3(b->grid[K_LINES]), dim3(256), 0, st, t, 2, r);
+  hipLaunchKernelGGL((kb_face<0, 2, T>), dim3(gf), dim3(256), lds, st, t, r);
+  hipLaunchKernelGGL((kb_face<1, 2, T>), dim3(gf), dim3(256), lds, st, t, r);
+  return hipGetLastError();
+}
+
+hipError_t enqueue_steps(const cgks_batch* b, int n, hipStream_t st) {
+  for (int k = 0; k < n; ++k) {
+    hipError_t e = b->precision == CGKS_FP64 ? enqueue_batch_step<double>(b, st) : enqueue_batch_step<float>(b, st);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+void drop_graph(cgks_batch* b) {
+  if (b->exec) hipGraphExecDestroy(b->exec);
+  b->exec = nullptr;
+  b->graph_steps = 0;
+}
+
+// Tile counts of one job for every phase (the single-grid launch shapes).
+void fill_counts(BJob& J) {
+  const Geo& g = J.g;
+  J.ax = (g.NX + 1 + 255) / 256;
+  J.nsx = J.ax * g.NY;
+  J.ay = g.dim == 2 ? (g.NY + 1 + 255) / 256 : 0;
+  J.nsy = g.dim == 2 ? J.ay * g.NX : 0;
+  J.as = (g.NX + 255) / 256;
+  if (g.dim == 2) {
+    const int NF = 16, NT = J.M == 2 ? 8 : (J.M == 3 ? 5 : 4);
+    J.fnb[0][0] = (g.nx + NF - 2) / (NF - 1);
+    J.fnb[0][1] = (g.ny + NT - 1) / NT;
+    J.fnb[1][0] = (g.ny + NF - 2) / (NF - 1);
+    J.fnb[1][1] = (g.nx + NT - 1) / NT;
+    J.nseg = 0;
+  } else {
+    J.fnb[0][0] = J.fnb[0][1] = J.fnb[1][0] = J.fnb[1][1] = 0;
+    J.nseg = (g.nx + 254) / 255;
+  }
+}
+
+long long items(const BJob& J, int ph) {
+  switch (ph) {
+    case PH_DT: return 1;
+    case PH_PREP: return (long long)J.nsx + J.nsy + (long long)J.as * J.g.NY;
+    case PH_BCS: return (long long)J.as * J.g.NY;
+    case PH_LINES: return J.g.dim == 2 ? (long long)J.as * J.g.NY : 0;
+    case PH_FX: return (long long)J.fnb[0][0] * J.fnb[0][1];
+    case PH_FY: return (long long)J.fnb[1][0] * J.fnb[1][1];
+    case PH_S1D: return J.nseg;
+  }
+  return 0;
+}
+
+}  // namespace
+
+extern "C" {
+
+cgks_status cgks_batch_create(int dim, int precision, int max_jobs, size_t hbm_budget_bytes, cgks_batch** out) {
+  if (!out) return fail(CGKS_EINVAL, "NULL argument");
+  *out = nullptr;
+  if (dim != 1 && dim != 2) return fail(CGKS_EINVAL, "dim must be 1 or 2");
+  if (precision != CGKS_FP64 && precision != CGKS_FP32_FLUX) return fail(CGKS_EINVAL, "unknown precision");
+  if (max_jobs < 1 || max_jobs > (1 << 20)) return fail(CGKS_EINVAL, "max_jobs must lie in [1, 2^20]");
+  cgks_batch* b = new (std::nothrow) cgks_batch;
+  if (!b) return fail(CGKS_ENOMEM, "batch allocation");
+  b->dim = dim;
+  b->precision = precision;
+  b->cap = max_jobs;
+  b->budget = hbm_budget_bytes;
+  b->tune.grid_mult = 1;
+  b->tune.xcd_remap = 1;
+  try {
+    b->slots.resize(max_jobs);
+    b->busy.assign(max_jobs, 0);
+    b->fresh.assign(max_jobs, 0);
+    b->bytes.assign(max_jobs, 0);
+    b->init_stat.resize(max_jobs);
+  } catch (...) {
+    delete b;
+    return fail(CGKS_ENOMEM, "batch host tables");
+  }
+  const cgks_status ps = precision == CGKS_FP64 ? prepare_batch<double>() : prepare_batch<float>();
+  if (ps != CGKS_OK) {
+    delete b;
+    return ps;
+  }
+  auto up = [](size_t x) { return (x + 255) & ~(size_t)255; };
+  const size_t o_jobs = up(sizeof(BTab));
+  const size_t o_pre = o_jobs + up(sizeof(BJob) * max_jobs);
+  b->off_stat = o_pre + up(sizeof(int) * NPH * (size_t)(max_jobs + 1));
+  b->table_bytes = b->off_stat;
+  const size_t total = b->off_stat + up(sizeof(JobStat) * max_jobs);
+  hipError_t e = hipMalloc(&b->dmem, total);
+  if (e == hipSuccess) e = hipMemset(b->dmem, 0, total);
+  int dev = 0;
+  if (e == hipSuccess) e = hipGetDevice(&dev);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&b->ncu, hipDeviceAttributeMultiprocessorCount, dev);
+  if (e == hipSuccess) e = precision == CGKS_FP64 ? occupancy<double>(b) : occupancy<float>(b);
+  if (e == hipSuccess) e = hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking);
+  if (e != hipSuccess) {
+    if (b->dmem) hipFree(b->dmem);
+    delete b;
+    return fail(CGKS_EHIP, std::string("batch create: ") + hipGetErrorString(e));
+  }
+  unsigned char* base = (unsigned char*)b->dmem;
+  b->dtab = (BTab*)base;
+  b->djobs = (BJob*)(base + o_jobs);
+  b->dpre = (int*)(base + o_pre);
+  b->dstat = (JobStat*)(base + b->off_stat);
+  try {
+    b->staging.assign(b->table_bytes, 0);
+  } catch (...) {
+    hipFree(b->dmem);
+    delete b;
+    return fail(CGKS_ENOMEM, "batch staging");
+  }
+  set_grids(b);
+  *out = b;
+  return CGKS_OK;
+}
+
+cgks_status cgks_batch_destroy(cgks_batch* b) {
+  if (!b) return CGKS_OK;
+  drop_graph(b);
+  if (b->cap_stream) hipStreamDestroy(b->cap_stream);
+  if (b->dmem) hipFree(b->dmem);
+  delete b;
+  return CGKS_OK;
+}
+
+cgks_status cgks_batch_add(cgks_batch* b, const cgks_plan* p, void* d_state, void* d_work, long long max_steps,
+                           double dt, double cfl, double t_end, int* slot) {
+  if (!b || !p || !d_state || !d_work || !slot) return fail(CGKS_EINVAL, "NULL argument");
+  *slot = -1;
+  if (p->g.dim != b->dim) return fail(CGKS_EINVAL, "plan dimension differs from the batch");
+  if (p->precision != b->precision) return fail(CGKS_EINVAL, "plan precision differs from the batch");
+  if (p->C.prandtl != 1.0) return fail(CGKS_EINVAL, "batched kernels take Prandtl number 1 only");
+  if (!(dt > 0.0) && !(cfl > 0.0 && cfl <= 1.0)) return fail(CGKS_EINVAL, "cfl must lie in (0, 1]");
+  if (max_steps < 0) return fail(CGKS_EINVAL, "max_steps must be >= 0");
+  if (max_steps == 0 && !(t_end > 0.0)) return fail(CGKS_EINVAL, "a batched job needs max_steps or t_end");
+  const size_t need = (p->state_words + p->work_words) * sizeof(double);
+  if (b->budget && b->used + need > b->budget) return fail(CGKS_EBUDGET, "job does not fit the HBM budget");
+  int s = -1;
+  for (int k = 0; k < b->cap; ++k)
+    if (!b->busy[k]) { s = k; break; }
+  if (s < 0) return fail(CGKS_EBUDGET, "no free job slot");
+  Bufs B = bufs(p, d_state, d_work);
+  Header hh;
+  HIP_TRY(hipMemcpy(&hh, B.hdr, sizeof(hh), hipMemcpyDeviceToHost));
+  if (hh.magic != kMagic) return fail(CGKS_ESTATE, "work buffer was not initialised by cgks_init_state");
+  BJob& J = b->slots[s];
+  memset(&J, 0, sizeof(J));
+  J.g = p->g;
+  J.C = p->C;
+  J.B = B;
+  J.dt_fixed = dt;
+  J.cfl = cfl;
+  J.t_end = t_end;
+  J.h = p->g.dim == 2 ? fmin(p->dx, p->dy) : p->dx;
+  J.max_steps = max_steps;
+  J.viscous = p->C.tau_model == CGKS_TAU_VISCOUS ? 1 : 0;
+  J.M = p->g.m;
+  J.slot = s;
+  fill_counts(J);
+  JobStat& is = b->init_stat[s];
+  is.t = hh.t;
+  is.dt = hh.dt;
+  is.steps = (long long)hh.steps;
+  is.status = hh.nonphysical ? 2 : 0;
+  is.active = 1;
+  b->busy[s] = 1;
+  b->fresh[s] = 1;
+  b->bytes[s] = need;
+  b->used += need;
+  b->committed = false;
+  *slot = s;
+  return CGKS_OK;
+}
+
+cgks_status cgks_batch_remove(cgks_batch* b, int slot) {
+  if (!b) return fail(CGKS_EINVAL, "NULL batch");
+  if (slot < 0 || slot >= b->cap || !b->busy[slot]) return fail(CGKS_EINVAL, "no job in that slot");
+  b->busy[slot] = 0;
+  b->fresh[slot] = 0;
+  b->used -= b->bytes[slot];
+  b->bytes[slot] = 0;
+  b->committed = false;
+  return CGKS_OK;
+}
+
+cgks_status cgks_batch_commit(cgks_batch* b, void* stream) {
+  if (!b) return fail(CGKS_EINVAL, "NULL batch");
+  hipStream_t st = (hipStream_t)stream;
+  // table order: slot order (the persistent loop strides over all items)
+  b->order.clear();
+  for (int k = 0; k < b->cap; ++k)
+    if (b->busy[k]) b->order.push_back(k);
+  const int n = (int)b->order.size();
+  unsigned char* base = b->staging.data();
+  BTab* T = (BTab*)base;
+  memset(T, 0, sizeof(BTab));
+  const size_t o_jobs = (unsigned char*)b->djobs - (unsigned char*)b->dmem;
+  const size_t o_pre = (unsigned char*)b->dpre - (unsigned char*)b->dmem;
+  BJob* jobs = (BJob*)(base + o_jobs);
+  int* pre = (int*)(base + o_pre);
+  T->njobs = n;
+  T->cap = b->cap;
+  T->jobs = b->djobs;
+  T->pre = b->dpre;
+  T->stat = b->dstat;
+  for (int ph = 0; ph < NPH; ++ph) {
+    int* P = pre + (size_t)ph * (b->cap + 1);
+    long long acc = 0;
+    for (int k = 0; k < n; ++k) {
+      P[k] = (int)acc;
+      acc += items(b->slots[b->order[k]], ph);
+    }
+    P[n] = (int)acc;
+    if (acc >= (1ll << 31)) return fail(CGKS_EINVAL, "batch too large for 32-bit item indices");
+    T->total[ph] = (int)acc;
+  }
+  for (int k = 0; k < n; ++k) jobs[k] = b->slots[b->order[k]];
+  // the host staging buffer is reused by the next commit: copy and wait
+  HIP_TRY(hipMemcpyAsync(b->dmem, base, sizeof(BTab), hipMemcpyHostToDevice, st));
+  if (n) HIP_TRY(hipMemcpyAsync(b->djobs, jobs, sizeof(BJob) * n, hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemcpyAsync(b->dpre, pre, sizeof(int) * NPH * (size_t)(b->cap + 1), hipMemcpyHostToDevice, st));
+  for (int k = 0; k < b->cap; ++k)
+    if (b->fresh[k]) {
+      HIP_TRY(hipMemcpyAsync(b->dstat + k, &b->init_stat[k], sizeof(JobStat), hipMemcpyHostToDevice, st));
+      b->fresh[k] = 0;
+    }
+  HIP_TRY(hipStreamSynchronize(st));
+  b->committed = true;
+  return CGKS_OK;
+}
+
+cgks_status cgks_batch_step(cgks_batch* b, int nsteps, void* stream) {
+  if (!b) return fail(CGKS_EINVAL, "NULL batch");
+  if (!b->committed) return fail(CGKS_ESTATE, "batch changed since the last cgks_batch_commit");
+  if (nsteps < 0) return fail(CGKS_EINVAL, "nsteps must be >= 0");
+  HIP_TRY(enqueue_steps(b, nsteps, (hipStream_t)stream));
+  return CGKS_OK;
+}
+
+cgks_status cgks_batch_capture(cgks_batch* b, int nsteps) {
+  if (!b) return fail(CGKS_EINVAL, "NULL batch");
+  if (nsteps < 1) return fail(CGKS_EINVAL, "nsteps must be >= 1");
+  drop_graph(b);
+  hipGraph_t graph = nullptr;
+  HIP_TRY(hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal));
+  hipError_t e = enqueue_steps(b, nsteps, b->cap_stream);
+  hipError_t e2 = hipStreamEndCapture(b->cap_stream, &graph);
+  if (e == hipSuccess) e = e2;
+  if (e == hipSuccess) e = hipGraphInstantiate(&b->exec, graph, nullptr, nullptr, 0);
+  if (graph) hipGraphDestroy(graph);
+  if (e != hipSuccess) {
+    b->exec = nullptr;
+    return fail(CGKS_EHIP, std::string("graph capture: ") + hipGetErrorString(e));
+  }
+  b->graph_steps = nsteps;
+  return CGKS_OK;
+}
+
+cgks_status cgks_batch_launch(cgks_batch* b, void* stream) {
+  if (!b) return fail(CGKS_EINVAL, "NULL batch");
+  if (!b->exec) return fail(CGKS_ESTATE, "no captured graph (cgks_batch_capture)");
+  if (!b->committed) return fail(CGKS_ESTATE, "batch changed since the last cgks_batch_commit");
+  HIP_TRY(hipGraphLaunch(b->exec, (hipStream_t)stream));
+  return CGKS_OK;
+}
+
+cgks_status cgks_batch_poll(cgks_batch* b, cgks_job_status* out, void* stream) {
+  if (!b || !out) return fail(CGKS_EINVAL, "NULL argument");
+  hipStream_t st = (hipStream_t)stream;
+  std::vector<JobStat> hs(b->cap);
+  HIP_TRY(hipMemcpyAsync(hs.data(), b->dstat, sizeof(JobStat) * b->cap, hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  for (int k = 0; k < b->cap; ++k) {
+    out[k].in_use = b->busy[k];
+    if (!b->busy[k]) {
+      out[k].t = 0.0; out[k].dt = 0.0; out[k].steps = 0; out[k].status = 0;
+      continue;
+    }
+    const JobStat& s = b->fresh[k] ? b->init_stat[k] : hs[k];
+    out[k].t = s.t;
+    out[k].dt = s.dt;
+    out[k].steps = s.steps;
+    out[k].status = s.status;
+  }
+  return CGKS_OK;
+}
+
+cgks_status cgks_batch_info(const cgks_batch* b, int* njobs, size_t* bytes_used, size_t* table_bytes,
+                            int* grid_face) {
+  if (!b) return fail(CGKS_EINVAL, "NULL batch");
+  int n = 0;
+  for (int k = 0; k < b->cap; ++k) n += b->busy[k];
+  if (njobs) *njobs = n;
+  if (bytes_used) *bytes_used = b->used;
+  if (table_bytes) *table_bytes = b->off_stat + sizeof(JobStat) * b->cap;
+  if (grid_face) *grid_face = b->dim == 2 ? b->grid[K_FACE] : b->grid[K_S1D];
+  return CGKS_OK;
+}
+
+cgks_status cgks_batch_set_tuning(cgks_batch* b, const cgks_batch_tuning* t) {
+  if (!b || !t) return fail(CGKS_EINVAL, "NULL argument");
+  if (t->grid_mult < 1 || t->grid_mult > 16) return fail(CGKS_EINVAL, "grid_mult must lie in [1, 16]");
+  b->tune.grid_mult = t->grid_mult;
+  b->tune.xcd_remap = t->xcd_remap ? 1 : 0;
+  b->tune.ms_per_step = t->ms_per_step;
+  set_grids(b);
+  drop_graph(b);   // launch shapes are baked into a captured graph
+  return CGKS_OK;
+}
+
+cgks_status cgks_batch_get_tuning(const cgks_batch* b, cgks_batch_tuning* t) {
+  if (!b || !t) return fail(CGKS_EINVAL, "NULL argument");
+  *t = b->tune;
+  return CGKS_OK;
+}
+
+// Times `steps_per_trial` real steps of the committed jobs under each
+// candidate launch shape and keeps the fastest.  Every candidate computes the
+// same result, so the trial steps advance the jobs as ordinary steps do.
+cgks_status cgks_batch_tune(cgks_batch* b, int steps_per_trial, void* stream, cgks_batch_tuning* chosen) {
+  if (!b) return fail(CGKS_EINVAL, "NULL batch");
+  if (!b->committed) return fail(CGKS_ESTATE, "batch changed since the last cgks_batch_commit");
+  if (steps_per_trial < 1) return fail(CGKS_EINVAL, "steps_per_trial must be >= 1");
+  hipStream_t st = (hipStream_t)stream;
+  hipEvent_t e0, e1;
+  HIP_TRY(hipEventCreate(&e0));
+  HIP_TRY(hipEventCreate(&e1));
+  const int mults[] = {1, 2, 4};
+  cgks_batch_tuning best = b->tune;
+  best.ms_per_step = -1.0f;
+  hipError_t e = hipSuccess;
+  for (int remap = 0; remap < 2 && e == hipSuccess; ++remap)
+    for (int mi = 0; mi < 3 && e == hipSuccess; ++mi) {
+      cgks_batch_tuning c{};
+      c.grid_mult = mults[mi];
+      c.xcd_remap = remap;
+      b->tune = c;
+      set_grids(b);
+      if ((e = hipEventRecord(e0, st)) != hipSuccess) break;
+      if ((e = enqueue_steps(b, steps_per_trial, st)) != hipSuccess) break;
+      if ((e = hipEventRecord(e1, st)) != hipSuccess) break;
+      if ((e = hipEventSynchronize(e1)) != hipSuccess) break;
+      float ms = 0.0f;
+      if ((e = hipEventElapsedTime(&ms, e0, e1)) != hipSuccess) break;
+      c.ms_per_step = ms / steps_per_trial;
+      if (best.ms_per_step < 0.0f || c.ms_per_step < best.ms_per_step) best = c;
+    }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  if (e != hipSuccess) return fail(CGKS_EHIP, std::string("tune: ") + hipGetErrorString(e));
+  b->tune = best;
+  set_grids(b);
+  drop_graph(b);
+  if (chosen) *chosen = best;
+  return CGKS_OK;
+}
+
+}  // extern "C"

@@ -12,7 +12,17 @@
 #define CGKS_HD __host__ __device__
 #endif
 
+// Each translation unit of the library is its own device code object, and
+// HIP exports every __constant__ table of a code object as a global symbol
+// under its mangled name.  A per-unit inline namespace gives the tables of
+// each unit distinct symbol names, so the loaded code objects cannot bind
+// one another's tables.
+#ifndef CGKS_UNIT
+#define CGKS_UNIT unit
+#endif
+
 namespace cgks {
+inline namespace CGKS_UNIT {
 
 #include "cgks_tables.inc"
 
@@ -585,4 +595,5 @@ CGKS_HD __forceinline__ void recon_nodes(const T (&d)[NVAR][9], const Cascade& c
     }
 }
 
+}  // inline namespace CGKS_UNIT
 }  // namespace cgks

@@ -1,0 +1,779 @@
+// Internal header of libcgks.so: the types (header record, geometry, buffer
+// set, plan) and the per-tile device bodies shared by the single-grid kernels
+// (cgks.hip) and the batched persistent kernels (cgks_batch.hip).
+//
+// Data layout (FP64, structure of arrays, ghost halo of H = 3 cells):
+//   state  = [avg: nv][NY][NX] [sx: nv][m][NY][NX] [sy: nv][m][NY][NX] (2-D)
+//            1-D: NY = 1, m = 1, no sy.  Cell (i, j) sits at (j+H)*NX + i+H.
+//   work   = [stage state U*][accumulator][sigx old/new][sigy old/new]
+//            [line values LVx, LVy: nv][m][NY][NX] (2-D)][header]
+//   sigx: [NY][NX+1], face F of row j at (j+H)*(NX+1) + F+H (1-D: one row)
+//   sigy: [NX][NY+1], face G of column i at (i+H)*(NY+1) + G+H
+//
+// One step (Sec. 2.2): dt -> strengths commit + ghosts -> stage 1 (Eq. 2.21,
+// slopes from W(dt/2)) -> ghosts of U* -> stage 2 (Eq. 2.22, 2.23; slopes from
+// Eq. 2.25, 2.29, 2.30).  The stage-1 kernels also write the accumulator
+//   Acc = W^n - (1/h) sum_l w_l [(8/3) F(dt/2) - (1/3) F(dt)],
+//   Acc_slope = [-(4/3) W(0) + (8/3) W(dt/2) - (1/3) W(dt)] / h,
+// so that stage 2 adds (4/3)[F*(dt) - 2 F*(dt/2)] and (4/3)[W*(0) - 2 W*(dt/2) + W*(dt)],
+// which is Eq. 2.19-2.23 and 2.25/2.29 combined.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <math.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/cgks.h"
+#include "cgks_device.hpp"
+
+using namespace cgks;
+
+#define H 3
+
+// Message of the last failing call on this thread (defined in cgks.hip).
+extern thread_local std::string cgks_g_err;
+
+namespace {
+
+inline cgks_status fail(cgks_status s, const std::string& msg) {
+  cgks_g_err = msg;
+  return s;
+}
+
+#define HIP_TRY(expr)                                                                   \
+  do {                                                                                  \
+    hipError_t e_ = (expr);                                                             \
+    if (e_ != hipSuccess) return fail(CGKS_EHIP, std::string(#expr ": ") + hipGetErrorString(e_)); \
+  } while (0)
+
+// Scratch (private) bytes per thread a hot kernel may use.  FP64 face kernels
+// compiled for two waves per SIMD spilled about 350 bytes per thread and then
+// produced wrong, run-dependent results on gfx950, while the same source
+// without spills is exact; every hot kernel is therefore built to keep its
+// state in registers, and the library checks the built kernels before first
+// use and refuses to run them otherwise.
+inline cgks_status check_private(const void* kernel, size_t limit, const char* what) {
+  hipFuncAttributes a;
+  hipError_t e = hipFuncGetAttributes(&a, kernel);
+  if (e != hipSuccess) return fail(CGKS_EHIP, std::string("hipFuncGetAttributes: ") + hipGetErrorString(e));
+  if (a.localSizeBytes > limit)
+    return fail(CGKS_EHIP, std::string(what) + " uses " + std::to_string(a.localSizeBytes) +
+                               " bytes of scratch per thread (limit " + std::to_string(limit) + "): rebuild");
+  return CGKS_OK;
+}
+
+struct Header {
+  double t;
+  double dt;
+  unsigned long long smax_bits;
+  unsigned long long rmin_bits;
+  unsigned long long steps;
+  unsigned long long nonphysical;
+  unsigned long long fallbacks;
+  unsigned long long magic;
+  int active;
+  int nparts;      // per-block speed partials written by the last reduction
+  int pad[14];
+};
+static_assert(sizeof(Header) <= 256, "header");
+
+// Per-job progress record of a batch, written by the dt phase each step.
+struct JobStat {
+  double t;
+  double dt;
+  long long steps;
+  int status;   // 0 running, 1 finished (t_end or step limit), 2 nonphysical
+  int active;
+};
+constexpr unsigned long long kMagic = 0x43474b5331ull;
+
+// Geometry passed by value to every kernel.
+struct Geo {
+  int dim, nx, ny, NX, NY, m, nv;
+  int bc[4];
+  size_t cells;
+  __host__ __device__ size_t cell(int i, int j) const {
+    return (size_t)(dim == 2 ? j + H : 0) * NX + (i + H);
+  }
+  __host__ __device__ size_t avg(int v, int i, int j) const { return (size_t)v * cells + cell(i, j); }
+  __host__ __device__ size_t sx(int v, int l, int i, int j) const {
+    return (size_t)nv * cells + ((size_t)v * m + l) * cells + cell(i, j);
+  }
+  __host__ __device__ size_t sy(int v, int l, int i, int j) const {
+    return (size_t)nv * cells + (size_t)nv * m * cells + ((size_t)v * m + l) * cells + cell(i, j);
+  }
+  __host__ __device__ size_t lv(int v, int l, int i, int j) const { return ((size_t)v * m + l) * cells + cell(i, j); }
+  __host__ __device__ size_t sgx(int j, int F) const { return (size_t)(dim == 2 ? j + H : 0) * (NX + 1) + F + H; }
+  __host__ __device__ size_t sgy(int i, int G) const { return (size_t)(i + H) * (NY + 1) + G + H; }
+};
+
+struct Bufs {
+  double* U;      // state (W^n, then W^{n+1})
+  double* S;      // stage state W*
+  double* A;      // accumulator
+  double* sxo;    // strengths in use (previous step)
+  double* sxn;    // strengths computed in this step
+  double* syo;
+  double* syn;
+  double* lvx;
+  double* lvy;
+  double* part;   // per-block [max(|U|+c), min(rho)] of the last reduction
+  Header* hdr;
+};
+
+}  // namespace
+
+struct cgks_plan {
+  Geo g;
+  Consts C;
+  int precision;
+  double dx, dy;
+  size_t state_words, sig_x_words, sig_y_words;
+  size_t off_S, off_A, off_sxo, off_sxn, off_syo, off_syn, off_lvx, off_lvy, off_part, off_hdr, work_words;
+  size_t max_parts;
+};
+
+namespace {
+
+Bufs bufs(const cgks_plan* p, void* d_state, void* d_work) {
+  Bufs b;
+  double* w = (double*)d_work;
+  b.U = (double*)d_state;
+  b.S = w + p->off_S;
+  b.A = w + p->off_A;
+  b.sxo = w + p->off_sxo;
+  b.sxn = w + p->off_sxn;
+  b.syo = w + p->off_syo;
+  b.syn = w + p->off_syn;
+  b.lvx = w + p->off_lvx;
+  b.lvy = w + p->off_lvy;
+  b.part = w + p->off_part;
+  b.hdr = (Header*)(w + p->off_hdr);
+  return b;
+}
+
+// ---------------------------------------------------------------------------
+// boundary conditions (ghost cells and ghost faces)
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int src_cell(int k, int n, int lo, int hi, int& mir) {
+  mir = 0;
+  if (k < 0) {
+    if (lo == CGKS_BC_PERIODIC) return k + n;
+    mir = 1;
+    return -k - 1;
+  }
+  if (k >= n) {
+    if (hi == CGKS_BC_PERIODIC) return k - n;
+    mir = 1;
+    return 2 * n - 1 - k;
+  }
+  return k;
+}
+
+__device__ __forceinline__ int src_face(int F, int n, int lo, int hi) {
+  if (F < 0) return lo == CGKS_BC_PERIODIC ? F + n : -F;
+  if (F > n) return hi == CGKS_BC_PERIODIC ? F - n : 2 * n - F;
+  return F;
+}
+
+// Ghost cells mirror interior cells (transmissive, reflective) or wrap
+// (periodic).  Mirrored: averages copied, the slope normal to the mirror
+// negated, slopes along Gauss lines crossing the mirror taken at the mirrored
+// Gauss point; a reflective wall also makes the normal momentum odd.
+__device__ __forceinline__ void bc_state_at(const Geo& g, double* U, int I, int J) {
+  if (I >= g.NX) return;
+  const int i = I - H, j = (g.dim == 2) ? J - H : 0;
+  const bool gx = (i < 0 || i >= g.nx), gy = (g.dim == 2) && (j < 0 || j >= g.ny);
+  if (!gx && !gy) return;
+  int mx, my = 0;
+  const int si = src_cell(i, g.nx, g.bc[0], g.bc[1], mx);
+  const int sj = (g.dim == 2) ? src_cell(j, g.ny, g.bc[2], g.bc[3], my) : 0;
+  const bool rx = mx && (g.bc[i < 0 ? 0 : 1] == CGKS_BC_REFLECTIVE);
+  const bool ry = my && (g.bc[j < 0 ? 2 : 3] == CGKS_BC_REFLECTIVE);
+  for (int v = 0; v < g.nv; ++v) {
+    double odd = 1.0;
+    if (rx && v == 1) odd = -odd;
+    if (ry && v == 2) odd = -odd;
+    U[g.avg(v, i, j)] = odd * U[g.avg(v, si, sj)];
+    for (int l = 0; l < g.m; ++l) {
+      const int lx = my ? g.m - 1 - l : l;   // x-slope lines are horizontal: mirrored by a y-mirror
+      U[g.sx(v, l, i, j)] = (mx ? -odd : odd) * U[g.sx(v, lx, si, sj)];
+      if (g.dim == 2) {
+        const int ly = mx ? g.m - 1 - l : l;
+        U[g.sy(v, l, i, j)] = (my ? -odd : odd) * U[g.sy(v, ly, si, sj)];
+      }
+    }
+  }
+}
+
+
+// Commit the strengths computed in the previous step (new -> old) and fill
+// the ghost faces and ghost rows/columns of the old set.
+__device__ __forceinline__ void bc_sigma_at(const Geo& g, int which, const double* sxn, double* sxo,
+                                            const double* syn, double* syo, int a, int b) {
+  if (which == 0) {
+    // x-faces: a = F + H in [0, NX], b = row J
+    if (a > g.NX) return;
+    const int F = a - H, j = (g.dim == 2) ? b - H : 0;
+    int my = 0;
+    const int sj = (g.dim == 2) ? src_cell(j, g.ny, g.bc[2], g.bc[3], my) : 0;
+    const int sF = src_face(F, g.nx, g.bc[0], g.bc[1]);
+    sxo[g.sgx(j, F)] = sxn[g.sgx(sj, sF)];
+  } else {
+    // y-faces: a = G + H in [0, NY], b = column I
+    if (a > g.NY) return;
+    const int G = a - H, i = b - H;
+    int mx = 0;
+    const int si = src_cell(i, g.nx, g.bc[0], g.bc[1], mx);
+    const int sG = src_face(G, g.ny, g.bc[2], g.bc[3]);
+    syo[g.sgy(i, G)] = syn[g.sgy(si, sG)];
+  }
+}
+
+
+__device__ __forceinline__ double sigma_pair(const double* Wl, const double* Wr, int D, double gam) {
+  auto pr = [&](const double* W) {
+    double ke = 0.5 * W[1] * W[1] / W[0];
+    if (D == 2) ke += 0.5 * W[2] * W[2] / W[0];
+    return (gam - 1.0) * (W[D + 1] - ke);
+  };
+  const double pl = pr(Wl), pp = pr(Wr);
+  const double cl = sqrt(gam * pl / Wl[0]), cr = sqrt(gam * pp / Wr[0]);
+  const double dp = fabs(pl - pp);
+  const double mn = Wl[1] / Wl[0] / cl - Wr[1] / Wr[0] / cr;
+  const double mt = (D == 2) ? Wl[2] / Wl[0] / cl - Wr[2] / Wr[0] / cr : 0.0;
+  return dp / pl + dp / pp + mn * mn + mt * mt;
+}
+
+
+// ---------------------------------------------------------------------------
+// time step (Sec. 4): reduction of max(|U| + c) and min(rho), then dt
+// ---------------------------------------------------------------------------
+// Block-level max(|U| + c) and min(rho); thread 0 writes the block's partial
+// (reduced by k_dt before the next step).  Called by every thread of the block.
+__device__ __forceinline__ void reduce_speed(const Bufs& B, double s, double r, bool valid, int bid, int nparts) {
+  __shared__ double red[2][16];
+  double sm = valid ? s : 0.0;
+  double rm = valid ? r : INFINITY;
+  for (int off = 32; off > 0; off >>= 1) {
+    sm = fmax(sm, __shfl_xor(sm, off, 64));
+    rm = fmin(rm, __shfl_xor(rm, off, 64));
+  }
+  const int w = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
+  if ((threadIdx.x & 63) == 0) { red[0][w] = sm; red[1][w] = rm; }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int k = 1; k < nw; ++k) { sm = fmax(sm, red[0][k]); rm = fmin(rm, red[1][k]); }
+    B.part[2 * bid] = sm;
+    B.part[2 * bid + 1] = rm;
+    if (bid == 0) B.hdr->nparts = nparts;
+  }
+}
+
+__device__ __forceinline__ bool cell_speed(const double* W, int D, double gam, double& s) {
+  const double r = W[0];
+  const double U = W[1] / r, V = (D == 2) ? W[2] / r : 0.0;
+  const double p = (gam - 1.0) * (W[D + 1] - 0.5 * r * (U * U + V * V));
+  const bool ok = (r > 0.0) && (p > 0.0) && isfinite(W[D + 1]);
+  s = ok ? sqrt(U * U + V * V) + sqrt(gam * p / r) : 0.0;
+  return ok;
+}
+
+
+// One block: reduce the speed partials, then dt, the active flag, time and
+// step count; max_steps > 0 stops the run after that many steps.  The
+// optional progress record gets t, dt, steps and the status.
+__device__ void dt_block(Header* hdr, const double* part, double dt_fixed, double cfl, double t_end, double h,
+                         double mu, int viscous, long long max_steps, JobStat* stat) {
+  __shared__ double red[2][256];
+  __syncthreads();
+  const int np = hdr->nparts;
+  double sm = 0.0, rm = INFINITY;
+  for (int k = threadIdx.x; k < np; k += blockDim.x) {
+    sm = fmax(sm, part[2 * k]);
+    rm = fmin(rm, part[2 * k + 1]);
+  }
+  red[0][threadIdx.x] = sm;
+  red[1][threadIdx.x] = rm;
+  __syncthreads();
+  for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) {
+      red[0][threadIdx.x] = fmax(red[0][threadIdx.x], red[0][threadIdx.x + w]);
+      red[1][threadIdx.x] = fmin(red[1][threadIdx.x], red[1][threadIdx.x + w]);
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x != 0) return;
+  double dt = dt_fixed;
+  if (!(dt > 0.0)) {
+    dt = cfl * h / red[0][0];
+    if (viscous && mu > 0.0) {
+      const double dv = cfl * h * h * red[1][0] / (4.0 * mu);
+      if (dv < dt) dt = dv;
+    }
+  }
+  int active = 1;
+  if (hdr->nonphysical) { active = 0; dt = 0.0; }   // sticky: a nonphysical state stops the run
+  else if (max_steps > 0 && (long long)hdr->steps >= max_steps) { active = 0; dt = 0.0; }
+  else if (t_end > 0.0) {
+    if (hdr->t >= t_end) { active = 0; dt = 0.0; }
+    else if (hdr->t + dt > t_end) dt = t_end - hdr->t;
+  }
+  hdr->dt = dt;
+  hdr->active = active;
+  if (active) {
+    hdr->t += dt;
+    hdr->steps += 1;
+  }
+  if (stat) {
+    // finished once no further step will be taken: the step enqueued now is
+    // the last one when it reaches the step limit or t_end
+    const bool last = (max_steps > 0 && (long long)hdr->steps >= max_steps) || (t_end > 0.0 && hdr->t >= t_end);
+    stat->t = hdr->t;
+    stat->dt = dt;
+    stat->steps = (long long)hdr->steps;
+    stat->status = hdr->nonphysical ? 2 : ((active && !last) ? 0 : 1);
+    stat->active = active;
+  }
+}
+
+
+// ---------------------------------------------------------------------------
+// 2-D Step 1 (Sec. 3.3): tangential ASE-DFF in each column (row) gives the
+// line averages of the cell on the horizontal (vertical) Gauss lines.
+// ---------------------------------------------------------------------------
+template <int M>
+__device__ __forceinline__ void lines_at(const Geo& g, const Consts& C, const double* U, const double* sxo,
+                                         const double* syo, double* lvx, double* lvy, int I, int J) {
+  const int i = I - H;
+  const int j = J - H;
+  if (i > g.nx + 2) return;
+  double wq[4];
+#pragma unroll
+  for (int l = 0; l < M; ++l) wq[l] = kGw[M][l];
+  // x-face line values: column i, rows j-2..j+2, needed for j in [-1, ny]
+  if (j >= -1 && j <= g.ny) {
+    double d[4][9], s[6];
+#pragma unroll
+    for (int f = 0; f < 6; ++f) s[f] = syo[g.sgy(i, j - 2 + f)];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+#pragma unroll
+      for (int k = 0; k < 5; ++k) d[v][k] = U[g.avg(v, i, j + k - 2)];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const int o = k < 2 ? k - 2 : k - 1;
+        double a = 0.0;
+#pragma unroll
+        for (int l = 0; l < M; ++l) a += wq[l] * U[g.sy(v, l, i, j + o)];
+        d[v][5 + k] = C.dy * a;
+      }
+    }
+    const Cascade cs = cascade(s, C.order, C.thres);
+    double out[4][4];
+    recon_nodes<double, 4>(d, cs, C, out);
+#pragma unroll
+    for (int l = 0; l < M; ++l)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) lvx[g.lv(v, l, i, j)] = out[l][v];
+  }
+  // y-face line values: row j, columns i-2..i+2, needed for i in [-1, nx]
+  if (i >= -1 && i <= g.nx && j >= -3 && j <= g.ny + 2) {
+    double d[4][9], s[6];
+#pragma unroll
+    for (int f = 0; f < 6; ++f) s[f] = sxo[g.sgx(j, i - 2 + f)];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+#pragma unroll
+      for (int k = 0; k < 5; ++k) d[v][k] = U[g.avg(v, i + k - 2, j)];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const int o = k < 2 ? k - 2 : k - 1;
+        double a = 0.0;
+#pragma unroll
+        for (int l = 0; l < M; ++l) a += wq[l] * U[g.sx(v, l, i + o, j)];
+        d[v][5 + k] = C.dx * a;
+      }
+    }
+    const Cascade cs = cascade(s, C.order, C.thres);
+    double out[4][4];
+    recon_nodes<double, 4>(d, cs, C, out);
+#pragma unroll
+    for (int l = 0; l < M; ++l)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) lvy[g.lv(v, l, i, j)] = out[l][v];
+  }
+}
+
+
+// ---------------------------------------------------------------------------
+// 2-D face kernel: Step 2 (normal ASE-DFF on every Gauss line), Step 3
+// (tangential derivatives), Step 4 (flux), and the cell update of one
+// direction.  DIR 0: x-faces (normal x), DIR 1: y-faces.
+// ---------------------------------------------------------------------------
+template <int M> struct Tile {
+  static constexpr int NF = 16;                               // faces along the normal
+  static constexpr int NT = M == 2 ? 8 : (M == 3 ? 5 : 4);    // lines along the tangential
+  static constexpr int NC = NF + 1;                           // reconstructed cells
+  static constexpr int NR = NT + 2;                           // reconstructed lines
+  static constexpr int RK1 = 17, RK2 = 8;                     // results per Gauss point (stage 1 / 2)
+};
+
+template <int M, typename T> struct Lds {
+  static constexpr size_t s2v = (size_t)Tile<M>::NR * Tile<M>::NC * M * 8 * sizeof(T);
+  static constexpr size_t s2d = s2v;
+  static constexpr size_t s2dd = (size_t)Tile<M>::NT * Tile<M>::NC * M * 8 * sizeof(T);
+  static constexpr size_t recon = s2v + s2d + s2dd;
+  static constexpr size_t res = (size_t)Tile<M>::NF * Tile<M>::NT * M * Tile<M>::RK1 * sizeof(double);
+  static constexpr size_t fin = (size_t)(Tile<M>::NF - 1) * Tile<M>::NT * 4 * sizeof(double);
+  // reconstruction | Gauss-point results | updated averages: separate, so a
+  // thread stores its flux results as soon as they are computed
+  static constexpr size_t off_res = recon;
+  static constexpr size_t off_fin = recon + res;
+  static constexpr size_t total = recon + res + fin;
+};
+
+// Waves per SIMD the face kernels are compiled for.  Both variants fit their
+// registers without spilling to scratch (FP64 with the whole register file of
+// one wave per SIMD, FP32 with half of it); the library checks at start-up
+// that no face kernel uses private memory.
+template <typename T> struct FaceWaves {
+  static constexpr int value = sizeof(T) == 8 ? 1 : 2;
+};
+
+// One tile (bx, by) of nbx x nby; callable from a persistent loop (starts
+// with a barrier so the LDS of the previous tile is free).
+template <int DIR, int STAGE, int M, typename T, bool PR>
+__device__ void face2d_tile(const Geo& g, const Consts& C, const Bufs& B, unsigned char* smem, int bx, int by,
+                            int nbx, int nby) {
+  using TL = Tile<M>;
+  constexpr int NF = TL::NF, NT = TL::NT, NC = TL::NC, NR = TL::NR;
+  const Header* hdr = B.hdr;
+  __syncthreads();
+  if (!hdr->active) return;
+  const double dt = hdr->dt;
+  T* s2v = (T*)smem;
+  T* s2d = (T*)(smem + Lds<M, T>::s2v);
+  T* s2dd = (T*)(smem + Lds<M, T>::s2v + Lds<M, T>::s2d);
+  double* res = (double*)(smem + Lds<M, T>::off_res);
+  double* fin = (double*)(smem + Lds<M, T>::off_fin);
+  auto I2 = [&](int r, int c, int l, int sd, int v) { return (((r * NC + c) * M + l) * 2 + sd) * 4 + v; };
+
+  const int nmax = DIR == 0 ? g.nx : g.ny;   // cells along the normal
+  const int tmax = DIR == 0 ? g.ny : g.nx;   // cells along the tangential
+  const int F0 = bx * (NF - 1);
+  const int T0 = by * NT;
+  const double hn = DIR == 0 ? C.dx : C.dy, ht = DIR == 0 ? C.dy : C.dx;
+  const double* Uin = STAGE == 1 ? B.U : B.S;
+  const double* LV = DIR == 0 ? B.lvx : B.lvy;
+  const double* sgN = DIR == 0 ? B.sxo : B.syo;   // normal-face strengths
+  const double* sgT = DIR == 0 ? B.syo : B.sxo;   // tangential-face strengths
+  const int gcomp[4] = {0, DIR == 0 ? 1 : 2, DIR == 0 ? 2 : 1, 3};
+  auto gi = [&](int n, int t) { return DIR == 0 ? n : t; };
+  auto gj = [&](int n, int t) { return DIR == 0 ? t : n; };
+  auto sN = [&](int v, int l, int n, int t) {  // normal slope on line l
+    return DIR == 0 ? g.sx(v, l, gi(n, t), gj(n, t)) : g.sy(v, l, gi(n, t), gj(n, t));
+  };
+  auto sgn_idx = [&](int t, int face) { return DIR == 0 ? g.sgx(t, face) : g.sgy(t, face); };
+  auto sgt_idx = [&](int n, int face) { return DIR == 0 ? g.sgy(n, face) : g.sgx(n, face); };
+
+  // ---- Step 2: normal reconstruction on each line, both faces of a cell ----
+  constexpr int NA = NC * NR * M;
+  for (int it = threadIdx.x; it < NA; it += blockDim.x) {
+    int c, r, l;
+    if (DIR == 0) { c = it % NC; r = (it / NC) % NR; l = it / (NC * NR); }
+    else { r = it % NR; c = (it / NR) % NC; l = it / (NC * NR); }
+    const int n = F0 - 1 + c, t = T0 - 1 + r;
+    if (n < -1 || n > nmax || t < -1 || t > tmax) continue;
+    double s[6];
+#pragma unroll
+    for (int f = 0; f < 6; ++f) s[f] = sgN[sgn_idx(t, n - 2 + f)];
+    const Cascade cs = cascade(s, C.order, C.thres);
+    T d[4][9];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int gv = gcomp[v];
+#pragma unroll
+      for (int k = 0; k < 5; ++k) d[v][k] = T(LV[g.lv(gv, l, gi(n + k - 2, t), gj(n + k - 2, t))]);
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const int o = k < 2 ? k - 2 : k - 1;
+        d[v][5 + k] = T(hn * Uin[sN(gv, l, n + o, t)]);
+      }
+    }
+    T out[2][3][4];
+    recon_faces<T, 4>(d, cs, C, out);
+    const T ih = T(1.0 / hn), ih2 = T(1.0 / (hn * hn));
+#pragma unroll
+    for (int sd = 0; sd < 2; ++sd)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        s2v[I2(r, c, l, sd, v)] = out[sd][0][v];
+        s2d[I2(r, c, l, sd, v)] = out[sd][1][v] * ih;
+        if (r >= 1 && r <= NT) s2dd[I2(r - 1, c, l, sd, v)] = out[sd][2][v] * ih2;
+      }
+  }
+  __syncthreads();
+
+  // ---- Steps 3-4 at every face Gauss point: one Gauss point per thread ----
+  constexpr int NB = NF * NT * M;
+  static_assert(NB <= 256, "one Gauss point per thread of a 256-thread block");
+  const int it = threadIdx.x;
+  int f, r, l;
+  if (DIR == 0) { f = it % NF; r = (it / NF) % NT; l = it / (NF * NT); }
+  else { r = it % NT; f = (it / NT) % NF; l = it / (NF * NT); }
+  if (it < NB && F0 + f <= nmax && T0 + r < tmax) {
+    const int nf = F0 + f, t = T0 + r;
+    T Wk[2][6][4];
+#pragma unroll
+    for (int sd = 0; sd < 2; ++sd) {
+      const int c = sd == 0 ? f : f + 1;      // left state: cell nf-1 (its +1/2 face); right: cell nf
+      const int ncell = nf - 1 + sd;
+      double A = 0.0;
+#pragma unroll
+      for (int q = -1; q <= 2; ++q) A += sgT[sgt_idx(ncell, t + q)];
+      const T at = T(dff_of(A, C.thres));
+      const T it1 = at / T(ht), it2 = at / T(ht * ht);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        Wk[sd][0][v] = s2v[I2(r + 1, c, l, sd, v)];
+        Wk[sd][1][v] = s2d[I2(r + 1, c, l, sd, v)];
+        Wk[sd][3][v] = s2dd[I2(r, c, l, sd, v)];
+        T a1 = 0, a2 = 0, ax = 0;
+#pragma unroll
+        for (int rr = 0; rr < 3; ++rr)
+#pragma unroll
+          for (int q = 0; q < M; ++q) {
+            const T w1 = T(kT1[M][l][rr * M + q]), w2 = T(kT2[M][l][rr * M + q]);
+            const T val = s2v[I2(r + rr, c, q, sd, v)];
+            a1 += w1 * val;
+            a2 += w2 * val;
+            ax += w1 * s2d[I2(r + rr, c, q, sd, v)];
+          }
+        Wk[sd][2][v] = it1 * a1;
+        Wk[sd][5][v] = it2 * a2;
+        Wk[sd][4][v] = it1 * ax;
+      }
+      // first order from the cell average where the state is nonphysical
+      T rho, U, V, p;
+      primitive<T, 2>(Wk[sd][0], T(C.gamma - 1.0), rho, U, V, p);
+      if (!(rho > T(0)) || !(p > T(0))) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          Wk[sd][0][v] = T(Uin[g.avg(gcomp[v], gi(ncell, t), gj(ncell, t))]);
+#pragma unroll
+          for (int dd = 1; dd < 6; ++dd) Wk[sd][dd][v] = T(0);
+        }
+        atomicAdd((unsigned long long*)&B.hdr->fallbacks, 1ull);
+      }
+    }
+    FaceOut fo;
+    gks_flux<T, 2, PR>(Wk[0], Wk[1], dt, C, fo);
+    // results to LDS (global component order)
+    double* rp = res + (((size_t)f * NT + r) * M + l) * (STAGE == 1 ? TL::RK1 : TL::RK2);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int gv = gcomp[v];
+      if (STAGE == 1) {
+        rp[gv] = fo.Fh[v];
+        rp[4 + gv] = (8.0 / 3.0) * fo.Fh[v] - (1.0 / 3.0) * fo.F1[v];
+        rp[8 + gv] = fo.Wh[v];
+        rp[12 + gv] = -(4.0 / 3.0) * fo.W0[v] + (8.0 / 3.0) * fo.Wh[v] - (1.0 / 3.0) * fo.W1[v];
+      } else {
+        rp[gv] = (4.0 / 3.0) * (fo.F1[v] - 2.0 * fo.Fh[v]);
+        rp[4 + gv] = (4.0 / 3.0) * (fo.W0[v] - 2.0 * fo.Wh[v] + fo.W1[v]);
+      }
+    }
+    if (STAGE == 1) rp[16] = fo.sigma;
+  }
+  __syncthreads();
+
+  // ---- strengths of this step (stage 1): mean over the Gauss points ----
+  if (STAGE == 1) {
+    for (int it = threadIdx.x; it < NF * NT; it += blockDim.x) {
+      const int f = DIR == 0 ? it % NF : it / NT, r = DIR == 0 ? it / NF : it % NT;
+      const int nf = F0 + f, t = T0 + r;
+      if (nf > nmax || t >= tmax) continue;
+      double s = 0.0;
+      for (int l = 0; l < M; ++l) s += res[(((size_t)f * NT + r) * M + l) * TL::RK1 + 16];
+      (DIR == 0 ? B.sxn : B.syn)[sgn_idx(t, nf)] = s / M;
+    }
+  }
+
+  // ---- cell update of this direction ----
+  constexpr int RK = STAGE == 1 ? TL::RK1 : TL::RK2;
+  const double ihn = 1.0 / hn;
+  for (int it = threadIdx.x; it < (NF - 1) * NT * 4; it += blockDim.x) {
+    int ci, r, v;
+    if (DIR == 0) { ci = it % (NF - 1); r = (it / (NF - 1)) % NT; v = it / ((NF - 1) * NT); }
+    else { r = it % NT; ci = (it / NT) % (NF - 1); v = it / ((NF - 1) * NT); }
+    const int n = F0 + ci, t = T0 + r;
+    if (n >= nmax || t >= tmax) continue;
+    const int i = gi(n, t), j = gj(n, t);
+    const double* ra = res + (((size_t)ci * NT + r) * M) * RK;        // face n
+    const double* rb = res + (((size_t)(ci + 1) * NT + r) * M) * RK;  // face n+1
+    const size_t ia = g.avg(v, i, j);
+    if (STAGE == 1) {
+      double dF = 0.0, dA = 0.0;
+      for (int l = 0; l < M; ++l) {
+        const double w = kGw[M][l];
+        dF += w * (rb[l * RK + v] - ra[l * RK + v]);
+        dA += w * (rb[l * RK + 4 + v] - ra[l * RK + 4 + v]);
+      }
+      const double base = DIR == 0 ? B.U[ia] : B.S[ia];
+      const double abase = DIR == 0 ? B.U[ia] : B.A[ia];
+      const double snew = base - dF * ihn;
+      B.S[ia] = snew;
+      B.A[ia] = abase - dA * ihn;
+      if (DIR == 1) fin[((size_t)ci * NT + r) * 4 + v] = snew;
+      for (int l = 0; l < M; ++l) {
+        const size_t is = DIR == 0 ? g.sx(v, l, i, j) : g.sy(v, l, i, j);
+        B.S[is] = (rb[l * RK + 8 + v] - ra[l * RK + 8 + v]) * ihn;
+        B.A[is] = (rb[l * RK + 12 + v] - ra[l * RK + 12 + v]) * ihn;
+      }
+    } else {
+      double dA = 0.0;
+      for (int l = 0; l < M; ++l) dA += kGw[M][l] * (rb[l * RK + v] - ra[l * RK + v]);
+      const double base = DIR == 0 ? B.A[ia] : B.U[ia];
+      const double unew = base - dA * ihn;
+      B.U[ia] = unew;
+      if (DIR == 1) fin[((size_t)ci * NT + r) * 4 + v] = unew;
+      for (int l = 0; l < M; ++l) {
+        const size_t is = DIR == 0 ? g.sx(v, l, i, j) : g.sy(v, l, i, j);
+        B.U[is] = B.A[is] + (rb[l * RK + 4 + v] - ra[l * RK + 4 + v]) * ihn;
+      }
+    }
+  }
+  if (DIR == 1) {
+    __syncthreads();
+    // health and (stage 2) the speed reduction for the next time step
+    const int it = threadIdx.x;
+    bool valid = false;
+    double s = 0.0, rr = 1.0;
+    if (it < (NF - 1) * NT) {
+      const int r = it % NT, ci = it / NT;
+      const int n = F0 + ci, t = T0 + r;
+      if (n < nmax && t < tmax) {
+        double W[4];
+        for (int v = 0; v < 4; ++v) W[v] = fin[((size_t)ci * NT + r) * 4 + v];
+        rr = W[0];
+        valid = cell_speed(W, 2, C.gamma, s);
+        if (!valid) atomicAdd((unsigned long long*)&B.hdr->nonphysical, 1ull);
+      }
+    }
+    if (STAGE == 2) reduce_speed(B, s, rr, valid, bx + nbx * by, nbx * nby);
+  }
+}
+
+
+// ---------------------------------------------------------------------------
+// 1-D stage kernel: one thread per face; each reconstructs its two cells.
+// A block owns faces F0..F0+255 and updates cells F0..F0+254.
+// ---------------------------------------------------------------------------
+template <int STAGE, typename T, bool PR>
+__device__ void stage1d_seg(const Geo& g, const Consts& C, const Bufs& B, double (*res)[12], int seg, int nseg) {
+  const Header* hdr = B.hdr;
+  __syncthreads();
+  if (!hdr->active) return;
+  const double dt = hdr->dt;
+  constexpr int NFB = 256;
+  const int F0 = seg * (NFB - 1);
+  const int f = threadIdx.x;
+  const int F = F0 + f;
+  const double* Uin = STAGE == 1 ? B.U : B.S;
+  const double h = C.dx;
+  if (F <= g.nx) {
+    T Wk[2][6][4];
+#pragma unroll
+    for (int sd = 0; sd < 2; ++sd) {
+      const int cell = F - 1 + sd;
+      double s[6];
+#pragma unroll
+      for (int q = 0; q < 6; ++q) s[q] = B.sxo[g.sgx(0, cell - 2 + q)];
+      const Cascade cs = cascade(s, C.order, C.thres);
+      T d[3][9];
+#pragma unroll
+      for (int v = 0; v < 3; ++v) {
+#pragma unroll
+        for (int k = 0; k < 5; ++k) d[v][k] = T(Uin[g.avg(v, cell + k - 2, 0)]);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          const int o = k < 2 ? k - 2 : k - 1;
+          d[v][5 + k] = T(h * Uin[g.sx(v, 0, cell + o, 0)]);
+        }
+      }
+      T out[2][3][3];
+      recon_faces<T, 3>(d, cs, C, out);
+      const int side = sd == 0 ? 0 : 1;   // left state: +1/2 face of cell F-1; right: -1/2 face of cell F
+#pragma unroll
+      for (int v = 0; v < 4; ++v)
+#pragma unroll
+        for (int dd = 0; dd < 6; ++dd) Wk[sd][dd][v] = T(0);
+#pragma unroll
+      for (int v = 0; v < 3; ++v) {
+        Wk[sd][0][v] = out[side][0][v];
+        Wk[sd][1][v] = out[side][1][v] / T(h);
+        Wk[sd][3][v] = out[side][2][v] / T(h * h);
+      }
+      T rho, U, V, p;
+      primitive<T, 1>(Wk[sd][0], T(C.gamma - 1.0), rho, U, V, p);
+      if (!(rho > T(0)) || !(p > T(0))) {
+#pragma unroll
+        for (int v = 0; v < 3; ++v) {
+          Wk[sd][0][v] = T(Uin[g.avg(v, cell, 0)]);
+          Wk[sd][1][v] = T(0);
+          Wk[sd][3][v] = T(0);
+        }
+        atomicAdd((unsigned long long*)&B.hdr->fallbacks, 1ull);
+      }
+    }
+    FaceOut fo;
+    gks_flux<T, 1, PR>(Wk[0], Wk[1], dt, C, fo);
+#pragma unroll
+    for (int v = 0; v < 3; ++v) {
+      if (STAGE == 1) {
+        res[f][v] = fo.Fh[v];
+        res[f][3 + v] = (8.0 / 3.0) * fo.Fh[v] - (1.0 / 3.0) * fo.F1[v];
+        res[f][6 + v] = fo.Wh[v];
+        res[f][9 + v] = -(4.0 / 3.0) * fo.W0[v] + (8.0 / 3.0) * fo.Wh[v] - (1.0 / 3.0) * fo.W1[v];
+      } else {
+        res[f][v] = (4.0 / 3.0) * (fo.F1[v] - 2.0 * fo.Fh[v]);
+        res[f][3 + v] = (4.0 / 3.0) * (fo.W0[v] - 2.0 * fo.Wh[v] + fo.W1[v]);
+      }
+    }
+    if (STAGE == 1) B.sxn[g.sgx(0, F)] = fo.sigma;
+  }
+  __syncthreads();
+  const int i = F0 + f;  // cell
+  bool valid = false;
+  double s = 0.0, rr = 1.0;
+  if (f < NFB - 1 && i < g.nx) {
+    const double ih = 1.0 / h;
+    double W[3];
+    for (int v = 0; v < 3; ++v) {
+      const size_t ia = g.avg(v, i, 0), is = g.sx(v, 0, i, 0);
+      if (STAGE == 1) {
+        const double u0 = B.U[ia];
+        W[v] = u0 - (res[f + 1][v] - res[f][v]) * ih;
+        B.S[ia] = W[v];
+        B.A[ia] = u0 - (res[f + 1][3 + v] - res[f][3 + v]) * ih;
+        B.S[is] = (res[f + 1][6 + v] - res[f][6 + v]) * ih;
+        B.A[is] = (res[f + 1][9 + v] - res[f][9 + v]) * ih;
+      } else {
+        W[v] = B.A[ia] - (res[f + 1][v] - res[f][v]) * ih;
+        B.U[ia] = W[v];
+        B.U[is] = B.A[is] + (res[f + 1][3 + v] - res[f][3 + v]) * ih;
+      }
+    }
+    rr = W[0];
+    valid = cell_speed(W, 1, C.gamma, s);
+    if (!valid) atomicAdd((unsigned long long*)&B.hdr->nonphysical, 1ull);
+  }
+  if (STAGE == 2) reduce_speed(B, s, rr, valid, seg, nseg);
+}
+
+}  // namespace

@@ -180,3 +180,34 @@ def test_nonphysical_state_is_reported():
     s = cgks.Solver(pb)
     h = s.health()
     assert h["status"] == cgks.ENONPHYSICAL and h["nonphysical"] >= 1
+
+
+@pytest.mark.parametrize("order,n,kind", [(5, 23, "quadrant"), (7, 17, "fourier"), (9, 19, "quadrant")])
+def test_small_ragged_grids_every_order(order, n, kind):
+    """One tile or less per direction with a ragged edge, every order.  Kernels
+    that spilled registers to scratch got these wrong, differently from run to
+    run; the library now refuses such builds."""
+    pb = (W.quadrant_2d(W.random_quadrants(11), n, order, nsteps=3, name=f"q{n}o{order}") if kind == "quadrant"
+          else W.fourier_2d(12, n, order, nsteps=3))
+    got, ref, _ = run_both(pb)
+    assert_parity(got, ref, 2, h=cell(pb))
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32_flux"])
+def test_bitwise_reproducible_across_runs(precision):
+    """The same problem stepped twice in one process, with unrelated device
+    work in between, gives bit-identical states for every order."""
+    import torch
+    from paper_2508_13705_amd import cgks
+    for order in (5, 7, 9):
+        pb = W.quadrant_2d(W.random_quadrants(order), 21, order, nsteps=0, name=f"rep{order}")
+        outs = []
+        for rep in range(2):
+            junk = torch.randn(1 << 22, device="cuda", dtype=torch.float64)   # leaves other data behind
+            _ = (junk * junk).sum().item()
+            s = cgks.Solver(pb, precision=precision)
+            s.step(4)
+            outs.append(s.read())
+            del s, junk
+        for k in ("avg", "sx", "sy", "sigx", "sigy"):
+            assert np.array_equal(outs[0][k], outs[1][k]), (order, k)

@@ -64,3 +64,27 @@ def test_status_strings():
     L = cgks.lib()
     assert L.cgks_status_string(0) == b"ok"
     assert L.cgks_status_string(4) == b"nonphysical state"
+
+
+@pytest.mark.parametrize("dim,prec,cap,frag", [
+    (3, 0, 4, "dim"),
+    (2, 7, 4, "precision"),
+    (2, 0, 0, "max_jobs"),
+])
+def test_batch_create_rejects_bad_arguments(dim, prec, cap, frag):
+    """Argument checks come before any device call (no GPU needed)."""
+    L = cgks.lib()
+    h = ctypes.c_void_p()
+    st = L.cgks_batch_create(dim, prec, cap, 0, ctypes.byref(h))
+    assert st == cgks.EINVAL
+    assert frag in L.cgks_last_error().decode()
+    assert not h.value
+
+
+def test_batch_calls_reject_null_batch():
+    L = cgks.lib()
+    assert L.cgks_batch_commit(None, None) == cgks.EINVAL
+    assert L.cgks_batch_step(None, 1, None) == cgks.EINVAL
+    assert L.cgks_batch_launch(None, None) == cgks.EINVAL
+    assert L.cgks_batch_remove(None, 0) == cgks.EINVAL
+    assert L.cgks_batch_destroy(None) == cgks.OK
