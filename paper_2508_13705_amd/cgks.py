@@ -69,6 +69,11 @@ def lib():
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"{LIB_PATH} is not built; run __graft_entry__.build()")
+        # One HIP runtime per process: PyTorch's libamdhip64 (the same soname
+        # as the one this library needs) is loaded first and serves both;
+        # loading this library first would bring in a second runtime that
+        # then finds no device.
+        import torch  # noqa: F401
         L = ctypes.CDLL(LIB_PATH)
         vp, dp = ctypes.c_void_p, ctypes.POINTER(ctypes.c_double)
         L.cgks_plan_create.argtypes = [ctypes.POINTER(GridDesc), ctypes.POINTER(SchemeDesc), ctypes.POINTER(vp)]

@@ -328,11 +328,6 @@ cgks_status cgks_batch_create(int dim, int precision, int max_jobs, size_t hbm_b
     delete b;
     return fail(CGKS_ENOMEM, "batch host tables");
   }
-  const cgks_status ps = precision == CGKS_FP64 ? prepare_batch<double>() : prepare_batch<float>();
-  if (ps != CGKS_OK) {
-    delete b;
-    return ps;
-  }
   auto up = [](size_t x) { return (x + 255) & ~(size_t)255; };
   const size_t o_jobs = up(sizeof(BTab));
   const size_t o_pre = o_jobs + up(sizeof(BJob) * max_jobs);
@@ -344,7 +339,16 @@ cgks_status cgks_batch_create(int dim, int precision, int max_jobs, size_t hbm_b
   int dev = 0;
   if (e == hipSuccess) e = hipGetDevice(&dev);
   if (e == hipSuccess) e = hipDeviceGetAttribute(&b->ncu, hipDeviceAttributeMultiprocessorCount, dev);
-  if (e == hipSuccess) e = precision == CGKS_FP64 ? occupancy<double>(b) : occupancy<float>(b);
+  if (e == hipSuccess) {
+    // kernel attributes (dynamic LDS, scratch check) before the occupancy query
+    const cgks_status ps = precision == CGKS_FP64 ? prepare_batch<double>() : prepare_batch<float>();
+    if (ps != CGKS_OK) {
+      hipFree(b->dmem);
+      delete b;
+      return ps;
+    }
+    e = precision == CGKS_FP64 ? occupancy<double>(b) : occupancy<float>(b);
+  }
   if (e == hipSuccess) e = hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking);
   if (e != hipSuccess) {
     if (b->dmem) hipFree(b->dmem);

@@ -179,40 +179,45 @@ def _grid2(nx, ny, x0, x1, y0, y1):
     return dx, dy, xc, yc
 
 
+def _sin_grid(ax, by, ph):
+    """sin(ax[i] + by[j] + ph) on the [j][i] grid, by the angle-addition
+    identity (outer products of 1-D arrays instead of n^2 sines)."""
+    return np.outer(np.cos(by + ph), np.sin(ax)) + np.outer(np.sin(by + ph), np.cos(ax))
+
+
+def _cos_grid(ax, by, ph):
+    """cos(ax[i] + by[j] + ph) on the [j][i] grid."""
+    return np.outer(np.cos(by + ph), np.cos(ax)) - np.outer(np.sin(by + ph), np.sin(ax))
+
+
 def smooth_2d(modes, n, order, u=1.0, v=1.0, p=1.0, gamma=1.4, L=2.0, nsteps=100, dt=0.0, t_end=0.0,
               name="smooth_2d", **scheme_kw):
     """rho = 1 + sum a sin(pi (kx x + ky y) + phi), constant (u, v, p), periodic
     [0, L]^2 with integer (kx, ky) when L = 2.  W is linear in rho: exact cell
-    averages by the product of sinc factors, line slopes from point values."""
+    averages by the product of sinc factors; the line slopes are exact
+    differences of face values, sin(w(x+h)) - sin(w(x-h)) = 2 cos(wx) sin(wh)."""
     m = GAUSS_M[order]
     xg, _ = gauss_legendre(m)
     dx, dy, xc, yc = _grid2(n, n, 0.0, L, 0.0, L)
-    X, Y = np.meshgrid(xc, yc)  # [j][i]
     ravg = np.ones((n, n))
     for a, kx, ky, ph in modes:
         wx, wy = math.pi * kx, math.pi * ky
-        ravg += a * np.sin(wx * X + wy * Y + ph) * _sinc(0.5 * wx * dx) * _sinc(0.5 * wy * dy)
-
-    def rho_at(x, y):
-        r = np.ones(np.broadcast(x, y).shape)
-        for a, kx, ky, ph in modes:
-            r = r + a * np.sin(math.pi * kx * x + math.pi * ky * y + ph)
-        return r
-
-    def cons_at(x, y):
-        r = rho_at(x, y)
-        one = np.ones_like(r)
-        return _cons(r, u * one, v * one, p * one, gamma, 2)
-
+        ravg += a * _sin_grid(wx * xc, wy * yc, ph) * _sinc(0.5 * wx * dx) * _sinc(0.5 * wy * dy)
+    # W = (rho, rho u, rho v, p/(gamma-1) + rho (u^2+v^2)/2) is affine in rho
+    dW = np.array([1.0, u, v, 0.5 * (u * u + v * v)])
     one = np.ones_like(ravg)
     avg = _cons(ravg, u * one, v * one, p * one, gamma, 2)
-    sx = np.zeros((4, m, n, n))
-    sy = np.zeros((4, m, n, n))
+    sx = np.empty((4, m, n, n))
+    sy = np.empty((4, m, n, n))
     for l in range(m):
-        yl = Y + xg[l] * dy
-        sx[:, l] = (cons_at(X + 0.5 * dx, yl) - cons_at(X - 0.5 * dx, yl)) / dx
-        xl = X + xg[l] * dx
-        sy[:, l] = (cons_at(xl, Y + 0.5 * dy) - cons_at(xl, Y - 0.5 * dy)) / dy
+        gx = np.zeros((n, n))
+        gy = np.zeros((n, n))
+        for a, kx, ky, ph in modes:
+            wx, wy = math.pi * kx, math.pi * ky
+            gx += (2.0 * a * math.sin(0.5 * wx * dx) / dx) * _cos_grid(wx * xc, wy * (yc + xg[l] * dy), ph)
+            gy += (2.0 * a * math.sin(0.5 * wy * dy) / dy) * _cos_grid(wx * (xc + xg[l] * dx), wy * yc, ph)
+        sx[:, l] = dW[:, None, None] * gx
+        sy[:, l] = dW[:, None, None] * gy
     return {"name": name,
             "grid": {"dim": 2, "nx": n, "ny": n, "x0": 0.0, "x1": L, "y0": 0.0, "y1": L, "bc": ["periodic"] * 4},
             "scheme": default_scheme(order, gamma=gamma, tau="zero", **scheme_kw),
