@@ -8,8 +8,17 @@ every cell (reconstruction, interface flux, update of cell averages and
 slopes).  The headline value is the FP32-flux variant (reconstruction and flux
 moments in FP32, FP64 accumulation); the FP64 path is timed beside it.
 
+Beside the headline, the same run measures (a) the batched path on the
+4096-problem 1-D Riemann batch (200-4000 cells each, 9th order, CFL 0.5),
+one persistent launch per phase for the whole batch in a captured hipGraph,
+against the same jobs stepped one at a time by the single-grid path, and
+(b) the serving loop on a Poisson trace of 2-D jobs (side 128-2048, orders
+5/7/9, smooth or four-quadrant data, 50-500 steps) under an HBM budget:
+p50/p99 latency and throughput.
+
 Prints one JSON line.  Usage:
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--n 2048] [--cpu-seconds 20]
+                    [--batch-steps 40] [--serve-jobs 24]
 """
 import argparse
 import hashlib
@@ -41,6 +50,13 @@ def parse():
     ap.add_argument("--n", type=int, default=2048)
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--fp64-steps", type=int, default=None, help="timed steps of the FP64 path (default: --steps)")
+    ap.add_argument("--batch-jobs", type=int, default=4096)
+    ap.add_argument("--batch-steps", type=int, default=40, help="timed batch steps of the 1-D batch (0: skip)")
+    ap.add_argument("--serve-jobs", type=int, default=24, help="jobs in the serving trace (0: skip)")
+    ap.add_argument("--serve-load", type=float, default=0.6, help="offered load of the serving trace")
+    ap.add_argument("--pmc-probe", action="store_true",
+                    help="for hardware-counter runs: one step of each path, then a device copy of "
+                         "COPY_BYTES (the calibration of the byte counters); prints nothing else")
     return ap.parse_args()
 
 
@@ -85,6 +101,74 @@ def time_path(problem, precision, steps, warmup):
     return el, per, h, st
 
 
+def bench_batch_1d(jobs, steps, precision, graph_steps=10):
+    """Batched 1-D Riemann problems: cell-updates/s of the captured batch
+    step, and of the same jobs stepped one by one on the single-grid path."""
+    import torch
+    from paper_2508_13705_amd import cgks
+    from paper_2508_13705_amd import workloads as W
+    probs = W.riemann_batch(seed=2, count=jobs)
+    stream = torch.cuda.Stream()
+    B = cgks.Batch(1, precision, max_jobs=jobs, stream=stream)
+    sol = [cgks.Solver(pb, precision=precision, stream=stream) for pb in probs]
+    cells = {}
+    for pb, s in zip(probs, sol):
+        cells[B.add(s, max_steps=0, t_end=pb["run"]["t_end"])] = pb["grid"]["nx"]
+    B.commit()
+    tuning = B.tune(1)
+    B.capture(graph_steps)
+    B.launch()
+    st0 = B.poll()
+    reps = max(1, steps // graph_steps)
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        B.launch()
+    st1 = B.poll()
+    el = time.perf_counter() - t0
+    upd = sum(cells[k] * (st1[k]["steps"] - st0[k]["steps"]) for k in cells)
+    active = sum(1 for k in cells if st1[k]["status"] == 0)
+    nonphys = sum(1 for k in cells if st1[k]["status"] == 2)
+    # the same jobs one at a time, single-grid path (a sample, same step count)
+    sample = sol[: min(256, len(sol))]
+    with torch.cuda.stream(stream):
+        for s in sample:
+            s.step(2, t_end=0.15)
+        h0 = [s.health()["steps"] for s in sample]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for s in sample:
+            s.step(graph_steps, t_end=0.15)
+        torch.cuda.synchronize()
+        el1 = time.perf_counter() - t0
+        h1 = [s.health()["steps"] for s in sample]
+    upd1 = sum(s.plan.gd.nx * (b - a) for s, a, b in zip(sample, h0, h1))
+    return {"workload": f"{jobs} 1-D Riemann problems, 200-4000 cells, order 9, CFL 0.5, t_end 0.15, seed 2",
+            "precision": precision, "value": upd / el, "unit": "cell-updates/s", "batch_steps": reps * graph_steps,
+            "ms_per_batch_step": 1e3 * el / (reps * graph_steps), "jobs_active": active, "jobs_nonphysical": nonphys,
+            "tuning": tuning,
+            "single_grid_sequential": {"value": upd1 / el1 if el1 > 0 else None, "jobs": len(sample),
+                                       "steps_each": graph_steps},
+            "speedup_vs_single_grid": (upd / el) / (upd1 / el1) if upd1 > 0 else None}
+
+
+def bench_serving(jobs, load, ref_rate, precision="fp32_flux"):
+    """Serving loop on a Poisson trace of 2-D jobs; arrival rate set for an
+    offered load `load` of the measured single-grid rate `ref_rate`."""
+    from paper_2508_13705_amd import serving
+    from paper_2508_13705_amd import workloads as W
+    probe = W.serving_trace(seed=5, count=jobs, rate=1.0)
+    work = sum(j["n"] * j["n"] * j["nsteps"] for j in probe) / jobs
+    rate = load * ref_rate / work
+    trace = W.serving_trace(seed=5, count=jobs, rate=rate)
+    loop = serving.ServingLoop(2, precision, hbm_budget=64 << 30, max_jobs=32, graph_steps=4, prep_workers=4)
+    rep = loop.run(trace, log=lambda m: print("[serve]", m, file=sys.stderr, flush=True))
+    rep.pop("records")
+    rep.update({"workload": f"{jobs} 2-D jobs, Poisson arrivals {rate:.3f}/s, side 2^U[7,11], order 5/7/9, "
+                            f"smooth or four-quadrant data, 50-500 steps, seed 5, budget 64 GiB",
+                "precision": precision, "offered_load": load, "mean_job_cell_updates": work})
+    return rep
+
+
 def cpu_baseline(seconds):
     """The plain FP64 oracle on a bounded sample of the same workload (a
     smaller periodic grid with the same order, viscosity model, spectrum
@@ -108,8 +192,32 @@ def cpu_baseline(seconds):
                       f"status {r['status']}"}
 
 
+COPY_BYTES = 1 << 30
+
+
+def pmc_probe(n):
+    import torch
+    from paper_2508_13705_amd import cgks
+    from paper_2508_13705_amd import workloads as W
+    problem = W.turbulence_2d(seed=4, n=n, order=9, nsteps=1, prandtl=0.72, quad=4)
+    for precision in ("fp32_flux", "fp64"):
+        s = cgks.Solver(problem, precision=precision)
+        s.step(1)
+        torch.cuda.synchronize()
+        del s
+        torch.cuda.empty_cache()
+    src = torch.ones(COPY_BYTES // 8, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"pmc_probe": True, "copy_bytes": COPY_BYTES, "n": n}))
+
+
 def main():
     a = parse()
+    if a.pmc_probe:
+        pmc_probe(a.n)
+        return
     if a.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)
@@ -167,6 +275,10 @@ def main():
         "kernel_ms": {"fp32_flux": p["avg_ms"], "fp64": q["avg_ms"]},
         "health": {"fp32_flux": p["health"], "fp64": q["health"]},
     }
+    if a.batch_steps > 0:
+        out["batch_1d"] = {prec: bench_batch_1d(a.batch_jobs, a.batch_steps, prec) for prec in ("fp64", "fp32_flux")}
+    if a.serve_jobs > 0:
+        out["serving"] = bench_serving(a.serve_jobs, a.serve_load, value)
     out["cpu_baseline"] = cpu_baseline(a.cpu_seconds)
     print(json.dumps(out))
 
