@@ -190,13 +190,13 @@ const char* kKernels2d[] = {"dt", "bc_sigma", "bc_state", "lines", "face_x_stage
                             "bc_state", "lines", "face_x_stage2", "face_y_stage2"};
 
 // Face kernels of one order and precision: dynamic LDS limit and the scratch
-// check (FP64 none; FP32 a few spill slots, verified bit-reproducible).
+// check (no scratch).
 template <int DIR, int STAGE, int M, typename T, bool PR>
 cgks_status prepare_face() {
   const void* f = (const void*)k_face2d<DIR, STAGE, M, T, PR>;
   hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)Lds<M, T>::total);
   if (e != hipSuccess) return fail(CGKS_EHIP, std::string("hipFuncSetAttribute: ") + hipGetErrorString(e));
-  return check_private(f, sizeof(T) == 8 ? 0 : 16, "face kernel");
+  return check_private(f, 0, "face kernel");
 }
 
 template <int M, typename T, bool PR>
@@ -288,6 +288,7 @@ cgks_status cgks_plan_create(const cgks_grid_desc* gd, const cgks_scheme_desc* s
   Consts& C = p->C;
   C.gamma = sd->gamma;
   C.Kd = 2.0 / (sd->gamma - 1.0);
+  C.iKd = 1.0 / C.Kd;
   C.c1 = sd->c1;
   C.c2 = sd->c2;
   C.mu = sd->mu;

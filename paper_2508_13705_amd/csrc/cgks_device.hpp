@@ -28,6 +28,7 @@ inline namespace CGKS_UNIT {
 
 struct Consts {
   double gamma, Kd;          // Kd = 2/(gamma-1) = K + D (K internal degrees of freedom)
+  double iKd;                // 1 / Kd
   double c1, c2, mu, prandtl;
   double thres, ghi, glo, eps;
   double dx, dy;
@@ -44,6 +45,25 @@ template <typename T> CGKS_HD T dev_sqrt(T x);
 template <> CGKS_HD __forceinline__ double dev_sqrt<double>(double x) { return sqrt(x); }
 template <> CGKS_HD __forceinline__ float dev_sqrt<float>(float x) { return sqrtf(x); }
 
+// Reciprocal and reciprocal square root: correctly rounded in double; the
+// hardware approximations (1 ulp) in the FP32 flux variant.
+template <typename T> CGKS_HD __forceinline__ T dev_rcp(T x) { return T(1) / x; }
+template <typename T> CGKS_HD __forceinline__ T dev_rsqrt(T x) { return T(1) / dev_sqrt<T>(x); }
+template <> CGKS_HD __forceinline__ float dev_rcp<float>(float x) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  return __builtin_amdgcn_rcpf(x);
+#else
+  return 1.0f / x;
+#endif
+}
+template <> CGKS_HD __forceinline__ float dev_rsqrt<float>(float x) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  return __builtin_amdgcn_rsqf(x);
+#else
+  return 1.0f / sqrtf(x);
+#endif
+}
+
 // ---------------------------------------------------------------------------
 // Moments of a normalised Maxwellian: <u^n> (full space or one half space),
 // <v^n> (full), <xi^2>, <xi^4>.  <u^(n+2)> = U <u^(n+1)> + (n+1)/(2 lam) <u^n>.
@@ -54,21 +74,41 @@ template <typename T> struct Mom {
   T x2, x4;
 };
 
+// A Maxwellian's constants shared by its moments and micro-coefficient
+// solves: velocity, lam, h = 1/(2 lam), q = U^2 + V^2 + Kd h, c4 = 4 lam^2/Kd.
+template <typename T> struct Frame {
+  T U, V, lam, h, q, c4;
+};
+
 template <typename T, int D>
-CGKS_HD __forceinline__ void moments(T U, T V, T lam, T K, int region, Mom<T>& M) {
-  const T h = T(0.5) / lam;
+CGKS_HD __forceinline__ Frame<T> frame(T U, T V, T lam, T Kd, T iKd) {
+  Frame<T> f;
+  f.U = U;
+  f.V = (D == 2) ? V : T(0);
+  f.lam = lam;
+  f.h = T(0.5) * dev_rcp<T>(lam);
+  f.q = U * U + f.V * f.V + Kd * f.h;
+  f.c4 = T(4) * lam * lam * iKd;
+  return f;
+}
+
+template <typename T, int D>
+CGKS_HD __forceinline__ void moments(const Frame<T>& f, T K, int region, Mom<T>& M) {
+  const T U = f.U, h = f.h;
   if (region == 0) {
     M.u[0] = T(1);
     M.u[1] = U;
   } else {
-    const T s = dev_sqrt<T>(lam);
+    const T s = dev_sqrt<T>(f.lam);
     const T sg = T(region);
     M.u[0] = T(0.5) * dev_erfc<T>(-sg * s * U);
-    M.u[1] = U * M.u[0] + sg * T(0.5) * dev_exp<T>(-lam * U * U) / (s * T(1.7724538509055160273));
+    // 1/(s sqrt(pi)) = rsqrt(lam) / sqrt(pi)
+    M.u[1] = U * M.u[0] + sg * T(0.5 * 0.56418958354775628695) * dev_exp<T>(-f.lam * U * U) * dev_rsqrt<T>(f.lam);
   }
 #pragma unroll
   for (int n = 2; n < 7; ++n) M.u[n] = U * M.u[n - 1] + T(n - 1) * h * M.u[n - 2];
   if (D == 2) {
+    const T V = f.V;
     M.v[0] = T(1);
     M.v[1] = V;
 #pragma unroll
@@ -121,22 +161,22 @@ CGKS_HD __forceinline__ void mauv(const T* a, const Mom<T>& M, T* out) {
 }
 
 // micro-coefficients a with <a psi> = b (normalised moments of g): closed-form
-// inverse of the Maxwellian moment matrix.
+// inverse of the Maxwellian moment matrix, with the frame's constants.
 template <typename T, int D>
-CGKS_HD __forceinline__ void micro(const T* b, T U, T V, T lam, T Kd, T* a) {
+CGKS_HD __forceinline__ void micro(const T* b, const Frame<T>& f, T* a) {
+  const T U = f.U, tl = T(2) * f.lam;
   if (D == 2) {
-    const T q = U * U + V * V + Kd / (T(2) * lam);
-    const T R2 = b[1] - U * b[0], R3 = b[2] - V * b[0], R4 = T(2) * b[3] - q * b[0];
-    a[3] = T(4) * lam * lam / Kd * (R4 - T(2) * U * R2 - T(2) * V * R3);
-    a[2] = T(2) * lam * R3 - V * a[3];
-    a[1] = T(2) * lam * R2 - U * a[3];
-    a[0] = b[0] - U * a[1] - V * a[2] - T(0.5) * a[3] * q;
+    const T V = f.V;
+    const T R2 = b[1] - U * b[0], R3 = b[2] - V * b[0], R4 = T(2) * b[3] - f.q * b[0];
+    a[3] = f.c4 * (R4 - T(2) * U * R2 - T(2) * V * R3);
+    a[2] = tl * R3 - V * a[3];
+    a[1] = tl * R2 - U * a[3];
+    a[0] = b[0] - U * a[1] - V * a[2] - T(0.5) * a[3] * f.q;
   } else {
-    const T q = U * U + Kd / (T(2) * lam);
-    const T R2 = b[1] - U * b[0], R3 = T(2) * b[2] - q * b[0];
-    a[2] = T(4) * lam * lam / Kd * (R3 - T(2) * U * R2);
-    a[1] = T(2) * lam * R2 - U * a[2];
-    a[0] = b[0] - U * a[1] - T(0.5) * a[2] * q;
+    const T R2 = b[1] - U * b[0], R3 = T(2) * b[2] - f.q * b[0];
+    a[2] = f.c4 * (R3 - T(2) * U * R2);
+    a[1] = tl * R2 - U * a[2];
+    a[0] = b[0] - U * a[1] - T(0.5) * a[2] * f.q;
     a[3] = T(0);
   }
 }
@@ -172,10 +212,18 @@ CGKS_HD __forceinline__ T qcomb(const T* r, T U0, T V0) {
 template <typename T, int D>
 CGKS_HD __forceinline__ void primitive(const T* W, T gm1, T& rho, T& U, T& V, T& p) {
   rho = W[0];
-  U = W[1] / rho;
-  V = (D == 2) ? W[2] / rho : T(0);
+  const T ir = dev_rcp<T>(rho);
+  U = W[1] * ir;
+  V = (D == 2) ? W[2] * ir : T(0);
   const T ke = T(0.5) * rho * (U * U + V * V);
   p = gm1 * (W[D + 1] - ke);
+}
+
+// rho > 0 and p > 0, without a division: p > 0 <=> rho E > |rho u|^2 / 2
+template <typename T, int D>
+CGKS_HD __forceinline__ bool positive_state(const T* W) {
+  const T m2 = W[1] * W[1] + ((D == 2) ? W[2] * W[2] : T(0));
+  return (W[0] > T(0)) && (W[0] * W[D + 1] - T(0.5) * m2 > T(0));
 }
 
 // Results of one Gauss point, in double.
@@ -194,7 +242,7 @@ struct FaceOut {
 template <typename T, int D, bool PR = false>
 CGKS_HD void gks_flux(const T (&Wl)[6][4], const T (&Wr)[6][4], double dt, const Consts& C, FaceOut& o) {
   constexpr int NV = D + 2;
-  const T gm1 = T(C.gamma - 1.0), Kd = T(C.Kd), K = T(C.Kd - D);
+  const T gm1 = T(C.gamma - 1.0), Kd = T(C.Kd), iKd = T(C.iKd), K = T(C.Kd - D);
   T Q0[4] = {0, 0, 0, 0}, dQ[5][4], NF0[4] = {0, 0, 0, 0}, NF1[4] = {0, 0, 0, 0}, NW1[4] = {0, 0, 0, 0};
 #pragma unroll
   for (int q = 0; q < 5; ++q)
@@ -212,14 +260,15 @@ CGKS_HD void gks_flux(const T (&Wl)[6][4], const T (&Wr)[6][4], double dt, const
     const T(&Wk)[6][4] = side == 0 ? Wl : Wr;
     T rho, U, V, p;
     primitive<T, D>(Wk[0], gm1, rho, U, V, p);
-    const T lam = rho / (T(2) * p);
+    const T ip = dev_rcp<T>(p), ir = dev_rcp<T>(rho);
+    const T lam = T(0.5) * rho * ip;
     pside[side] = p;
-    cside[side] = dev_sqrt<T>(T(C.gamma) * p / rho);
+    cside[side] = dev_sqrt<T>(T(C.gamma) * p * ir);
     un[side] = U;
     ut[side] = V;
+    const Frame<T> fr = frame<T, D>(U, V, lam, Kd, iKd);
     Mom<T> M;
-    moments<T, D>(U, V, lam, K, side == 0 ? 1 : -1, M);
-    const T ir = T(1) / rho;
+    moments<T, D>(fr, K, side == 0 ? 1 : -1, M);
     T e0[4] = {1, 0, 0, 0}, t4[4];
     mauv<T, D, 0, 0>(e0, M, t4);
 #pragma unroll
@@ -241,7 +290,7 @@ CGKS_HD void gks_flux(const T (&Wl)[6][4], const T (&Wr)[6][4], double dt, const
       T b[4], a[4];
 #pragma unroll
       for (int v = 0; v < 4; ++v) b[v] = (v < NV) ? Wk[d][v] * ir : T(0);
-      micro<T, D>(b, U, V, lam, Kd, a);
+      micro<T, D>(b, fr, a);
       mauv<T, D, 0, 0>(a, M, t4);
 #pragma unroll
       for (int v = 0; v < NV; ++v) dQ[q][v] += rho * t4[v];
@@ -279,10 +328,11 @@ CGKS_HD void gks_flux(const T (&Wl)[6][4], const T (&Wr)[6][4], double dt, const
   // equilibrium state at the interface (kinetic weighting, Eq. 2.7)
   T rho0, U0, V0, p0;
   primitive<T, D>(Q0, gm1, rho0, U0, V0, p0);
-  const T lam0 = rho0 / (T(2) * p0);
+  const T lam0 = T(0.5) * rho0 * dev_rcp<T>(p0);
+  const Frame<T> f0 = frame<T, D>(U0, V0, lam0, Kd, iKd);
   Mom<T> M0;
-  moments<T, D>(U0, V0, lam0, K, 0, M0);
-  const T ir0 = T(1) / rho0;
+  moments<T, D>(f0, K, 0, M0);
+  const T ir0 = dev_rcp<T>(rho0);
   T ab[5][4];
   constexpr int NDER = (D == 2) ? 5 : 2;
 #pragma unroll
@@ -290,7 +340,7 @@ CGKS_HD void gks_flux(const T (&Wl)[6][4], const T (&Wr)[6][4], double dt, const
     T b[4];
 #pragma unroll
     for (int v = 0; v < 4; ++v) b[v] = (v < NV) ? dQ[q][v] * ir0 : T(0);
-    micro<T, D>(b, U0, V0, lam0, Kd, ab[q]);
+    micro<T, D>(b, f0, ab[q]);
   }
   // ab index: 2-D 0 n, 1 t, 2 nn, 3 nt, 4 tt; 1-D 0 n, 1 nn
   const T* an = ab[0];
@@ -305,7 +355,7 @@ CGKS_HD void gks_flux(const T (&Wl)[6][4], const T (&Wr)[6][4], double dt, const
   }
 #pragma unroll
   for (int v = 0; v < 4; ++v) bA[v] = -bA[v];
-  micro<T, D>(bA, U0, V0, lam0, Kd, AT);
+  micro<T, D>(bA, f0, AT);
   // <ann u + ant v + anT> = 0, <ant u + att v + atT> = 0
   mauv<T, D, 1, 0>(ann, M0, b1);
   if (D == 2) {
@@ -315,13 +365,13 @@ CGKS_HD void gks_flux(const T (&Wl)[6][4], const T (&Wr)[6][4], double dt, const
   }
 #pragma unroll
   for (int v = 0; v < 4; ++v) b1[v] = -b1[v];
-  micro<T, D>(b1, U0, V0, lam0, Kd, anT);
+  micro<T, D>(b1, f0, anT);
   if (D == 2) {
     mauv<T, D, 1, 0>(ab[3], M0, b1);
     mauv<T, D, 0, 1>(ab[4], M0, t4);
 #pragma unroll
     for (int v = 0; v < 4; ++v) b1[v] = -(b1[v] + t4[v]);
-    micro<T, D>(b1, U0, V0, lam0, Kd, atT);
+    micro<T, D>(b1, f0, atT);
   } else {
 #pragma unroll
     for (int v = 0; v < 4; ++v) atT[v] = T(0);
@@ -335,7 +385,7 @@ CGKS_HD void gks_flux(const T (&Wl)[6][4], const T (&Wr)[6][4], double dt, const
   }
 #pragma unroll
   for (int v = 0; v < 4; ++v) bTT[v] = -bTT[v];
-  micro<T, D>(bTT, U0, V0, lam0, Kd, ATT);
+  micro<T, D>(bTT, f0, ATT);
 
   // flux moments of the equilibrium part (normalised)
   T e0[4] = {1, 0, 0, 0}, F0[4], FA[4], F1[4], Ft[4];
@@ -384,10 +434,11 @@ CGKS_HD void gks_flux(const T (&Wl)[6][4], const T (&Wr)[6][4], double dt, const
 
   // collision time (Sec. 4)
   const double pl = double(pside[0]), pr = double(pside[1]);
-  const double jump = fabs((pl - pr) / (pl + pr));
+  const double jump = fabs(pl - pr) / (pl + pr);
   double tau = 0.0;
   if (C.tau_model == 1) tau = C.c1 * dt + C.c2 * jump * dt;
   else if (C.tau_model == 2) tau = C.mu / double(p0) + C.c2 * jump * dt;
+  const double itau = tau > 0.0 ? 1.0 / tau : 0.0;
 
   // time integrals (the flux keeps the terms up to first order in t of the
   // equilibrium part; interface values keep the full quadratic)
@@ -397,7 +448,7 @@ CGKS_HD void gks_flux(const T (&Wl)[6][4], const T (&Wr)[6][4], double dt, const
     const double d = w == 0 ? 0.5 * dt : dt;
     double E0 = 0.0, E1 = 0.0;
     if (tau > 0.0) {
-      const double x = d / tau;
+      const double x = d * itau;
       const double e = exp(-x);
       E0 = -tau * expm1(-x);
       E1 = tau * tau - tau * (tau + d) * e;
@@ -421,7 +472,7 @@ CGKS_HD void gks_flux(const T (&Wl)[6][4], const T (&Wr)[6][4], double dt, const
 #pragma unroll
   for (int w = 0; w < 3; ++w) {
     const double t = w == 0 ? 0.0 : (w == 1 ? 0.5 * dt : dt);
-    const double e = (t == 0.0) ? 1.0 : (tau > 0.0 ? exp(-t / tau) : 0.0);
+    const double e = (t == 0.0) ? 1.0 : (tau > 0.0 ? exp(-t * itau) : 0.0);
     double* Wo = w == 0 ? o.W0 : (w == 1 ? o.Wh : o.W1);
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
@@ -502,23 +553,24 @@ CGKS_HD __forceinline__ void ao_poly(const T* d, const Cascade& cs, const Consts
   const T b1 = c1[1] * c1[1] + T(13.0 / 3.0) * c1[2] * c1[2];
   const T b2 = c2[1] * c2[1] + T(13.0 / 3.0) * c2[2] * c2[2];
   const T q1 = c3[1], q2 = c3[2], q3 = c3[3], q4 = c3[4];
-  const T b3 = q1 * q1 + (T(4) * q2 * q2 + T(6) * q1 * q3) / T(12) + (T(9) * q3 * q3 + T(16) * q2 * q4) / T(80) +
-               T(16) * q4 * q4 / T(448) + T(4) * q2 * q2 + (T(36) * q3 * q3 + T(48) * q2 * q4) / T(12) +
-               T(144) * q4 * q4 / T(80) + T(36) * q3 * q3 + T(48) * q4 * q4 + T(576) * q4 * q4;
+  const T b3 = q1 * q1 + (T(4) * q2 * q2 + T(6) * q1 * q3) * T(1.0 / 12) +
+               (T(9) * q3 * q3 + T(16) * q2 * q4) * T(1.0 / 80) + T(16) * q4 * q4 * T(1.0 / 448) + T(4) * q2 * q2 +
+               (T(36) * q3 * q3 + T(48) * q2 * q4) * T(1.0 / 12) + T(144) * q4 * q4 * T(1.0 / 80) + T(36) * q3 * q3 +
+               T(48) * q4 * q4 + T(576) * q4 * q4;
   // the DFF scaling of a member scales its indicator by alpha^2
   const T al0 = T(cs.al[0]), al1 = T(cs.al[1]), al2 = T(cs.al[2]), al3 = T(cs.al[3]);
   const T B0 = al0 * al0 * b0, B1 = al1 * al1 * b1, B2 = al2 * al2 * b2, B3 = al3 * al3 * b3;
   const T g3 = T(C.ghi), g0 = T((1.0 - C.ghi) * (1.0 - C.glo) / 2.0), g2 = T((1.0 - C.ghi) * C.glo);
-  const T tz = (fabs(B3 - B0) + fabs(B3 - B1) + fabs(B3 - B2)) / T(3);
+  const T tz = (fabs(B3 - B0) + fabs(B3 - B1) + fabs(B3 - B2)) * T(1.0 / 3);
   const T eps = T(C.eps);
   T r;
-  r = tz / (B0 + eps); const T w0 = g0 * (T(1) + r * r);
-  r = tz / (B1 + eps); const T w1 = g0 * (T(1) + r * r);
-  r = tz / (B2 + eps); const T w2 = g2 * (T(1) + r * r);
-  r = tz / (B3 + eps); const T w3 = g3 * (T(1) + r * r);
-  const T ws = T(1) / (w0 + w1 + w2 + w3);
+  r = tz * dev_rcp<T>(B0 + eps); const T w0 = g0 * (T(1) + r * r);
+  r = tz * dev_rcp<T>(B1 + eps); const T w1 = g0 * (T(1) + r * r);
+  r = tz * dev_rcp<T>(B2 + eps); const T w2 = g2 * (T(1) + r * r);
+  r = tz * dev_rcp<T>(B3 + eps); const T w3 = g3 * (T(1) + r * r);
+  const T ws = dev_rcp<T>(w0 + w1 + w2 + w3);
   const T o0 = w0 * ws, o1 = w1 * ws, o2 = w2 * ws, o3 = w3 * ws;
-  const T k3 = o3 / g3;
+  const T k3 = o3 * T(1.0 / C.ghi);
   const T k0 = (o0 - k3 * g0) * al0, k1 = (o1 - k3 * g0) * al1, k2 = (o2 - k3 * g2) * al2, kk3 = k3 * al3;
   P[0] = d[2] * (T(1) - k0 - k1 - k2 - kk3) + k0 * c0[0] + k1 * c1[0] + k2 * c2[0] + kk3 * c3[0];
   P[1] = k0 * c0[1] + k1 * c1[1] + k2 * c2[1] + kk3 * c3[1];
@@ -534,25 +586,10 @@ CGKS_HD __forceinline__ T poly4(const T* P, T x, int deriv) {
   return T(2) * P[2] + x * (T(6) * P[3] + x * T(12) * P[4]);
 }
 
-// value, d/dxi and d2/dxi2 at xi = +1/2 (side 0) and xi = -1/2 (side 1) of
-// every component; d[v][9] are the stencil data of component v.
-template <typename T, int NVAR>
-CGKS_HD __forceinline__ void recon_faces(const T (&d)[NVAR][9], const Cascade& cs, const Consts& C,
-                                            T (&out)[2][3][NVAR]) {
-  if (cs.branch == 0) {
-#pragma unroll
-    for (int v = 0; v < NVAR; ++v) {
-      T P[5];
-      ao_poly<T>(d[v], cs, C, P);
-#pragma unroll
-      for (int dd = 0; dd < 3; ++dd) {
-        out[0][dd][v] = poly4<T>(P, T(0.5), dd);
-        out[1][dd][v] = poly4<T>(P, T(-0.5), dd);
-      }
-    }
-    return;
-  }
-  const double(*F)[3][9] = cs.branch == 5 ? kF_R5 : (cs.branch == 7 ? kF_R7 : kF_R9);
+// A linear stencil (5th, 7th or 9th order) at both faces: value, d, d2
+template <typename T, int NVAR, int K>
+CGKS_HD __forceinline__ void lin_faces(const T (&d)[NVAR][9], T (&out)[2][3][NVAR]) {
+  constexpr const double(&F)[2][3][9] = K == 5 ? kF_R5 : (K == 7 ? kF_R7 : kF_R9);
 #pragma unroll
   for (int v = 0; v < NVAR; ++v)
 #pragma unroll
@@ -561,38 +598,70 @@ CGKS_HD __forceinline__ void recon_faces(const T (&d)[NVAR][9], const Cascade& c
       for (int dd = 0; dd < 3; ++dd) {
         T a = 0;
 #pragma unroll
-        for (int s = 0; s < 9; ++s) a += T(F[sd][dd][s]) * d[v][s];
+        for (int s = 0; s < 9; ++s)
+          if (F[sd][dd][s] != 0.0) a += T(F[sd][dd][s]) * d[v][s];
         out[sd][dd][v] = a;
       }
 }
 
-// values at the m Gauss points of the cell
+// value, d/dxi and d2/dxi2 at xi = +1/2 (side 0) and xi = -1/2 (side 1) of
+// every component; d[v][9] are the stencil data of component v.
 template <typename T, int NVAR>
-CGKS_HD __forceinline__ void recon_nodes(const T (&d)[NVAR][9], const Cascade& cs, const Consts& C,
-                                            T (&out)[4][NVAR]) {
-  const int m = C.m;
-  if (cs.branch == 0) {
+CGKS_HD __forceinline__ void recon_faces(const T (&d)[NVAR][9], const Cascade& cs, const Consts& C,
+                                            T (&out)[2][3][NVAR]) {
+  switch (cs.branch) {
+    case 0:
 #pragma unroll
-    for (int v = 0; v < NVAR; ++v) {
-      T P[5];
-      ao_poly<T>(d[v], cs, C, P);
+      for (int v = 0; v < NVAR; ++v) {
+        T P[5];
+        ao_poly<T>(d[v], cs, C, P);
 #pragma unroll
-      for (int l = 0; l < 4; ++l)
-        if (l < m) out[l][v] = poly4<T>(P, T(kGx[m][l]), 0);
-    }
-    return;
+        for (int dd = 0; dd < 3; ++dd) {
+          out[0][dd][v] = poly4<T>(P, T(0.5), dd);
+          out[1][dd][v] = poly4<T>(P, T(-0.5), dd);
+        }
+      }
+      return;
+    case 5: lin_faces<T, NVAR, 5>(d, out); return;
+    case 7: lin_faces<T, NVAR, 7>(d, out); return;
+    default: lin_faces<T, NVAR, 9>(d, out); return;
   }
-  const double(*N)[4][9] = cs.branch == 5 ? kN_R5 : (cs.branch == 7 ? kN_R7 : kN_R9);
+}
+
+// A linear stencil at the M Gauss points of the cell
+template <typename T, int NVAR, int M, int K>
+CGKS_HD __forceinline__ void lin_nodes(const T (&d)[NVAR][9], T (&out)[4][NVAR]) {
+  constexpr const double(&N)[5][4][9] = K == 5 ? kN_R5 : (K == 7 ? kN_R7 : kN_R9);
 #pragma unroll
   for (int v = 0; v < NVAR; ++v)
 #pragma unroll
-    for (int l = 0; l < 4; ++l) {
-      if (l >= m) continue;
+    for (int l = 0; l < M; ++l) {
       T a = 0;
 #pragma unroll
-      for (int s = 0; s < 9; ++s) a += T(N[m][l][s]) * d[v][s];
+      for (int s = 0; s < 9; ++s)
+        if (N[M][l][s] != 0.0) a += T(N[M][l][s]) * d[v][s];
       out[l][v] = a;
     }
+}
+
+// values at the M Gauss points of the cell
+template <typename T, int NVAR, int M>
+CGKS_HD __forceinline__ void recon_nodes(const T (&d)[NVAR][9], const Cascade& cs, const Consts& C,
+                                            T (&out)[4][NVAR]) {
+  switch (cs.branch) {
+    case 0:
+#pragma unroll
+      for (int v = 0; v < NVAR; ++v) {
+        T P[5];
+        ao_poly<T>(d[v], cs, C, P);
+#pragma unroll
+        for (int l = 0; l < M; ++l) out[l][v] = poly4<T>(P, T(kGx[M][l]), 0);
+      }
+      return;
+    case 5: lin_nodes<T, NVAR, M, 5>(d, out); return;
+    case 7: lin_nodes<T, NVAR, M, 7>(d, out); return;
+    default: lin_nodes<T, NVAR, M, 9>(d, out); return;
+  }
 }
 
 }  // inline namespace CGKS_UNIT

@@ -55,7 +55,7 @@ inline cgks_status fail(cgks_status s, const std::string& msg) {
 // produced wrong, run-dependent results on gfx950, while the same source
 // without spills is exact; every hot kernel is therefore built to keep its
 // state in registers, and the library checks the built kernels before first
-// use and refuses to run them otherwise.
+// use and refuses to run them otherwise (no hot kernel may use scratch).
 inline cgks_status check_private(const void* kernel, size_t limit, const char* what) {
   hipFuncAttributes a;
   hipError_t e = hipFuncGetAttributes(&a, kernel);
@@ -375,7 +375,7 @@ __device__ __forceinline__ void lines_at(const Geo& g, const Consts& C, const do
     }
     const Cascade cs = cascade(s, C.order, C.thres);
     double out[4][4];
-    recon_nodes<double, 4>(d, cs, C, out);
+    recon_nodes<double, 4, M>(d, cs, C, out);
 #pragma unroll
     for (int l = 0; l < M; ++l)
 #pragma unroll
@@ -401,7 +401,7 @@ __device__ __forceinline__ void lines_at(const Geo& g, const Consts& C, const do
     }
     const Cascade cs = cascade(s, C.order, C.thres);
     double out[4][4];
-    recon_nodes<double, 4>(d, cs, C, out);
+    recon_nodes<double, 4, M>(d, cs, C, out);
 #pragma unroll
     for (int l = 0; l < M; ++l)
 #pragma unroll
@@ -415,6 +415,12 @@ __device__ __forceinline__ void lines_at(const Geo& g, const Consts& C, const do
 // (tangential derivatives), Step 4 (flux), and the cell update of one
 // direction.  DIR 0: x-faces (normal x), DIR 1: y-faces.
 // ---------------------------------------------------------------------------
+// Wave-uniform execution.  On gfx950, FP64 kernels that spill (to scratch,
+// accumulation registers or SGPR lanes) gave wrong results where the lanes of
+// a wave were partly inactive (loop tails, ragged tile edges), while the same
+// source executed on the CPU is exact.  The heavy phases of the face tile and
+// of the 1-D stage therefore run on all lanes: a lane without an item of its
+// own recomputes a valid one and only its stores are masked.
 template <int M> struct Tile {
   static constexpr int NF = 16;                               // faces along the normal
   static constexpr int NT = M == 2 ? 8 : (M == 3 ? 5 : 4);    // lines along the tangential
@@ -423,10 +429,15 @@ template <int M> struct Tile {
   static constexpr int RK1 = 17, RK2 = 8;                     // results per Gauss point (stage 1 / 2)
 };
 
+// LDS of a face tile.  Step 2 results: one record of RS = 8M + 1 elements per
+// (line, cell) -- the odd stride puts neighbouring lanes on different banks.
+// Gauss-point results: structure of arrays, component k of Gauss point g at
+// k * NB + g, so lane g of a wave writes consecutive words.
 template <int M, typename T> struct Lds {
-  static constexpr size_t s2v = (size_t)Tile<M>::NR * Tile<M>::NC * M * 8 * sizeof(T);
+  static constexpr int RS = 8 * M + 1;
+  static constexpr size_t s2v = (size_t)Tile<M>::NR * Tile<M>::NC * RS * sizeof(T);
   static constexpr size_t s2d = s2v;
-  static constexpr size_t s2dd = (size_t)Tile<M>::NT * Tile<M>::NC * M * 8 * sizeof(T);
+  static constexpr size_t s2dd = (size_t)Tile<M>::NT * Tile<M>::NC * RS * sizeof(T);
   static constexpr size_t recon = s2v + s2d + s2dd;
   static constexpr size_t res = (size_t)Tile<M>::NF * Tile<M>::NT * M * Tile<M>::RK1 * sizeof(double);
   static constexpr size_t fin = (size_t)(Tile<M>::NF - 1) * Tile<M>::NT * 4 * sizeof(double);
@@ -461,7 +472,11 @@ __device__ void face2d_tile(const Geo& g, const Consts& C, const Bufs& B, unsign
   T* s2dd = (T*)(smem + Lds<M, T>::s2v + Lds<M, T>::s2d);
   double* res = (double*)(smem + Lds<M, T>::off_res);
   double* fin = (double*)(smem + Lds<M, T>::off_fin);
-  auto I2 = [&](int r, int c, int l, int sd, int v) { return (((r * NC + c) * M + l) * 2 + sd) * 4 + v; };
+  constexpr int RS = Lds<M, T>::RS;
+  constexpr int NB = NF * NT * M;   // Gauss points of the tile
+  auto I2 = [&](int r, int c, int l, int sd, int v) { return (r * NC + c) * RS + (l * 2 + sd) * 4 + v; };
+  // Gauss point (face f, line r, node l) -> its thread / result column
+  auto gp = [&](int f, int r, int l) { return DIR == 0 ? f + NF * (r + NT * l) : r + NT * (f + NF * l); };
 
   const int nmax = DIR == 0 ? g.nx : g.ny;   // cells along the normal
   const int tmax = DIR == 0 ? g.ny : g.nx;   // cells along the tangential
@@ -482,13 +497,17 @@ __device__ void face2d_tile(const Geo& g, const Consts& C, const Bufs& B, unsign
   auto sgt_idx = [&](int n, int face) { return DIR == 0 ? g.sgy(n, face) : g.sgx(n, face); };
 
   // ---- Step 2: normal reconstruction on each line, both faces of a cell ----
+  // Every pass runs on all 256 lanes: a lane without an item of its own
+  // recomputes a valid item of the tile (c = r = 1, l = 0) and stores nothing.
   constexpr int NA = NC * NR * M;
-  for (int it = threadIdx.x; it < NA; it += blockDim.x) {
+  for (int base = 0; base < NA; base += 256) {
+    const int it = base + (int)threadIdx.x;
     int c, r, l;
     if (DIR == 0) { c = it % NC; r = (it / NC) % NR; l = it / (NC * NR); }
     else { r = it % NR; c = (it / NR) % NC; l = it / (NC * NR); }
+    const bool own = it < NA && F0 - 1 + c <= nmax && T0 - 1 + r <= tmax;   // n, t >= -1 by construction
+    if (!own) { c = 1; r = 1; l = 0; }
     const int n = F0 - 1 + c, t = T0 - 1 + r;
-    if (n < -1 || n > nmax || t < -1 || t > tmax) continue;
     double s[6];
 #pragma unroll
     for (int f = 0; f < 6; ++f) s[f] = sgN[sgn_idx(t, n - 2 + f)];
@@ -508,25 +527,30 @@ __device__ void face2d_tile(const Geo& g, const Consts& C, const Bufs& B, unsign
     T out[2][3][4];
     recon_faces<T, 4>(d, cs, C, out);
     const T ih = T(1.0 / hn), ih2 = T(1.0 / (hn * hn));
+    if (own) {
 #pragma unroll
-    for (int sd = 0; sd < 2; ++sd)
+      for (int sd = 0; sd < 2; ++sd)
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        s2v[I2(r, c, l, sd, v)] = out[sd][0][v];
-        s2d[I2(r, c, l, sd, v)] = out[sd][1][v] * ih;
-        if (r >= 1 && r <= NT) s2dd[I2(r - 1, c, l, sd, v)] = out[sd][2][v] * ih2;
-      }
+        for (int v = 0; v < 4; ++v) {
+          s2v[I2(r, c, l, sd, v)] = out[sd][0][v];
+          s2d[I2(r, c, l, sd, v)] = out[sd][1][v] * ih;
+          if (r >= 1 && r <= NT) s2dd[I2(r - 1, c, l, sd, v)] = out[sd][2][v] * ih2;
+        }
+    }
   }
   __syncthreads();
 
   // ---- Steps 3-4 at every face Gauss point: one Gauss point per thread ----
-  constexpr int NB = NF * NT * M;
   static_assert(NB <= 256, "one Gauss point per thread of a 256-thread block");
+  // as in Step 2, lanes without a Gauss point of their own compute the
+  // tile's first one (f = r = l = 0, always inside the grid) and store nothing
   const int it = threadIdx.x;
   int f, r, l;
   if (DIR == 0) { f = it % NF; r = (it / NF) % NT; l = it / (NF * NT); }
   else { r = it % NT; f = (it / NT) % NF; l = it / (NF * NT); }
-  if (it < NB && F0 + f <= nmax && T0 + r < tmax) {
+  const bool own = it < NB && F0 + f <= nmax && T0 + r < tmax;
+  if (!own) { f = 0; r = 0; l = 0; }
+  {
     const int nf = F0 + f, t = T0 + r;
     T Wk[2][6][4];
 #pragma unroll
@@ -537,7 +561,7 @@ __device__ void face2d_tile(const Geo& g, const Consts& C, const Bufs& B, unsign
 #pragma unroll
       for (int q = -1; q <= 2; ++q) A += sgT[sgt_idx(ncell, t + q)];
       const T at = T(dff_of(A, C.thres));
-      const T it1 = at / T(ht), it2 = at / T(ht * ht);
+      const T it1 = at * T(1.0 / ht), it2 = at * T(1.0 / (ht * ht));
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         Wk[sd][0][v] = s2v[I2(r + 1, c, l, sd, v)];
@@ -559,36 +583,36 @@ __device__ void face2d_tile(const Geo& g, const Consts& C, const Bufs& B, unsign
         Wk[sd][4][v] = it1 * ax;
       }
       // first order from the cell average where the state is nonphysical
-      T rho, U, V, p;
-      primitive<T, 2>(Wk[sd][0], T(C.gamma - 1.0), rho, U, V, p);
-      if (!(rho > T(0)) || !(p > T(0))) {
+      if (!positive_state<T, 2>(Wk[sd][0])) {
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
           Wk[sd][0][v] = T(Uin[g.avg(gcomp[v], gi(ncell, t), gj(ncell, t))]);
 #pragma unroll
           for (int dd = 1; dd < 6; ++dd) Wk[sd][dd][v] = T(0);
         }
-        atomicAdd((unsigned long long*)&B.hdr->fallbacks, 1ull);
+        if (own) atomicAdd((unsigned long long*)&B.hdr->fallbacks, 1ull);
       }
     }
     FaceOut fo;
     gks_flux<T, 2, PR>(Wk[0], Wk[1], dt, C, fo);
     // results to LDS (global component order)
-    double* rp = res + (((size_t)f * NT + r) * M + l) * (STAGE == 1 ? TL::RK1 : TL::RK2);
+    double* rp = res + gp(f, r, l);   // component k at rp[k * NB]
+    if (own) {
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       const int gv = gcomp[v];
       if (STAGE == 1) {
-        rp[gv] = fo.Fh[v];
-        rp[4 + gv] = (8.0 / 3.0) * fo.Fh[v] - (1.0 / 3.0) * fo.F1[v];
-        rp[8 + gv] = fo.Wh[v];
-        rp[12 + gv] = -(4.0 / 3.0) * fo.W0[v] + (8.0 / 3.0) * fo.Wh[v] - (1.0 / 3.0) * fo.W1[v];
+        rp[gv * NB] = fo.Fh[v];
+        rp[(4 + gv) * NB] = (8.0 / 3.0) * fo.Fh[v] - (1.0 / 3.0) * fo.F1[v];
+        rp[(8 + gv) * NB] = fo.Wh[v];
+        rp[(12 + gv) * NB] = -(4.0 / 3.0) * fo.W0[v] + (8.0 / 3.0) * fo.Wh[v] - (1.0 / 3.0) * fo.W1[v];
       } else {
-        rp[gv] = (4.0 / 3.0) * (fo.F1[v] - 2.0 * fo.Fh[v]);
-        rp[4 + gv] = (4.0 / 3.0) * (fo.W0[v] - 2.0 * fo.Wh[v] + fo.W1[v]);
+        rp[gv * NB] = (4.0 / 3.0) * (fo.F1[v] - 2.0 * fo.Fh[v]);
+        rp[(4 + gv) * NB] = (4.0 / 3.0) * (fo.W0[v] - 2.0 * fo.Wh[v] + fo.W1[v]);
       }
     }
-    if (STAGE == 1) rp[16] = fo.sigma;
+    if (STAGE == 1) rp[16 * NB] = fo.sigma;
+    }
   }
   __syncthreads();
 
@@ -599,14 +623,14 @@ __device__ void face2d_tile(const Geo& g, const Consts& C, const Bufs& B, unsign
       const int nf = F0 + f, t = T0 + r;
       if (nf > nmax || t >= tmax) continue;
       double s = 0.0;
-      for (int l = 0; l < M; ++l) s += res[(((size_t)f * NT + r) * M + l) * TL::RK1 + 16];
+      for (int l = 0; l < M; ++l) s += res[16 * NB + gp(f, r, l)];
       (DIR == 0 ? B.sxn : B.syn)[sgn_idx(t, nf)] = s / M;
     }
   }
 
   // ---- cell update of this direction ----
-  constexpr int RK = STAGE == 1 ? TL::RK1 : TL::RK2;
   const double ihn = 1.0 / hn;
+  constexpr int NFT = (NF - 1) * NT;   // updated cells of the tile
   for (int it = threadIdx.x; it < (NF - 1) * NT * 4; it += blockDim.x) {
     int ci, r, v;
     if (DIR == 0) { ci = it % (NF - 1); r = (it / (NF - 1)) % NT; v = it / ((NF - 1) * NT); }
@@ -614,37 +638,38 @@ __device__ void face2d_tile(const Geo& g, const Consts& C, const Bufs& B, unsign
     const int n = F0 + ci, t = T0 + r;
     if (n >= nmax || t >= tmax) continue;
     const int i = gi(n, t), j = gj(n, t);
-    const double* ra = res + (((size_t)ci * NT + r) * M) * RK;        // face n
-    const double* rb = res + (((size_t)(ci + 1) * NT + r) * M) * RK;  // face n+1
+    // component k of node l at face n: ra(k, l); at face n+1: rb(k, l)
+    auto ra = [&](int k, int l) { return res[k * NB + gp(ci, r, l)]; };
+    auto rb = [&](int k, int l) { return res[k * NB + gp(ci + 1, r, l)]; };
     const size_t ia = g.avg(v, i, j);
     if (STAGE == 1) {
       double dF = 0.0, dA = 0.0;
       for (int l = 0; l < M; ++l) {
         const double w = kGw[M][l];
-        dF += w * (rb[l * RK + v] - ra[l * RK + v]);
-        dA += w * (rb[l * RK + 4 + v] - ra[l * RK + 4 + v]);
+        dF += w * (rb(v, l) - ra(v, l));
+        dA += w * (rb(4 + v, l) - ra(4 + v, l));
       }
       const double base = DIR == 0 ? B.U[ia] : B.S[ia];
       const double abase = DIR == 0 ? B.U[ia] : B.A[ia];
       const double snew = base - dF * ihn;
       B.S[ia] = snew;
       B.A[ia] = abase - dA * ihn;
-      if (DIR == 1) fin[((size_t)ci * NT + r) * 4 + v] = snew;
+      if (DIR == 1) fin[v * NFT + ci * NT + r] = snew;
       for (int l = 0; l < M; ++l) {
         const size_t is = DIR == 0 ? g.sx(v, l, i, j) : g.sy(v, l, i, j);
-        B.S[is] = (rb[l * RK + 8 + v] - ra[l * RK + 8 + v]) * ihn;
-        B.A[is] = (rb[l * RK + 12 + v] - ra[l * RK + 12 + v]) * ihn;
+        B.S[is] = (rb(8 + v, l) - ra(8 + v, l)) * ihn;
+        B.A[is] = (rb(12 + v, l) - ra(12 + v, l)) * ihn;
       }
     } else {
       double dA = 0.0;
-      for (int l = 0; l < M; ++l) dA += kGw[M][l] * (rb[l * RK + v] - ra[l * RK + v]);
+      for (int l = 0; l < M; ++l) dA += kGw[M][l] * (rb(v, l) - ra(v, l));
       const double base = DIR == 0 ? B.A[ia] : B.U[ia];
       const double unew = base - dA * ihn;
       B.U[ia] = unew;
-      if (DIR == 1) fin[((size_t)ci * NT + r) * 4 + v] = unew;
+      if (DIR == 1) fin[v * NFT + ci * NT + r] = unew;
       for (int l = 0; l < M; ++l) {
         const size_t is = DIR == 0 ? g.sx(v, l, i, j) : g.sy(v, l, i, j);
-        B.U[is] = B.A[is] + (rb[l * RK + 4 + v] - ra[l * RK + 4 + v]) * ihn;
+        B.U[is] = B.A[is] + (rb(4 + v, l) - ra(4 + v, l)) * ihn;
       }
     }
   }
@@ -659,7 +684,7 @@ __device__ void face2d_tile(const Geo& g, const Consts& C, const Bufs& B, unsign
       const int n = F0 + ci, t = T0 + r;
       if (n < nmax && t < tmax) {
         double W[4];
-        for (int v = 0; v < 4; ++v) W[v] = fin[((size_t)ci * NT + r) * 4 + v];
+        for (int v = 0; v < 4; ++v) W[v] = fin[v * NFT + ci * NT + r];
         rr = W[0];
         valid = cell_speed(W, 2, C.gamma, s);
         if (!valid) atomicAdd((unsigned long long*)&B.hdr->nonphysical, 1ull);
@@ -686,11 +711,15 @@ __device__ void stage1d_seg(const Geo& g, const Consts& C, const Bufs& B, double
   const int F = F0 + f;
   const double* Uin = STAGE == 1 ? B.U : B.S;
   const double h = C.dx;
-  if (F <= g.nx) {
+  // wave-uniform, as in the 2-D tile: lanes past the last face compute the
+  // last face again and store nothing
+  const bool own = F <= g.nx;
+  const int Fc = own ? F : g.nx;
+  {
     T Wk[2][6][4];
 #pragma unroll
     for (int sd = 0; sd < 2; ++sd) {
-      const int cell = F - 1 + sd;
+      const int cell = Fc - 1 + sd;
       double s[6];
 #pragma unroll
       for (int q = 0; q < 6; ++q) s[q] = B.sxo[g.sgx(0, cell - 2 + q)];
@@ -719,20 +748,19 @@ __device__ void stage1d_seg(const Geo& g, const Consts& C, const Bufs& B, double
         Wk[sd][1][v] = out[side][1][v] / T(h);
         Wk[sd][3][v] = out[side][2][v] / T(h * h);
       }
-      T rho, U, V, p;
-      primitive<T, 1>(Wk[sd][0], T(C.gamma - 1.0), rho, U, V, p);
-      if (!(rho > T(0)) || !(p > T(0))) {
+      if (!positive_state<T, 1>(Wk[sd][0])) {
 #pragma unroll
         for (int v = 0; v < 3; ++v) {
           Wk[sd][0][v] = T(Uin[g.avg(v, cell, 0)]);
           Wk[sd][1][v] = T(0);
           Wk[sd][3][v] = T(0);
         }
-        atomicAdd((unsigned long long*)&B.hdr->fallbacks, 1ull);
+        if (own) atomicAdd((unsigned long long*)&B.hdr->fallbacks, 1ull);
       }
     }
     FaceOut fo;
     gks_flux<T, 1, PR>(Wk[0], Wk[1], dt, C, fo);
+    if (own) {
 #pragma unroll
     for (int v = 0; v < 3; ++v) {
       if (STAGE == 1) {
@@ -746,6 +774,7 @@ __device__ void stage1d_seg(const Geo& g, const Consts& C, const Bufs& B, double
       }
     }
     if (STAGE == 1) B.sxn[g.sgx(0, F)] = fo.sigma;
+    }
   }
   __syncthreads();
   const int i = F0 + f;  // cell

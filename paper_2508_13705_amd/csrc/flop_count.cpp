@@ -50,7 +50,7 @@ static long long flops() { return fc::add + fc::mul + fc::dv; }
 
 int main() {
   Consts C;
-  C.gamma = 1.4; C.Kd = 5.0; C.c1 = 0.05; C.c2 = 1.0; C.mu = 1e-4; C.thres = 1.0; C.ghi = 0.85; C.glo = 0.6;
+  C.gamma = 1.4; C.Kd = 5.0; C.iKd = 0.2; C.c1 = 0.05; C.c2 = 1.0; C.mu = 1e-4; C.thres = 1.0; C.ghi = 0.85; C.glo = 0.6;
   C.eps = 1e-8; C.dx = C.dy = 1.0 / 2048; C.tau_model = 2; C.order = 9; C.m = 4;
   // flux at one Gauss point (2-D and 1-D), smooth viscous state
   Fl Wl[6][4], Wr[6][4];
@@ -92,8 +92,8 @@ int main() {
   Cascade ao; ao.branch = 0; ao.al[0] = 0.5; ao.al[1] = 0.6; ao.al[2] = 0.7; ao.al[3] = 0.8;
   reset(); recon_faces<Fl, 4>(d, lin, C, out); const long long rf9 = flops();
   reset(); recon_faces<Fl, 4>(d, ao, C, out); const long long rfao = flops();
-  reset(); recon_nodes<Fl, 4>(d, lin, C, nodes); const long long rn9 = flops();
-  reset(); recon_nodes<Fl, 4>(d, ao, C, nodes); const long long rnao = flops();
+  reset(); recon_nodes<Fl, 4, 4>(d, lin, C, nodes); const long long rn9 = flops();
+  reset(); recon_nodes<Fl, 4, 4>(d, ao, C, nodes); const long long rnao = flops();
   printf("recon faces r9 %lld AO %lld; nodes(m=4) r9 %lld AO %lld  (4 components)\n", rf9, rfao, rn9, rnao);
   // per 2-D cell and stage with the linear 9th-order branch (smooth flow), m = 4:
   //  Step 1: one node evaluation per direction (+ tangential slope sums 2*4*4*m)

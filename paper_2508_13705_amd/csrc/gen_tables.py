@@ -153,7 +153,9 @@ def fmt(v):
 
 
 def main():
-    lines = ["// Generated by gen_tables.py -- do not edit.", "// Slots: Q[-2..2], hQx[-2], hQx[-1], hQx[+1], hQx[+2]."]
+    lines = ["// Generated by gen_tables.py -- do not edit.", "// Slots: Q[-2..2], hQx[-2], hQx[-1], hQx[+1], hQx[+2].",
+             "// constexpr tables are indexed with compile-time indices only (folded into the",
+             "// instructions); the tangential weights are indexed per thread (device memory)."]
     maps = {k: coefficient_map(k) for k in STENCILS}
     # check the face rows against the printed coefficients
     for k, rows in PRINTED.items():
@@ -164,14 +166,14 @@ def main():
     # polynomial coefficient maps for the AO(5,3) members
     for k, deg in (("S0", 3), ("S1", 3), ("S2", 3), ("R5", 5)):
         C = maps[k]
-        lines.append(f"__constant__ double kC_{k}[{deg}][9] = {{")
+        lines.append(f"constexpr double kC_{k}[{deg}][9] = {{")
         for r in range(deg):
             lines.append("  {" + ", ".join(fmt(C[r][s]) for s in range(9)) + "},")
         lines.append("};")
     # linear-stencil evaluation weights at the faces: [side 0: xi=+1/2, 1: xi=-1/2][d][9]
     for k in ("R5", "R7", "R9"):
         C = maps[k]
-        lines.append(f"__constant__ double kF_{k}[2][3][9] = {{")
+        lines.append(f"constexpr double kF_{k}[2][3][9] = {{")
         for side, xi in ((0, Fr(1, 2)), (1, Fr(-1, 2))):
             lines.append("  {")
             for d in range(3):
@@ -180,7 +182,7 @@ def main():
         lines.append("};")
     # Gauss points, weights, and linear-stencil values at the Gauss points
     lines.append("// Gauss-Legendre points on [-1/2, 1/2] and weights (sum 1) for m = 2, 3, 4")
-    lines.append("__constant__ double kGx[5][4] = {")
+    lines.append("constexpr double kGx[5][4] = {")
     gx = {}
     for m in range(5):
         if m < 2:
@@ -190,7 +192,7 @@ def main():
         gx[m] = (x, w)
         lines.append("  {" + ", ".join(fmt(v) for v in x + [0] * (4 - m)) + "},")
     lines.append("};")
-    lines.append("__constant__ double kGw[5][4] = {")
+    lines.append("constexpr double kGw[5][4] = {")
     for m in range(5):
         if m < 2:
             lines.append("  {0, 0, 0, 0},")
@@ -199,7 +201,7 @@ def main():
     lines.append("};")
     for k in ("R5", "R7", "R9"):
         C = [[mp.mpf(c.numerator) / c.denominator for c in row] for row in maps[k]]
-        lines.append(f"__constant__ double kN_{k}[5][4][9] = {{  // [m][l][slot]: value at node l")
+        lines.append(f"constexpr double kN_{k}[5][4][9] = {{  // [m][l][slot]: value at node l")
         for m in range(5):
             lines.append("  {")
             for l in range(4):

@@ -84,6 +84,7 @@ class ServingLoop:
         preparing = {}      # job id -> (future, job, bytes, admission time)
         running = {}        # slot -> record
         done, rejected = [], []
+        blocked = set()
         reserved = 0
         free_slots = self.max_jobs
         captured = False
@@ -107,6 +108,7 @@ class ServingLoop:
                     rejected.append({"id": job["id"], "bytes": nbytes})
                     continue
                 if reserved + nbytes > self.budget:
+                    blocked.add(job["id"])     # waits for memory
                     break
                 queue.popleft()
                 reserved += nbytes
@@ -150,6 +152,7 @@ class ServingLoop:
                 for s in finished:
                     r = running.pop(s)
                     r["completed"] = now()
+                    r["waited_for_memory"] = r["id"] in blocked
                     r["status"] = st[s]["status"]
                     r["steps"] = st[s]["steps"]
                     r["t"] = st[s]["t"]

@@ -11,7 +11,7 @@ pytestmark = pytest.mark.gpu
 
 def _trace():
     # small sides (16..64), every order, both kinds of initial data, 4-20 steps
-    tr = W.serving_trace(seed=5, count=12, rate=200.0, nmin_log2=4.0, nmax_log2=6.0, steps=(4, 20))
+    tr = W.serving_trace(seed=5, count=12, rate=1e4, nmin_log2=4.0, nmax_log2=6.0, steps=(4, 20))
     return tr
 
 
@@ -28,7 +28,7 @@ def test_each_result_is_the_same_alone_and_in_the_mix():
                                                                 rep["max_running"]), flush=True)
     assert rep["jobs"] == len(tr) and rep["rejected"] == 0
     assert rep["max_running"] >= 2            # jobs shared the device
-    assert any(r["admitted"] - r["arrival"] > 1e-3 for r in rep["records"])   # someone waited for memory
+    assert any(r["waited_for_memory"] for r in rep["records"])   # admission waited for memory
     assert rep["latency_p99_s"] >= rep["latency_p50_s"] > 0
     for r in rep["records"]:
         job = r["job"]
