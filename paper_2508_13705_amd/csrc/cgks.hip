@@ -44,17 +44,30 @@ __global__ void k_dt(Header* hdr, const double* part, double dt_fixed, double cf
   dt_block(hdr, part, dt_fixed, cfl, t_end, h, mu, viscous, 0, nullptr);
 }
 
+// Block (x, y) of a 2-D grid as the dispatcher orders it (x fastest) goes to
+// XCD b mod 8, b = y * gridDim.x + x.  The kernels below work on the logical
+// block xcd_block(b) instead: each XCD takes one contiguous run of logical
+// blocks (a band of rows or tiles), so the halos that neighbouring blocks
+// share are fetched into one L2.  A bijection for any block count.
+__device__ __forceinline__ int xcd_block(int b, int n) {
+  const int q = n >> 3, r = n & 7, x = b & 7, k = b >> 3;
+  return (x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q) + k;
+}
+
 template <int M>
 __global__ __launch_bounds__(256) void k_lines(Geo g, Consts C, const double* U, const double* sxo,
                                                const double* syo, double* lvx, double* lvy, const Header* hdr) {
   if (!hdr->active) return;
-  lines_at<M>(g, C, U, sxo, syo, lvx, lvy, blockIdx.x * blockDim.x + threadIdx.x, blockIdx.y);
+  const int lb = xcd_block(blockIdx.y * gridDim.x + blockIdx.x, gridDim.x * gridDim.y);
+  const int bx = lb % gridDim.x, by = lb / gridDim.x;
+  lines_at<M>(g, C, U, sxo, syo, lvx, lvy, bx * blockDim.x + threadIdx.x, by);
 }
 
 template <int DIR, int STAGE, int M, typename T, bool PR>
 __global__ __launch_bounds__(256, FaceWaves<T>::value) void k_face2d(Geo g, Consts C, Bufs B) {
   extern __shared__ __align__(16) unsigned char smem[];
-  face2d_tile<DIR, STAGE, M, T, PR>(g, C, B, smem, blockIdx.x, blockIdx.y, gridDim.x, gridDim.y);
+  const int lb = xcd_block(blockIdx.y * gridDim.x + blockIdx.x, gridDim.x * gridDim.y);
+  face2d_tile<DIR, STAGE, M, T, PR>(g, C, B, smem, lb % gridDim.x, lb / gridDim.x, gridDim.x, gridDim.y);
 }
 
 template <int STAGE, typename T, bool PR>

@@ -136,9 +136,9 @@ __global__ __launch_bounds__(256, 1) void kb_face(const BTab* tab, int remap) {
     const int nbx = J.fnb[DIR][0], nby = J.fnb[DIR][1];
     const int bx = k % nbx, by = k / nbx;
     switch (J.M) {
-      case 2: face2d_tile<DIR, STAGE, 2, T, false>(J.g, J.C, J.B, smem, bx, by, nbx, nby); break;
-      case 3: face2d_tile<DIR, STAGE, 3, T, false>(J.g, J.C, J.B, smem, bx, by, nbx, nby); break;
-      default: face2d_tile<DIR, STAGE, 4, T, false>(J.g, J.C, J.B, smem, bx, by, nbx, nby); break;
+      case 2: face2d_tile<DIR, STAGE, 2, T, false, 4>(J.g, J.C, J.B, smem, bx, by, nbx, nby); break;
+      case 3: face2d_tile<DIR, STAGE, 3, T, false, 4>(J.g, J.C, J.B, smem, bx, by, nbx, nby); break;
+      default: face2d_tile<DIR, STAGE, 4, T, false, 4>(J.g, J.C, J.B, smem, bx, by, nbx, nby); break;
     }
   });
 }

@@ -429,23 +429,42 @@ template <int M> struct Tile {
   static constexpr int RK1 = 17, RK2 = 8;                     // results per Gauss point (stage 1 / 2)
 };
 
-// LDS of a face tile.  Step 2 results: one record of RS = 8M + 1 elements per
-// (line, cell) -- the odd stride puts neighbouring lanes on different banks.
-// Gauss-point results: structure of arrays, component k of Gauss point g at
-// k * NB + g, so lane g of a wave writes consecutive words.
+// LDS of a face tile, laid out by lifetime (barriers B1..B4 of the tile):
+//   staging  Step 2 inputs: line values and h-scaled normal slopes of the
+//            cells n = F0-3 .. F0+NF+1 on the NR lines (element type T),
+//            then the normal strengths of faces F0-3 .. F0+NF+2 (double);
+//            written before B1, read in Step 2 (before B2);
+//   recon    Step 2 results: one record of RS = 8M + 1 elements per (line,
+//            cell) -- the odd stride puts neighbouring lanes on different
+//            banks; written in Step 2, read in Step 3 (before B3);
+//   atab     tangential DFF factors of the Step 3 states; written before B1,
+//            read in Step 3;
+//   res      Gauss-point results, structure of arrays (component k of Gauss
+//            point g at k * NB + g, so lane g of a wave writes consecutive
+//            words); written after B3, read in the cell update (after B4);
+//   fin      updated averages of the tile (y-faces), written after B4.
+// recon | staging | atab, with res and then fin over recon and staging,
+// which are dead once B3 has passed.
 template <int M, typename T> struct Lds {
+  using TL = Tile<M>;
   static constexpr int RS = 8 * M + 1;
-  static constexpr size_t s2v = (size_t)Tile<M>::NR * Tile<M>::NC * RS * sizeof(T);
+  static constexpr int NCS = TL::NC + 4, NSG = TL::NC + 5;
+  static constexpr int NSTV = 4 * M * TL::NR * NCS;   // per staged array
+  static constexpr size_t a8(size_t x) { return (x + 7) / 8 * 8; }
+  static constexpr size_t s2v = (size_t)TL::NR * TL::NC * RS * sizeof(T);
   static constexpr size_t s2d = s2v;
-  static constexpr size_t s2dd = (size_t)Tile<M>::NT * Tile<M>::NC * RS * sizeof(T);
-  static constexpr size_t recon = s2v + s2d + s2dd;
-  static constexpr size_t res = (size_t)Tile<M>::NF * Tile<M>::NT * M * Tile<M>::RK1 * sizeof(double);
-  static constexpr size_t fin = (size_t)(Tile<M>::NF - 1) * Tile<M>::NT * 4 * sizeof(double);
-  // reconstruction | Gauss-point results | updated averages: separate, so a
-  // thread stores its flux results as soon as they are computed
-  static constexpr size_t off_res = recon;
-  static constexpr size_t off_fin = recon + res;
-  static constexpr size_t total = recon + res + fin;
+  static constexpr size_t s2dd = (size_t)TL::NT * TL::NC * RS * sizeof(T);
+  static constexpr size_t recon = a8(s2v + s2d + s2dd);
+  static constexpr size_t st_sg = a8(2 * NSTV * sizeof(T));          // offset of the strengths in staging
+  static constexpr size_t staging = st_sg + (size_t)TL::NR * NSG * sizeof(double);
+  static constexpr size_t res = (size_t)TL::NF * TL::NT * M * TL::RK1 * sizeof(double);
+  static constexpr size_t fin = (size_t)(TL::NF - 1) * TL::NT * 4 * sizeof(double);
+  static constexpr size_t off_staging = recon;
+  static constexpr size_t off_res = 0;
+  static constexpr size_t off_fin = res;
+  static constexpr size_t body = recon + staging > res + fin ? recon + staging : res + fin;
+  static constexpr size_t off_atab = a8(body);
+  static constexpr size_t total = off_atab + (size_t)TL::NC * TL::NT * sizeof(T);
 };
 
 // Waves per SIMD the face kernels are compiled for.  Both variants fit their
@@ -457,8 +476,10 @@ template <typename T> struct FaceWaves {
 };
 
 // One tile (bx, by) of nbx x nby; callable from a persistent loop (starts
-// with a barrier so the LDS of the previous tile is free).
-template <int DIR, int STAGE, int M, typename T, bool PR>
+// with a barrier so the LDS of the previous tile is free).  SU: staging passes
+// whose loads are issued together (all of them where registers allow; the
+// persistent batched kernels keep more per-job state live and take fewer).
+template <int DIR, int STAGE, int M, typename T, bool PR, int SU = 32>
 __device__ void face2d_tile(const Geo& g, const Consts& C, const Bufs& B, unsigned char* smem, int bx, int by,
                             int nbx, int nby) {
   using TL = Tile<M>;
@@ -470,7 +491,7 @@ __device__ void face2d_tile(const Geo& g, const Consts& C, const Bufs& B, unsign
   T* s2v = (T*)smem;
   T* s2d = (T*)(smem + Lds<M, T>::s2v);
   T* s2dd = (T*)(smem + Lds<M, T>::s2v + Lds<M, T>::s2d);
-  double* res = (double*)(smem + Lds<M, T>::off_res);
+  double* res = (double*)(smem + Lds<M, T>::off_res);     // over recon and staging, after B3
   double* fin = (double*)(smem + Lds<M, T>::off_fin);
   constexpr int RS = Lds<M, T>::RS;
   constexpr int NB = NF * NT * M;   // Gauss points of the tile
@@ -496,6 +517,63 @@ __device__ void face2d_tile(const Geo& g, const Consts& C, const Bufs& B, unsign
   auto sgn_idx = [&](int t, int face) { return DIR == 0 ? g.sgx(t, face) : g.sgy(t, face); };
   auto sgt_idx = [&](int n, int face) { return DIR == 0 ? g.sgy(n, face) : g.sgx(n, face); };
 
+  // ---- Step 2 inputs to LDS: one batch of loads for the whole tile ----
+  // Entries outside the stored grid (ghosts included) are clamped into it;
+  // only items that no thread owns read them.  Every pass runs on all lanes
+  // (wave-uniform); only the LDS stores are masked.
+  constexpr int NCS = Lds<M, T>::NCS, NSG = Lds<M, T>::NSG, NSTV = Lds<M, T>::NSTV;
+  T* stv = (T*)(smem + Lds<M, T>::off_staging);                    // [v][l][r][cc]
+  T* sts = stv + NSTV;                                               // same shape
+  double* stg = (double*)(smem + Lds<M, T>::off_staging + Lds<M, T>::st_sg);   // [r][ff]
+  T* atab = (T*)(smem + Lds<M, T>::off_atab);                       // [c][r], r < NT
+  auto clampi = [](int x, int lo, int hi) { return x < lo ? lo : (x > hi ? hi : x); };
+  {
+    // a lane keeps one (line, cell) position of a staged plane; the passes
+    // walk the planes (array, variable, Gauss line), PPP planes per pass
+    constexpr int PL = NR * NCS, PPP = 256 / PL, NPL = 2 * 4 * M;
+    static_assert(PPP >= 1, "a plane fits one pass");
+    const int tid = threadIdx.x;
+    const int lp = tid / PL < PPP ? tid / PL : PPP - 1;   // lanes past the last plane slot repeat it
+    const int e = tid % PL;
+    const int cc = DIR == 0 ? e % NCS : e / NR, r = DIR == 0 ? e / NCS : e % NR;
+    const bool slot = tid < PPP * PL;
+    const int n = clampi(F0 - 3 + cc, -H, nmax + H - 1), t = clampi(T0 - 1 + r, -H, tmax + H - 1);
+    const size_t cell = g.cell(gi(n, t), gj(n, t));
+    const double* slope = Uin + (size_t)g.nv * g.cells + (DIR == 0 ? 0 : (size_t)g.nv * g.m * g.cells);
+#pragma unroll SU
+    for (int p0 = 0; p0 < NPL; p0 += PPP) {
+      const int pl = p0 + lp < NPL ? p0 + lp : NPL - 1;
+      const int arr = pl / (4 * M), vl = pl % (4 * M), v = vl / M, l = vl % M;
+      const size_t off = ((size_t)gcomp[v] * M + l) * g.cells + cell;
+      const T val = arr == 0 ? T(LV[off]) : T(hn * slope[off]);
+      if (slot && p0 + lp < NPL) stv[arr * NSTV + (vl * NR + r) * NCS + cc] = val;
+    }
+  }
+  {
+    // normal strengths of the staged faces, and the tangential DFF factors of
+    // the Step 3 states (cell F0-1+c, line T0+r): one item of each per lane
+    static_assert(NR * NSG <= 256 && NC * NT <= 256, "one pass");
+    const int it = threadIdx.x;
+    {
+      const int k = it < NR * NSG ? it : 0;
+      const int ff = DIR == 0 ? k % NSG : k / NR, r = DIR == 0 ? k / NSG : k % NR;
+      const int face = clampi(F0 - 3 + ff, -H, nmax + H), t = clampi(T0 - 1 + r, -H, tmax + H - 1);
+      const double sg = sgN[sgn_idx(t, face)];
+      if (it < NR * NSG) stg[r * NSG + ff] = sg;
+    }
+    {
+      const int k = it < NC * NT ? it : 0;
+      const int c = DIR == 0 ? k % NC : k / NT, r = DIR == 0 ? k / NC : k % NT;
+      const int ncell = clampi(F0 - 1 + c, -H, nmax + H - 1);
+      double A = 0.0;
+#pragma unroll
+      for (int q = -1; q <= 2; ++q) A += sgT[sgt_idx(ncell, clampi(T0 + r + q, -H, tmax + H))];
+      const T at = T(dff_of(A, C.thres));
+      if (it < NC * NT) atab[c * NT + r] = at;
+    }
+  }
+  __syncthreads();
+
   // ---- Step 2: normal reconstruction on each line, both faces of a cell ----
   // Every pass runs on all 256 lanes: a lane without an item of its own
   // recomputes a valid item of the tile (c = r = 1, l = 0) and stores nothing.
@@ -507,22 +585,20 @@ __device__ void face2d_tile(const Geo& g, const Consts& C, const Bufs& B, unsign
     else { r = it % NR; c = (it / NR) % NC; l = it / (NC * NR); }
     const bool own = it < NA && F0 - 1 + c <= nmax && T0 - 1 + r <= tmax;   // n, t >= -1 by construction
     if (!own) { c = 1; r = 1; l = 0; }
-    const int n = F0 - 1 + c, t = T0 - 1 + r;
+    // cell n = F0-1+c sits at staged column c+2; face n-2+f at column c+f
     double s[6];
 #pragma unroll
-    for (int f = 0; f < 6; ++f) s[f] = sgN[sgn_idx(t, n - 2 + f)];
+    for (int f = 0; f < 6; ++f) s[f] = stg[r * NSG + c + f];
     const Cascade cs = cascade(s, C.order, C.thres);
     T d[4][9];
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
-      const int gv = gcomp[v];
+      const T* pv = stv + ((v * M + l) * NR + r) * NCS + c;
+      const T* ps = sts + ((v * M + l) * NR + r) * NCS + c;
 #pragma unroll
-      for (int k = 0; k < 5; ++k) d[v][k] = T(LV[g.lv(gv, l, gi(n + k - 2, t), gj(n + k - 2, t))]);
+      for (int k = 0; k < 5; ++k) d[v][k] = pv[k];
 #pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        const int o = k < 2 ? k - 2 : k - 1;
-        d[v][5 + k] = T(hn * Uin[sN(gv, l, n + o, t)]);
-      }
+      for (int k = 0; k < 4; ++k) d[v][5 + k] = ps[k < 2 ? k : k + 1];   // cells n-2, n-1, n+1, n+2
     }
     T out[2][3][4];
     recon_faces<T, 4>(d, cs, C, out);
@@ -557,10 +633,7 @@ __device__ void face2d_tile(const Geo& g, const Consts& C, const Bufs& B, unsign
     for (int sd = 0; sd < 2; ++sd) {
       const int c = sd == 0 ? f : f + 1;      // left state: cell nf-1 (its +1/2 face); right: cell nf
       const int ncell = nf - 1 + sd;
-      double A = 0.0;
-#pragma unroll
-      for (int q = -1; q <= 2; ++q) A += sgT[sgt_idx(ncell, t + q)];
-      const T at = T(dff_of(A, C.thres));
+      const T at = atab[(f + sd) * NT + r];    // cell ncell = F0-1+(f+sd), line t
       const T it1 = at * T(1.0 / ht), it2 = at * T(1.0 / (ht * ht));
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
@@ -593,6 +666,7 @@ __device__ void face2d_tile(const Geo& g, const Consts& C, const Bufs& B, unsign
         if (own) atomicAdd((unsigned long long*)&B.hdr->fallbacks, 1ull);
       }
     }
+    __syncthreads();   // B3: the Step 2 records are read; the results may overwrite them
     FaceOut fo;
     gks_flux<T, 2, PR>(Wk[0], Wk[1], dt, C, fo);
     // results to LDS (global component order)
@@ -661,15 +735,21 @@ __device__ void face2d_tile(const Geo& g, const Consts& C, const Bufs& B, unsign
         B.A[is] = (rb(12 + v, l) - ra(12 + v, l)) * ihn;
       }
     } else {
+      // every load before the first store: U and A are distinct arrays, but
+      // the compiler cannot know it and would otherwise wait for each load
+      double aslope[M];
+#pragma unroll
+      for (int l = 0; l < M; ++l) aslope[l] = B.A[DIR == 0 ? g.sx(v, l, i, j) : g.sy(v, l, i, j)];
+      const double base = DIR == 0 ? B.A[ia] : B.U[ia];
       double dA = 0.0;
       for (int l = 0; l < M; ++l) dA += kGw[M][l] * (rb(v, l) - ra(v, l));
-      const double base = DIR == 0 ? B.A[ia] : B.U[ia];
       const double unew = base - dA * ihn;
       B.U[ia] = unew;
       if (DIR == 1) fin[v * NFT + ci * NT + r] = unew;
+#pragma unroll
       for (int l = 0; l < M; ++l) {
         const size_t is = DIR == 0 ? g.sx(v, l, i, j) : g.sy(v, l, i, j);
-        B.U[is] = B.A[is] + (rb(4 + v, l) - ra(4 + v, l)) * ihn;
+        B.U[is] = aslope[l] + (rb(4 + v, l) - ra(4 + v, l)) * ihn;
       }
     }
   }
@@ -783,19 +863,28 @@ __device__ void stage1d_seg(const Geo& g, const Consts& C, const Bufs& B, double
   if (f < NFB - 1 && i < g.nx) {
     const double ih = 1.0 / h;
     double W[3];
+    // every load before the first store (the arrays are distinct, which the
+    // compiler cannot know)
+    double in0[3], in1[3];
+#pragma unroll
+    for (int v = 0; v < 3; ++v) {
+      in0[v] = STAGE == 1 ? B.U[g.avg(v, i, 0)] : B.A[g.avg(v, i, 0)];
+      in1[v] = STAGE == 1 ? 0.0 : B.A[g.sx(v, 0, i, 0)];
+    }
+#pragma unroll
     for (int v = 0; v < 3; ++v) {
       const size_t ia = g.avg(v, i, 0), is = g.sx(v, 0, i, 0);
       if (STAGE == 1) {
-        const double u0 = B.U[ia];
+        const double u0 = in0[v];
         W[v] = u0 - (res[f + 1][v] - res[f][v]) * ih;
         B.S[ia] = W[v];
         B.A[ia] = u0 - (res[f + 1][3 + v] - res[f][3 + v]) * ih;
         B.S[is] = (res[f + 1][6 + v] - res[f][6 + v]) * ih;
         B.A[is] = (res[f + 1][9 + v] - res[f][9 + v]) * ih;
       } else {
-        W[v] = B.A[ia] - (res[f + 1][v] - res[f][v]) * ih;
+        W[v] = in0[v] - (res[f + 1][v] - res[f][v]) * ih;
         B.U[ia] = W[v];
-        B.U[is] = B.A[is] + (res[f + 1][3 + v] - res[f][3 + v]) * ih;
+        B.U[is] = in1[v] + (res[f + 1][3 + v] - res[f][3 + v]) * ih;
       }
     }
     rr = W[0];
