@@ -21,7 +21,10 @@
 namespace {
 
 // Phases of a step, in launch order (2-D; 1-D uses DT, PREP, S1D1, BCS, S1D2).
-enum Phase { PH_DT = 0, PH_PREP, PH_LINES, PH_FX, PH_FY, PH_BCS, PH_S1D, NPH };
+// The face phases are per order m: each has a kernel compiled for that m
+// alone, which keeps its registers within the register file.
+enum Phase { PH_DT = 0, PH_PREP, PH_LINES, PH_FX2, PH_FX3, PH_FX4, PH_FY2, PH_FY3, PH_FY4, PH_BCS, PH_S1D, NPH };
+constexpr int ph_face(int dir, int m) { return (dir == 0 ? PH_FX2 : PH_FY2) + (m - 2); }
 
 struct BJob {
   Geo g;
@@ -122,24 +125,14 @@ __global__ __launch_bounds__(256) void kb_lines(const BTab* tab, int stage, int 
   });
 }
 
-template <typename T>
-constexpr size_t face_lds() {
-  return std::max(Lds<2, T>::total, std::max(Lds<3, T>::total, Lds<4, T>::total));
-}
-
 // Fused reconstruction + flux + update of one direction and stage over the
-// face tiles of every job; the order (m) is a per-job switch.
-template <int DIR, int STAGE, typename T>
+// face tiles of every job of order m = M.
+template <int DIR, int STAGE, typename T, int M>
 __global__ __launch_bounds__(256, 1) void kb_face(const BTab* tab, int remap) {
   extern __shared__ __align__(16) unsigned char smem[];
-  for_items(tab, DIR == 0 ? PH_FX : PH_FY, remap, [&](const BJob& J, int k) {
+  for_items(tab, ph_face(DIR, M), remap, [&](const BJob& J, int k) {
     const int nbx = J.fnb[DIR][0], nby = J.fnb[DIR][1];
-    const int bx = k % nbx, by = k / nbx;
-    switch (J.M) {
-      case 2: face2d_tile<DIR, STAGE, 2, T, false, 4>(J.g, J.C, J.B, smem, bx, by, nbx, nby); break;
-      case 3: face2d_tile<DIR, STAGE, 3, T, false, 4>(J.g, J.C, J.B, smem, bx, by, nbx, nby); break;
-      default: face2d_tile<DIR, STAGE, 4, T, false, 4>(J.g, J.C, J.B, smem, bx, by, nbx, nby); break;
-    }
+    face2d_tile<DIR, STAGE, M, T, false>(J.g, J.C, J.B, smem, k % nbx, k / nbx, nbx, nby);
   });
 }
 
@@ -194,21 +187,29 @@ void set_grids(cgks_batch* b) {
 
 // Dynamic LDS limit of the batched face kernels and the scratch check of
 // every batched kernel (none may use scratch).
-template <int DIR, int STAGE, typename T>
+template <int DIR, int STAGE, typename T, int M>
 cgks_status prepare_bface() {
-  const void* f = (const void*)kb_face<DIR, STAGE, T>;
-  hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)face_lds<T>());
+  const void* f = (const void*)kb_face<DIR, STAGE, T, M>;
+  hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)Lds<M, T>::total);
   if (e != hipSuccess) return fail(CGKS_EHIP, std::string("hipFuncSetAttribute: ") + hipGetErrorString(e));
   return check_private(f, 0, "batched face kernel");
+}
+
+template <typename T, int M>
+cgks_status prepare_bfaces() {
+  cgks_status s;
+  if ((s = prepare_bface<0, 1, T, M>()) != CGKS_OK) return s;
+  if ((s = prepare_bface<1, 1, T, M>()) != CGKS_OK) return s;
+  if ((s = prepare_bface<0, 2, T, M>()) != CGKS_OK) return s;
+  return prepare_bface<1, 2, T, M>();
 }
 
 template <typename T>
 cgks_status prepare_batch() {
   cgks_status s;
-  if ((s = prepare_bface<0, 1, T>()) != CGKS_OK) return s;
-  if ((s = prepare_bface<1, 1, T>()) != CGKS_OK) return s;
-  if ((s = prepare_bface<0, 2, T>()) != CGKS_OK) return s;
-  if ((s = prepare_bface<1, 2, T>()) != CGKS_OK) return s;
+  if ((s = prepare_bfaces<T, 2>()) != CGKS_OK) return s;
+  if ((s = prepare_bfaces<T, 3>()) != CGKS_OK) return s;
+  if ((s = prepare_bfaces<T, 4>()) != CGKS_OK) return s;
   const void* k[] = {(const void*)kb_dt, (const void*)kb_prep, (const void*)kb_bcs, (const void*)kb_lines,
                      (const void*)kb_stage1d<1, T>, (const void*)kb_stage1d<2, T>};
   for (const void* f : k)
@@ -223,9 +224,20 @@ hipError_t occupancy(cgks_batch* b) {
   if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&b->occ[K_PREP], kb_prep, 256, 0))) return e;
   if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&b->occ[K_BCS], kb_bcs, 256, 0))) return e;
   if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&b->occ[K_LINES], kb_lines, 256, 0))) return e;
-  if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&b->occ[K_FACE], kb_face<1, 2, T>, 256, face_lds<T>())))
+  // the face grid serves every order: size it by the largest tile (m = 4)
+  if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&b->occ[K_FACE], kb_face<1, 2, T, 4>, 256,
+                                                        Lds<4, T>::total)))
     return e;
   return hipOccupancyMaxActiveBlocksPerMultiprocessor(&b->occ[K_S1D], kb_stage1d<2, T>, 256, 0);
+}
+
+// The face kernels of one direction and stage, one launch per order.
+template <int DIR, int STAGE, typename T>
+void launch_faces(int gf, hipStream_t st, const BTab* t, int r) {
+  constexpr size_t l2 = Lds<2, T>::total, l3 = Lds<3, T>::total, l4 = Lds<4, T>::total;
+  hipLaunchKernelGGL((kb_face<DIR, STAGE, T, 2>), dim3(gf), dim3(256), l2, st, t, r);
+  hipLaunchKernelGGL((kb_face<DIR, STAGE, T, 3>), dim3(gf), dim3(256), l3, st, t, r);
+  hipLaunchKernelGGL((kb_face<DIR, STAGE, T, 4>), dim3(gf), dim3(256), l4, st, t, r);
 }
 
 template <typename T>
@@ -240,15 +252,16 @@ hipError_t enqueue_batch_step(const cgks_batch* b, hipStream_t st) {
     hipLaunchKernelGGL((kb_stage1d<2, T>), dim3(b->grid[K_S1D]), dim3(256), 0, st, t, r);
     return hipGetLastError();
   }
-  const size_t lds = face_lds<T>();
   const int gf = b->grid[K_FACE];
+  // every order is launched (a phase without jobs of that order ends at
+  // once), so a captured step serves any later mix of orders
   hipLaunchKernelGGL(kb_lines, dim3(b->grid[K_LINES]), dim3(256), 0, st, t, 1, r);
-  hipLaunchKernelGGL((kb_face<0, 1, T>), dim3(gf), dim3(256), lds, st, t, r);
-  hipLaunchKernelGGL((kb_face<1, 1, T>), dim3(gf), dim3(256), lds, st, t, r);
+  launch_faces<0, 1, T>(gf, st, t, r);
+  launch_faces<1, 1, T>(gf, st, t, r);
   hipLaunchKernelGGL(kb_bcs, dim3(b->grid[K_BCS]), dim3(256), 0, st, t, r);
   hipLaunchKernelGGL(kb_lines, dim3(b->grid[K_LINES]), dim3(256), 0, st, t, 2, r);
-  hipLaunchKernelGGL((kb_face<0, 2, T>), dim3(gf), dim3(256), lds, st, t, r);
-  hipLaunchKernelGGL((kb_face<1, 2, T>), dim3(gf), dim3(256), lds, st, t, r);
+  launch_faces<0, 2, T>(gf, st, t, r);
+  launch_faces<1, 2, T>(gf, st, t, r);
   return hipGetLastError();
 }
 
@@ -293,8 +306,10 @@ long long items(const BJob& J, int ph) {
     case PH_PREP: return (long long)J.nsx + J.nsy + (long long)J.as * J.g.NY;
     case PH_BCS: return (long long)J.as * J.g.NY;
     case PH_LINES: return J.g.dim == 2 ? (long long)J.as * J.g.NY : 0;
-    case PH_FX: return (long long)J.fnb[0][0] * J.fnb[0][1];
-    case PH_FY: return (long long)J.fnb[1][0] * J.fnb[1][1];
+    case PH_FX2: case PH_FX3: case PH_FX4:
+      return J.M == 2 + (ph - PH_FX2) ? (long long)J.fnb[0][0] * J.fnb[0][1] : 0;
+    case PH_FY2: case PH_FY3: case PH_FY4:
+      return J.M == 2 + (ph - PH_FY2) ? (long long)J.fnb[1][0] * J.fnb[1][1] : 0;
     case PH_S1D: return J.nseg;
   }
   return 0;

@@ -443,6 +443,7 @@ CGKS_HD void gks_flux(const T (&Wl)[6][4], const T (&Wr)[6][4], double dt, const
   // time integrals (the flux keeps the terms up to first order in t of the
   // equilibrium part; interface values keep the full quadratic)
   const double r0 = double(rho0);
+  double ex[2] = {0.0, 0.0};   // exp(-dt/(2 tau)), exp(-dt/tau); 0 when tau = 0
 #pragma unroll
   for (int w = 0; w < 2; ++w) {
     const double d = w == 0 ? 0.5 * dt : dt;
@@ -450,6 +451,7 @@ CGKS_HD void gks_flux(const T (&Wl)[6][4], const T (&Wr)[6][4], double dt, const
     if (tau > 0.0) {
       const double x = d * itau;
       const double e = exp(-x);
+      ex[w] = e;
       E0 = -tau * expm1(-x);
       E1 = tau * tau - tau * (tau + d) * e;
     }
@@ -472,7 +474,7 @@ CGKS_HD void gks_flux(const T (&Wl)[6][4], const T (&Wr)[6][4], double dt, const
 #pragma unroll
   for (int w = 0; w < 3; ++w) {
     const double t = w == 0 ? 0.0 : (w == 1 ? 0.5 * dt : dt);
-    const double e = (t == 0.0) ? 1.0 : (tau > 0.0 ? exp(-t * itau) : 0.0);
+    const double e = w == 0 ? 1.0 : ex[w - 1];   // exp(-t/tau)
     double* Wo = w == 0 ? o.W0 : (w == 1 ? o.Wh : o.W1);
 #pragma unroll
     for (int v = 0; v < 4; ++v) {

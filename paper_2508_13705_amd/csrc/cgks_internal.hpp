@@ -448,12 +448,24 @@ template <int M> struct Tile {
 template <int M, typename T> struct Lds {
   using TL = Tile<M>;
   static constexpr int RS = 8 * M + 1;
+  // Step 2 records of (line r, cell c): x-faces row-major, r RW + c RS;
+  // y-faces cell-major, c CS + r RS.  A group of lanes that the LDS serves
+  // together (16 for 64-bit, 32 for 32-bit words) holds up to two lines and
+  // 16 cells on x-faces, and several lines and cells on y-faces; the padded
+  // strides RW and CS put every lane of such a group on its own bank in
+  // Step 3 (found by enumerating strides against the lane layout).  The
+  // second-derivative records (NT lines) use RW and cell stride CSD.
+  static constexpr int RW = M == 2 ? 304 : (M == 3 ? 432 : 592);
+  static constexpr int CS = M == 2 ? 200 : (M == 3 ? 189 : 204);
+  static constexpr int CSD = TL::NT * RS;
+  static_assert(RW >= TL::NC * RS && CS >= TL::NR * RS, "records do not overlap");
   static constexpr int NCS = TL::NC + 4, NSG = TL::NC + 5;
   static constexpr int NSTV = 4 * M * TL::NR * NCS;   // per staged array
   static constexpr size_t a8(size_t x) { return (x + 7) / 8 * 8; }
-  static constexpr size_t s2v = (size_t)TL::NR * TL::NC * RS * sizeof(T);
+  static constexpr size_t mx(size_t a, size_t b) { return a > b ? a : b; }
+  static constexpr size_t s2v = mx((size_t)TL::NR * RW, (size_t)TL::NC * CS) * sizeof(T);   // both layouts
   static constexpr size_t s2d = s2v;
-  static constexpr size_t s2dd = (size_t)TL::NT * TL::NC * RS * sizeof(T);
+  static constexpr size_t s2dd = mx((size_t)TL::NT * RW, (size_t)TL::NC * CSD) * sizeof(T);
   static constexpr size_t recon = a8(s2v + s2d + s2dd);
   static constexpr size_t st_sg = a8(2 * NSTV * sizeof(T));          // offset of the strengths in staging
   static constexpr size_t staging = st_sg + (size_t)TL::NR * NSG * sizeof(double);
@@ -495,7 +507,12 @@ __device__ void face2d_tile(const Geo& g, const Consts& C, const Bufs& B, unsign
   double* fin = (double*)(smem + Lds<M, T>::off_fin);
   constexpr int RS = Lds<M, T>::RS;
   constexpr int NB = NF * NT * M;   // Gauss points of the tile
-  auto I2 = [&](int r, int c, int l, int sd, int v) { return (r * NC + c) * RS + (l * 2 + sd) * 4 + v; };
+  auto I2 = [&](int r, int c, int l, int sd, int v) {     // value and normal-derivative records
+    return (DIR == 0 ? r * Lds<M, T>::RW + c * RS : c * Lds<M, T>::CS + r * RS) + (l * 2 + sd) * 4 + v;
+  };
+  auto I2D = [&](int r, int c, int l, int sd, int v) {    // second-derivative records (r < NT)
+    return (DIR == 0 ? r * Lds<M, T>::RW + c * RS : c * Lds<M, T>::CSD + r * RS) + (l * 2 + sd) * 4 + v;
+  };
   // Gauss point (face f, line r, node l) -> its thread / result column
   auto gp = [&](int f, int r, int l) { return DIR == 0 ? f + NF * (r + NT * l) : r + NT * (f + NF * l); };
 
@@ -610,7 +627,7 @@ __device__ void face2d_tile(const Geo& g, const Consts& C, const Bufs& B, unsign
         for (int v = 0; v < 4; ++v) {
           s2v[I2(r, c, l, sd, v)] = out[sd][0][v];
           s2d[I2(r, c, l, sd, v)] = out[sd][1][v] * ih;
-          if (r >= 1 && r <= NT) s2dd[I2(r - 1, c, l, sd, v)] = out[sd][2][v] * ih2;
+          if (r >= 1 && r <= NT) s2dd[I2D(r - 1, c, l, sd, v)] = out[sd][2][v] * ih2;
         }
     }
   }
@@ -639,7 +656,7 @@ __device__ void face2d_tile(const Geo& g, const Consts& C, const Bufs& B, unsign
       for (int v = 0; v < 4; ++v) {
         Wk[sd][0][v] = s2v[I2(r + 1, c, l, sd, v)];
         Wk[sd][1][v] = s2d[I2(r + 1, c, l, sd, v)];
-        Wk[sd][3][v] = s2dd[I2(r, c, l, sd, v)];
+        Wk[sd][3][v] = s2dd[I2D(r, c, l, sd, v)];
         T a1 = 0, a2 = 0, ax = 0;
 #pragma unroll
         for (int rr = 0; rr < 3; ++rr)
