@@ -57,17 +57,24 @@ __device__ __forceinline__ int xcd_block(int b, int n) {
 template <int M>
 __global__ __launch_bounds__(256) void k_lines(Geo g, Consts C, const double* U, const double* sxo,
                                                const double* syo, double* lvx, double* lvy, const Header* hdr) {
+  __shared__ double sm[LinesLds::total];
   if (!hdr->active) return;
   const int lb = xcd_block(blockIdx.y * gridDim.x + blockIdx.x, gridDim.x * gridDim.y);
-  const int bx = lb % gridDim.x, by = lb / gridDim.x;
-  lines_at<M>(g, C, U, sxo, syo, lvx, lvy, bx * blockDim.x + threadIdx.x, by);
+  lines_tile<M>(g, C, U, sxo, syo, lvx, lvy, lb % gridDim.x, lb / gridDim.x, sm);
 }
 
+// Grid (tiles along the normal, tiles along the tangential).  x-face tiles
+// are taken normal-first and y-face tiles tangential-first: either way the
+// tiles that run together are neighbours along x, the contiguous direction,
+// and share their cache lines in L2 (a y-face tile spans only NT + 2 cells
+// along x).
 template <int DIR, int STAGE, int M, typename T, bool PR>
 __global__ __launch_bounds__(256, FaceWaves<T>::value) void k_face2d(Geo g, Consts C, Bufs B) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int lb = xcd_block(blockIdx.y * gridDim.x + blockIdx.x, gridDim.x * gridDim.y);
-  face2d_tile<DIR, STAGE, M, T, PR>(g, C, B, smem, lb % gridDim.x, lb / gridDim.x, gridDim.x, gridDim.y);
+  const int bx = DIR == 0 ? lb % gridDim.x : lb / gridDim.y;
+  const int by = DIR == 0 ? lb / gridDim.x : lb % gridDim.y;
+  face2d_tile<DIR, STAGE, M, T, PR>(g, C, B, smem, bx, by, gridDim.x, gridDim.y);
 }
 
 template <int STAGE, typename T, bool PR>
@@ -135,7 +142,7 @@ hipError_t launch_stage2d(const cgks_plan* p, const Bufs& b, int stage, hipStrea
   using TL = Tile<M>;
   const double* Uin = stage == 1 ? b.U : b.S;
   {
-    dim3 grid((g.NX + 255) / 256, g.NY);
+    dim3 grid((g.NX + LT_X - 1) / LT_X, (g.NY + LT_Y - 1) / LT_Y);
     hipLaunchKernelGGL(k_lines<M>, grid, dim3(256), 0, st, g, p->C, Uin, b.sxo, b.syo, b.lvx, b.lvy, b.hdr);
     tick(mk, st);
   }

@@ -132,7 +132,9 @@ __global__ __launch_bounds__(256, 1) void kb_face(const BTab* tab, int remap) {
   extern __shared__ __align__(16) unsigned char smem[];
   for_items(tab, ph_face(DIR, M), remap, [&](const BJob& J, int k) {
     const int nbx = J.fnb[DIR][0], nby = J.fnb[DIR][1];
-    face2d_tile<DIR, STAGE, M, T, false>(J.g, J.C, J.B, smem, k % nbx, k / nbx, nbx, nby);
+    // neighbours along x first (x-faces: normal-first, y-faces: tangential-first)
+    const int bx = DIR == 0 ? k % nbx : k / nby, by = DIR == 0 ? k / nbx : k % nby;
+    face2d_tile<DIR, STAGE, M, T, false>(J.g, J.C, J.B, smem, bx, by, nbx, nby);
   });
 }
 

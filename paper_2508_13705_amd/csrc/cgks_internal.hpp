@@ -410,6 +410,128 @@ __device__ __forceinline__ void lines_at(const Geo& g, const Consts& C, const do
 }
 
 
+// Step 1 over a tile of LT_X x LT_Y cells (x fastest; block of 256 threads,
+// one cell each) with its inputs staged in LDS: the cell averages on the
+// tile and a border of two cells, the cell-averaged normal gradients (line
+// slopes weighted by the Gauss weights) on the strips each stencil direction
+// reads, and the strengths of the faces the cascades use.  Every input is
+// loaded once per tile, and the gradient means are formed once per cell
+// rather than once per use; the arithmetic and its order are those of
+// lines_at, so the results are the same bit for bit.
+constexpr int LT_X = 32, LT_Y = 8;
+struct LinesLds {
+  static constexpr int BX = LT_X + 4, BY = LT_Y + 4;
+  static constexpr int NAVG = 4 * BY * BX;        // averages [v][BY][BX], cells (i0-2+xx, j0-2+yy)
+  static constexpr int NGY = 4 * BY * LT_X;       // y-gradient means [v][BY][LT_X], cells (i0+xx, j0-2+yy)
+  static constexpr int NGX = 4 * LT_Y * BX;       // x-gradient means [v][LT_Y][BX], cells (i0-2+xx, j0+yy)
+  static constexpr int SYN = LT_Y + 5, SXN = LT_X + 5;
+  static constexpr int NSY = LT_X * SYN;          // y-face strengths [xx][gg], face j0-2+gg of column i0+xx
+  static constexpr int NSX = LT_Y * SXN;          // x-face strengths [yy][ff], face i0-2+ff of row j0+yy
+  static constexpr int total = NAVG + NGY + NGX + NSY + NSX;   // doubles
+};
+static_assert(LT_X * LT_Y == 256, "one cell per thread");
+
+template <int M>
+__device__ __forceinline__ void lines_tile(const Geo& g, const Consts& C, const double* U, const double* sxo,
+                                           const double* syo, double* lvx, double* lvy, int bx, int by,
+                                           double* sm) {
+  using L = LinesLds;
+  double* avg = sm;
+  double* gy = avg + L::NAVG;
+  double* gx = gy + L::NGY;
+  double* sy = gx + L::NGX;
+  double* sx = sy + L::NSY;
+  const int i0 = -H + bx * LT_X, j0 = -H + by * LT_Y;
+  const int tid = threadIdx.x;
+  auto ci = [&](int i) { return i < -H ? -H : (i > g.nx + H - 1 ? g.nx + H - 1 : i); };
+  auto cj = [&](int j) { return j < -H ? -H : (j > g.ny + H - 1 ? g.ny + H - 1 : j); };
+  double wq[4];
+#pragma unroll
+  for (int l = 0; l < M; ++l) wq[l] = kGw[M][l];
+  // staging (entries outside the stored grid are clamped into it; no cell
+  // that computes line values reads them)
+  for (int k = tid; k < L::NAVG; k += 256) {
+    const int v = k / (L::BY * L::BX), xx = k % L::BX, yy = (k / L::BX) % L::BY;
+    avg[k] = U[g.avg(v, ci(i0 - 2 + xx), cj(j0 - 2 + yy))];
+  }
+  for (int k = tid; k < L::NGY; k += 256) {
+    const int v = k / (L::BY * LT_X), xx = k % LT_X, yy = (k / LT_X) % L::BY;
+    const int i = ci(i0 + xx), j = cj(j0 - 2 + yy);
+    double a = 0.0;
+#pragma unroll
+    for (int l = 0; l < M; ++l) a += wq[l] * U[g.sy(v, l, i, j)];
+    gy[k] = a;
+  }
+  for (int k = tid; k < L::NGX; k += 256) {
+    const int v = k / (LT_Y * L::BX), xx = k % L::BX, yy = (k / L::BX) % LT_Y;
+    const int i = ci(i0 - 2 + xx), j = cj(j0 + yy);
+    double a = 0.0;
+#pragma unroll
+    for (int l = 0; l < M; ++l) a += wq[l] * U[g.sx(v, l, i, j)];
+    gx[k] = a;
+  }
+  for (int k = tid; k < L::NSY; k += 256) {   // faces contiguous in memory along gg
+    const int gg = k % L::SYN, xx = k / L::SYN;
+    const int G = j0 - 2 + gg;
+    sy[k] = syo[g.sgy(ci(i0 + xx), G < -H ? -H : (G > g.ny + H ? g.ny + H : G))];
+  }
+  for (int k = tid; k < L::NSX; k += 256) {
+    const int ff = k % L::SXN, yy = k / L::SXN;
+    const int F = i0 - 2 + ff;
+    sx[k] = sxo[g.sgx(cj(j0 + yy), F < -H ? -H : (F > g.nx + H ? g.nx + H : F))];
+  }
+  __syncthreads();
+  const int xx = tid % LT_X, yy = tid / LT_X;
+  const int i = i0 + xx, j = j0 + yy;
+  // x-face line values: column i, rows j-2..j+2, needed for j in [-1, ny]
+  if (i <= g.nx + 2 && j >= -1 && j <= g.ny) {
+    double d[4][9], s[6];
+#pragma unroll
+    for (int f = 0; f < 6; ++f) s[f] = sy[xx * L::SYN + yy + f];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+#pragma unroll
+      for (int k = 0; k < 5; ++k) d[v][k] = avg[(v * L::BY + yy + k) * L::BX + xx + 2];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const int o = k < 2 ? k - 2 : k - 1;
+        d[v][5 + k] = C.dy * gy[(v * L::BY + yy + 2 + o) * LT_X + xx];
+      }
+    }
+    const Cascade cs = cascade(s, C.order, C.thres);
+    double out[4][4];
+    recon_nodes<double, 4, M>(d, cs, C, out);
+#pragma unroll
+    for (int l = 0; l < M; ++l)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) lvx[g.lv(v, l, i, j)] = out[l][v];
+  }
+  // y-face line values: row j, columns i-2..i+2, needed for i in [-1, nx]
+  if (i >= -1 && i <= g.nx && j <= g.ny + 2) {
+    double d[4][9], s[6];
+#pragma unroll
+    for (int f = 0; f < 6; ++f) s[f] = sx[yy * L::SXN + xx + f];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+#pragma unroll
+      for (int k = 0; k < 5; ++k) d[v][k] = avg[(v * L::BY + yy + 2) * L::BX + xx + k];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const int o = k < 2 ? k - 2 : k - 1;
+        d[v][5 + k] = C.dx * gx[(v * LT_Y + yy) * L::BX + xx + 2 + o];
+      }
+    }
+    const Cascade cs = cascade(s, C.order, C.thres);
+    double out[4][4];
+    recon_nodes<double, 4, M>(d, cs, C, out);
+#pragma unroll
+    for (int l = 0; l < M; ++l)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) lvy[g.lv(v, l, i, j)] = out[l][v];
+  }
+}
+
+
 // ---------------------------------------------------------------------------
 // 2-D face kernel: Step 2 (normal ASE-DFF on every Gauss line), Step 3
 // (tangential derivatives), Step 4 (flux), and the cell update of one
