@@ -36,6 +36,7 @@ struct BJob {
   int ax, ay, as;          // 256-wide segments per row: sigma x-faces, sigma y-faces, state rows
   int nsx, nsy;            // PREP items of the sigma x / y parts
   int fnb[2][2];           // face tiles (along normal, along tangential) of x- and y-faces
+  int ltx, lty;            // Step 1 tiles along x and y
   int nseg;                // 1-D stage segments
 };
 
@@ -111,16 +112,17 @@ __global__ __launch_bounds__(256) void kb_bcs(const BTab* tab, int remap) {
   });
 }
 
-// Step 1 line values of the stage input (2-D).
+// Step 1 line values of the stage input (2-D), one LT_X x LT_Y tile per item.
 __global__ __launch_bounds__(256) void kb_lines(const BTab* tab, int stage, int remap) {
+  __shared__ double sm[LinesLds::total];
   for_items(tab, PH_LINES, remap, [&](const BJob& J, int k) {
     if (!J.B.hdr->active) return;
     const double* Uin = stage == 1 ? J.B.U : J.B.S;
-    const int I = (k % J.as) * 256 + threadIdx.x, Jr = k / J.as;
+    const int bx = k % J.ltx, by = k / J.ltx;
     switch (J.M) {
-      case 2: lines_at<2>(J.g, J.C, Uin, J.B.sxo, J.B.syo, J.B.lvx, J.B.lvy, I, Jr); break;
-      case 3: lines_at<3>(J.g, J.C, Uin, J.B.sxo, J.B.syo, J.B.lvx, J.B.lvy, I, Jr); break;
-      default: lines_at<4>(J.g, J.C, Uin, J.B.sxo, J.B.syo, J.B.lvx, J.B.lvy, I, Jr); break;
+      case 2: lines_tile<2>(J.g, J.C, Uin, J.B.sxo, J.B.syo, J.B.lvx, J.B.lvy, bx, by, sm); break;
+      case 3: lines_tile<3>(J.g, J.C, Uin, J.B.sxo, J.B.syo, J.B.lvx, J.B.lvy, bx, by, sm); break;
+      default: lines_tile<4>(J.g, J.C, Uin, J.B.sxo, J.B.syo, J.B.lvx, J.B.lvy, bx, by, sm); break;
     }
   });
 }
@@ -289,6 +291,8 @@ void fill_counts(BJob& J) {
   J.ay = g.dim == 2 ? (g.NY + 1 + 255) / 256 : 0;
   J.nsy = g.dim == 2 ? J.ay * g.NX : 0;
   J.as = (g.NX + 255) / 256;
+  J.ltx = (g.NX + LT_X - 1) / LT_X;
+  J.lty = (g.NY + LT_Y - 1) / LT_Y;
   if (g.dim == 2) {
     const int NF = 16, NT = J.M == 2 ? 8 : (J.M == 3 ? 5 : 4);
     J.fnb[0][0] = (g.nx + NF - 2) / (NF - 1);
@@ -307,7 +311,7 @@ long long items(const BJob& J, int ph) {
     case PH_DT: return 1;
     case PH_PREP: return (long long)J.nsx + J.nsy + (long long)J.as * J.g.NY;
     case PH_BCS: return (long long)J.as * J.g.NY;
-    case PH_LINES: return J.g.dim == 2 ? (long long)J.as * J.g.NY : 0;
+    case PH_LINES: return J.g.dim == 2 ? (long long)J.ltx * J.lty : 0;
     case PH_FX2: case PH_FX3: case PH_FX4:
       return J.M == 2 + (ph - PH_FX2) ? (long long)J.fnb[0][0] * J.fnb[0][1] : 0;
     case PH_FY2: case PH_FY3: case PH_FY4:

@@ -441,6 +441,7 @@ __device__ __forceinline__ void lines_tile(const Geo& g, const Consts& C, const 
   double* gx = gy + L::NGY;
   double* sy = gx + L::NGX;
   double* sx = sy + L::NSY;
+  __syncthreads();   // a persistent caller's previous tile has finished with the LDS
   const int i0 = -H + bx * LT_X, j0 = -H + by * LT_Y;
   const int tid = threadIdx.x;
   auto ci = [&](int i) { return i < -H ? -H : (i > g.nx + H - 1 ? g.nx + H - 1 : i); };
