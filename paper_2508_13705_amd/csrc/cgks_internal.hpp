@@ -346,78 +346,14 @@ __device__ void dt_block(Header* hdr, const double* part, double dt_fixed, doubl
 // 2-D Step 1 (Sec. 3.3): tangential ASE-DFF in each column (row) gives the
 // line averages of the cell on the horizontal (vertical) Gauss lines.
 // ---------------------------------------------------------------------------
-template <int M>
-__device__ __forceinline__ void lines_at(const Geo& g, const Consts& C, const double* U, const double* sxo,
-                                         const double* syo, double* lvx, double* lvy, int I, int J) {
-  const int i = I - H;
-  const int j = J - H;
-  if (i > g.nx + 2) return;
-  double wq[4];
-#pragma unroll
-  for (int l = 0; l < M; ++l) wq[l] = kGw[M][l];
-  // x-face line values: column i, rows j-2..j+2, needed for j in [-1, ny]
-  if (j >= -1 && j <= g.ny) {
-    double d[4][9], s[6];
-#pragma unroll
-    for (int f = 0; f < 6; ++f) s[f] = syo[g.sgy(i, j - 2 + f)];
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-#pragma unroll
-      for (int k = 0; k < 5; ++k) d[v][k] = U[g.avg(v, i, j + k - 2)];
-#pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        const int o = k < 2 ? k - 2 : k - 1;
-        double a = 0.0;
-#pragma unroll
-        for (int l = 0; l < M; ++l) a += wq[l] * U[g.sy(v, l, i, j + o)];
-        d[v][5 + k] = C.dy * a;
-      }
-    }
-    const Cascade cs = cascade(s, C.order, C.thres);
-    double out[4][4];
-    recon_nodes<double, 4, M>(d, cs, C, out);
-#pragma unroll
-    for (int l = 0; l < M; ++l)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) lvx[g.lv(v, l, i, j)] = out[l][v];
-  }
-  // y-face line values: row j, columns i-2..i+2, needed for i in [-1, nx]
-  if (i >= -1 && i <= g.nx && j >= -3 && j <= g.ny + 2) {
-    double d[4][9], s[6];
-#pragma unroll
-    for (int f = 0; f < 6; ++f) s[f] = sxo[g.sgx(j, i - 2 + f)];
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-#pragma unroll
-      for (int k = 0; k < 5; ++k) d[v][k] = U[g.avg(v, i + k - 2, j)];
-#pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        const int o = k < 2 ? k - 2 : k - 1;
-        double a = 0.0;
-#pragma unroll
-        for (int l = 0; l < M; ++l) a += wq[l] * U[g.sx(v, l, i + o, j)];
-        d[v][5 + k] = C.dx * a;
-      }
-    }
-    const Cascade cs = cascade(s, C.order, C.thres);
-    double out[4][4];
-    recon_nodes<double, 4, M>(d, cs, C, out);
-#pragma unroll
-    for (int l = 0; l < M; ++l)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) lvy[g.lv(v, l, i, j)] = out[l][v];
-  }
-}
-
-
 // Step 1 over a tile of LT_X x LT_Y cells (x fastest; block of 256 threads,
 // one cell each) with its inputs staged in LDS: the cell averages on the
 // tile and a border of two cells, the cell-averaged normal gradients (line
 // slopes weighted by the Gauss weights) on the strips each stencil direction
 // reads, and the strengths of the faces the cascades use.  Every input is
 // loaded once per tile, and the gradient means are formed once per cell
-// rather than once per use; the arithmetic and its order are those of
-// lines_at, so the results are the same bit for bit.
+// rather than once per use (with the same operations in the same order as
+// forming them at each use, so the results do not depend on the tiling).
 constexpr int LT_X = 32, LT_Y = 8;
 struct LinesLds {
   static constexpr int BX = LT_X + 4, BY = LT_Y + 4;
