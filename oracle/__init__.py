@@ -18,7 +18,9 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "cgks_oracle.c")
 _LIB = os.path.join(_HERE, "libcgks_oracle.so")
 
-BC = {"periodic": 0, "transmissive": 1, "reflective": 2}
+BC = {"periodic": 0, "transmissive": 1, "reflective": 2, "noslip": 3}
+SEG_TYPE = {"transmissive": 1, "reflective": 2, "noslip": 3, "inflow": 4}
+MAXSEG = 3
 TAU = {"zero": 0, "inviscid": 1, "viscous": 2}
 STENCIL = {"S0": 0, "S1": 1, "S2": 2, "R5": 3, "R7": 4, "R9": 5}
 
@@ -33,6 +35,11 @@ def build(force=True):
     return _LIB
 
 
+class Side(ctypes.Structure):
+    _fields_ = [("nseg", ctypes.c_int), ("type", ctypes.c_int * MAXSEG), ("prim", (ctypes.c_double * 4) * MAXSEG),
+                ("end0", ctypes.c_double * MAXSEG), ("speed", ctypes.c_double * MAXSEG)]
+
+
 class Params(ctypes.Structure):
     _fields_ = [
         ("dim", ctypes.c_int), ("nx", ctypes.c_int), ("ny", ctypes.c_int), ("order", ctypes.c_int),
@@ -44,6 +51,8 @@ class Params(ctypes.Structure):
         ("sigma_thres", ctypes.c_double), ("gamma_hi", ctypes.c_double), ("gamma_lo", ctypes.c_double),
         ("weno_eps", ctypes.c_double),
         ("cfl", ctypes.c_double),
+        ("x0", ctypes.c_double), ("y0", ctypes.c_double),
+        ("side", Side * 4),
     ]
 
 
@@ -91,6 +100,31 @@ def gauss_count(order):
     return {5: 2, 7: 3, 9: 4}[order]
 
 
+def _side(spec, side):
+    """Boundary code of one side; a prescribed state or a segmented side is
+    written into ``side`` (code 5).  ``spec``: a name of ``BC``, or
+    {"type": "inflow", "prim": [rho, u, v, p]} (1-D: [rho, u, p]), or
+    {"segments": [...], "ends": [[end0, speed], ...]} with one end per
+    segment but the last (segment k: centres below end0 + speed * t)."""
+    if isinstance(spec, str):
+        return BC[spec]
+    segs = spec["segments"] if "segments" in spec else [spec]
+    ends = spec.get("ends", [])
+    if not 1 <= len(segs) <= MAXSEG or len(ends) != len(segs) - 1:
+        raise ValueError(f"bad boundary segments: {spec}")
+    side.nseg = len(segs)
+    for k, sg in enumerate(segs):
+        name = sg if isinstance(sg, str) else sg["type"]
+        side.type[k] = SEG_TYPE[name]
+        if name == "inflow":
+            for v, x in enumerate(sg["prim"]):
+                side.prim[k][v] = float(x)
+    for k, (e, c) in enumerate(ends):
+        side.end0[k] = float(e)
+        side.speed[k] = float(c)
+    return 5
+
+
 def make_params(grid, scheme):
     """Fill the C parameter block from a problem's grid and scheme dicts."""
     p = Params()
@@ -102,7 +136,9 @@ def make_params(grid, scheme):
     p.dy = (grid["y1"] - grid["y0"]) / p.ny if grid["dim"] == 2 else 1.0
     bc = grid["bc"]
     for k in range(4):
-        p.bc[k] = BC[bc[k]] if k < len(bc) else 0
+        p.bc[k] = _side(bc[k], p.side[k]) if k < len(bc) else 0
+    p.x0 = grid["x0"]
+    p.y0 = grid.get("y0", 0.0)
     p.gamma = scheme.get("gamma", 1.4)
     p.tau_model = TAU[scheme.get("tau", "zero")]
     p.c1 = scheme.get("c1", 0.05)

@@ -37,15 +37,29 @@
 #define NPX 4   /* powers of xi^2 */
 #define HALO 3
 
+/* A side split into segments along its coordinate (y on x-sides, x on
+ * y-sides): segment k holds the cells whose centre lies below
+ * end0[k] + speed[k] t (the first such k; the last segment takes the rest). */
+#define MAXSEG 3
+typedef struct {
+  int nseg;
+  int type[MAXSEG];           /* 1 transmissive, 2 reflective, 3 no-slip wall, 4 prescribed state */
+  double prim[MAXSEG][4];     /* prescribed state: rho, u, v, p (1-D: rho, u, p) */
+  double end0[MAXSEG], speed[MAXSEG];
+} orc_side;
+
 typedef struct {
   int dim, nx, ny, order;
   double dx, dy;
-  int bc[4];          /* x-lo, x-hi, y-lo, y-hi: 0 periodic, 1 transmissive, 2 reflective */
+  int bc[4];          /* x-lo, x-hi, y-lo, y-hi: 0 periodic, 1 transmissive, 2 reflective,
+                         3 no-slip adiabatic wall, 5 segmented (side[k]) */
   double gamma;
   int tau_model;      /* 0: tau = 0, 1: inviscid, 2: viscous */
   double c1, c2, mu, prandtl;
   double sigma_thres, gamma_hi, gamma_lo, weno_eps;
   double cfl;
+  double x0, y0;      /* grid origin: segment ends are absolute coordinates */
+  orc_side side[4];
 } orc_params;
 
 /* ------------------------------------------------------------------------- */
@@ -795,66 +809,134 @@ static int face_src(int F, int n, int bc_lo, int bc_hi) {
   return (bc_hi == 0) ? F - n : 2 * n - F;
 }
 
-/* fill ghost cells: x-ghosts for the interior rows, then y-ghosts for all
- * columns (corners included).  Mirrored ghosts: averages copied, the normal
- * slope negated, the tangential line slopes copied with the Gauss nodes in
- * mirror order; reflective walls also negate the normal momentum. */
-static void fill_state(const orc_params* P, grid_t* g) {
-  const int nv = g->D + 2, m = g->m;
+/* Boundary kind of side s at coordinate c (cell centre along the side) and
+ * time t; a prescribed state is returned in conservative variables. */
+static int side_kind(const orc_params* P, int D, int s, double c, double t, double* cons) {
+  const int b = P->bc[s];
+  if (b != 5) return b;
+  const orc_side* S = &P->side[s];
+  int k = 0;
+  while (k < S->nseg - 1 && !(c < S->end0[k] + S->speed[k] * t)) ++k;
+  if (S->type[k] == 4) {
+    const double* w = S->prim[k];
+    if (D == 2) {
+      cons[0] = w[0]; cons[1] = w[0] * w[1]; cons[2] = w[0] * w[2];
+      cons[3] = w[3] / (P->gamma - 1.0) + 0.5 * w[0] * (w[1] * w[1] + w[2] * w[2]);
+    } else {
+      cons[0] = w[0]; cons[1] = w[0] * w[1];
+      cons[2] = w[2] / (P->gamma - 1.0) + 0.5 * w[0] * w[1] * w[1];
+    }
+  }
+  return S->type[k];
+}
+
+/* cell centres and face positions along the sides */
+static double ctr_y(const orc_params* P, const grid_t* g, int j) { return g->D == 2 ? P->y0 + (j + 0.5) * g->dy : 0.0; }
+static double ctr_x(const orc_params* P, const grid_t* g, int i) { return P->x0 + (i + 0.5) * g->dx; }
+
+/* Momentum components a wall negates: reflective (slip) walls the normal
+ * one, no-slip walls both (the mirrored ghost then has the opposite
+ * velocity, so the wall sees zero velocity; the temperature is mirrored,
+ * so no heat crosses it: adiabatic). */
+static double wall_sign(int kind, int v, int normal_v, int D) {
+  if (kind == 2) return v == normal_v ? -1.0 : 1.0;
+  if (kind == 3) return (v >= 1 && v <= D) ? -1.0 : 1.0;
+  return 1.0;
+}
+
+/* fill ghost cells at time t: x-ghosts for the interior rows, then y-ghosts
+ * for all columns (corners included).  Mirrored ghosts: averages copied, the
+ * normal slope negated, the tangential line slopes copied with the Gauss
+ * nodes in mirror order; walls also negate momentum (wall_sign).  A
+ * prescribed state fills its ghosts with that state and zero slopes. */
+static void fill_state(const orc_params* P, grid_t* g, double t) {
+  const int nv = g->D + 2, m = g->m, D = g->D;
+  double cons[4];
   for (int j = 0; j < g->ny; ++j)
     for (int k = -HALO; k < g->nx + HALO; ++k) {
       if (k >= 0 && k < g->nx) continue;
+      const int kind = side_kind(P, D, k < 0 ? 0 : 1, ctr_y(P, g, j), t, cons);
+      if (kind == 4) {
+        for (int v = 0; v < nv; ++v) {
+          GA(g, v, j, k) = cons[v];
+          for (int l = 0; l < m; ++l) {
+            GSX(g, v, l, j, k) = 0.0;
+            if (D == 2) GSY(g, v, l, j, k) = 0.0;
+          }
+        }
+        continue;
+      }
       int mir, s = src_index(k, g->nx, P->bc[0], P->bc[1], &mir);
-      int refl = mir && ((k < 0 ? P->bc[0] : P->bc[1]) == 2);
       for (int v = 0; v < nv; ++v) {
-        double odd = (refl && v == 1) ? -1.0 : 1.0;
+        double odd = mir ? wall_sign(kind, v, 1, D) : 1.0;
         GA(g, v, j, k) = odd * GA(g, v, j, s);
         for (int l = 0; l < m; ++l) {
           GSX(g, v, l, j, k) = (mir ? -1.0 : 1.0) * odd * GSX(g, v, l, j, s);
-          if (g->D == 2) GSY(g, v, l, j, k) = odd * GSY(g, v, mir ? m - 1 - l : l, j, s);
+          if (D == 2) GSY(g, v, l, j, k) = odd * GSY(g, v, mir ? m - 1 - l : l, j, s);
         }
       }
     }
-  if (g->D == 1) return;
+  if (D == 1) return;
   for (int k = -HALO; k < g->ny + HALO; ++k) {
     if (k >= 0 && k < g->ny) continue;
-    int mir, s = src_index(k, g->ny, P->bc[2], P->bc[3], &mir);
-    int refl = mir && ((k < 0 ? P->bc[2] : P->bc[3]) == 2);
-    for (int i = -HALO; i < g->nx + HALO; ++i)
+    for (int i = -HALO; i < g->nx + HALO; ++i) {
+      const int kind = side_kind(P, D, k < 0 ? 2 : 3, ctr_x(P, g, i), t, cons);
+      if (kind == 4) {
+        for (int v = 0; v < nv; ++v) {
+          GA(g, v, k, i) = cons[v];
+          for (int l = 0; l < m; ++l) { GSY(g, v, l, k, i) = 0.0; GSX(g, v, l, k, i) = 0.0; }
+        }
+        continue;
+      }
+      int mir, s = src_index(k, g->ny, P->bc[2], P->bc[3], &mir);
       for (int v = 0; v < nv; ++v) {
-        double odd = (refl && v == 2) ? -1.0 : 1.0;
+        double odd = mir ? wall_sign(kind, v, 2, D) : 1.0;
         GA(g, v, k, i) = odd * GA(g, v, s, i);
         for (int l = 0; l < m; ++l) {
           GSY(g, v, l, k, i) = (mir ? -1.0 : 1.0) * odd * GSY(g, v, l, s, i);
           GSX(g, v, l, k, i) = odd * GSX(g, v, mir ? m - 1 - l : l, s, i);
         }
       }
+    }
   }
 }
 
-static void fill_sigma(const orc_params* P, grid_t* g) {
-  const int ny = (g->D == 2) ? g->ny : 1;
+/* Ghost faces of the strengths at time t.  Beyond a prescribed state the
+ * ghost cells are uniform, so their faces carry no discontinuity (zero);
+ * otherwise the strengths are mirrored or wrapped like the cells.  In the
+ * ghost rows (columns) a face is judged by the cell that starts at it. */
+static void fill_sigma(const orc_params* P, grid_t* g, double t) {
+  const int ny = (g->D == 2) ? g->ny : 1, D = g->D;
+  double cons[4];
   for (int j = 0; j < ny; ++j)
     for (int F = -HALO; F <= g->nx + HALO; ++F) {
       if (F >= 0 && F <= g->nx) continue;
-      GSIGX(g, j, F) = GSIGX(g, j, face_src(F, g->nx, P->bc[0], P->bc[1]));
+      const int kind = side_kind(P, D, F < 0 ? 0 : 1, ctr_y(P, g, j), t, cons);
+      GSIGX(g, j, F) = kind == 4 ? 0.0 : GSIGX(g, j, face_src(F, g->nx, P->bc[0], P->bc[1]));
     }
   if (g->D == 1) return;
   for (int i = 0; i < g->nx; ++i)
     for (int G = -HALO; G <= g->ny + HALO; ++G) {
       if (G >= 0 && G <= g->ny) continue;
-      GSIGY(g, i, G) = GSIGY(g, i, face_src(G, g->ny, P->bc[2], P->bc[3]));
+      const int kind = side_kind(P, D, G < 0 ? 2 : 3, ctr_x(P, g, i), t, cons);
+      GSIGY(g, i, G) = kind == 4 ? 0.0 : GSIGY(g, i, face_src(G, g->ny, P->bc[2], P->bc[3]));
     }
   /* ghost rows of x-face strengths, ghost columns of y-face strengths */
   for (int k = -HALO; k < g->ny + HALO; ++k) {
     if (k >= 0 && k < g->ny) continue;
     int mir, s = src_index(k, g->ny, P->bc[2], P->bc[3], &mir);
-    for (int F = -HALO; F <= g->nx + HALO; ++F) GSIGX(g, k, F) = GSIGX(g, s, F);
+    for (int F = -HALO; F <= g->nx + HALO; ++F) {
+      const int kind = side_kind(P, D, k < 0 ? 2 : 3, ctr_x(P, g, F), t, cons);
+      GSIGX(g, k, F) = kind == 4 ? 0.0 : GSIGX(g, s, F);
+    }
   }
   for (int k = -HALO; k < g->nx + HALO; ++k) {
     if (k >= 0 && k < g->nx) continue;
     int mir, s = src_index(k, g->nx, P->bc[0], P->bc[1], &mir);
-    for (int G = -HALO; G <= g->ny + HALO; ++G) GSIGY(g, k, G) = GSIGY(g, s, G);
+    for (int G = -HALO; G <= g->ny + HALO; ++G) {
+      const int kind = side_kind(P, D, k < 0 ? 0 : 1, ctr_y(P, g, G), t, cons);
+      GSIGY(g, k, G) = kind == 4 ? 0.0 : GSIGY(g, s, G);
+    }
   }
 }
 
@@ -1166,9 +1248,9 @@ static int state_bad(const orc_params* P, const grid_t* g) {
   return 0;
 }
 
-static void init_sigma(const orc_params* P, grid_t* g) {
+static void init_sigma(const orc_params* P, grid_t* g, double t) {
   const int D = g->D;
-  fill_state(P, g);
+  fill_state(P, g, t);
   for (int j = 0; j < (D == 2 ? g->ny : 1); ++j)
     for (int F = 0; F <= g->nx; ++F) {
       double Wl[4], Wr[4];
@@ -1187,13 +1269,14 @@ static void init_sigma(const orc_params* P, grid_t* g) {
 
 /* one stage: all interface results.  xo: x-faces, yo: y-faces (transposed
  * layout [(i*(ny+1)+G)*m+l], local components) */
-static void stage_faces(const orc_params* P, grid_t* g, double dt, double* xo, double* yo, counters_t* cnt) {
-  fill_state(P, g);
+static void stage_faces(const orc_params* P, grid_t* g, double dt, double tb, double* xo, double* yo,
+                        counters_t* cnt) {
+  fill_state(P, g, tb);
   if (g->D == 1) { faces_1d(P, g, dt, xo, cnt); return; }
   xfaces_2d(P, g, dt, xo, cnt);
   grid_t t;
   transpose_grid(g, &t);
-  fill_state(P, g);  /* the transposed copy already holds the ghosts */
+  fill_state(P, g, tb);  /* the transposed copy already holds the ghosts */
   xfaces_2d(P, &t, dt, yo, cnt);
   free(t.avg); free(t.sx); free(t.sy);
 }
@@ -1238,7 +1321,7 @@ int orc_run(const orc_params* P, double* avg, double* sx, double* sy, double* si
           if (D == 2) GSY(&g, v, l, j, i) = sy[(((size_t)v * m + l) * ny + j) * nx + i];
         }
       }
-  if (init_sig) init_sigma(P, &g);
+  if (init_sig) init_sigma(P, &g, *t_io);
   else {
     for (int j = 0; j < ny; ++j)
       for (int F = 0; F <= nx; ++F) GSIGX(&g, j, F) = sigx[(size_t)j * (nx + 1) + F];
@@ -1267,13 +1350,13 @@ int orc_run(const orc_params* P, double* avg, double* sx, double* sy, double* si
   for (;;) {
     if (nsteps >= 0 && steps >= nsteps) break;
     if (t_end > 0.0 && t >= t_end) break;
-    fill_state(P, &g);
-    fill_sigma(P, &g);
+    fill_state(P, &g, t);
+    fill_sigma(P, &g, t);
     double dt = (dt_fixed > 0.0) ? dt_fixed : cfl_dt(P, &g);
     if (t_end > 0.0 && t + dt > t_end) dt = t_end - t;
 
     /* stage 1 on W^n (Eq. 2.21; Sec. 3.3 slope relations) */
-    stage_faces(P, &g, dt, X1, Y1, &cnt);
+    stage_faces(P, &g, dt, t, X1, Y1, &cnt);
     for (int j = 0; j < ny; ++j)
       for (int i = 0; i < nx; ++i)
         for (int v = 0; v < nv; ++v) {
@@ -1316,7 +1399,7 @@ int orc_run(const orc_params* P, double* avg, double* sx, double* sy, double* si
     if (state_bad(P, &gs)) status = 4;
 
     /* stage 2 on W* with the same dt and the old strengths (A28) */
-    stage_faces(P, &gs, dt, X2, Y2, &cnt);
+    stage_faces(P, &gs, dt, t + 0.5 * dt, X2, Y2, &cnt);   /* boundary data at the stage time */
     for (int j = 0; j < ny; ++j)
       for (int i = 0; i < nx; ++i)
         for (int v = 0; v < nv; ++v) {

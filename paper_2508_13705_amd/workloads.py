@@ -287,6 +287,90 @@ def quadrant_random(seed=3, n=1024, order=7, nsteps=200):
 CONFIG3 = [(0.138, 1.206, 1.206, 0.029), (0.5323, 0.0, 1.206, 0.3), (1.5, 0.0, 0.0, 1.5), (0.5323, 1.206, 0.0, 0.3)]
 
 
+# ---------------------------------------------------------------------------
+# Wall, inflow and moving boundaries (Sec. 4.8-4.10).  A side is a name
+# ("periodic", "transmissive", "reflective", "noslip"), a prescribed state
+# {"type": "inflow", "prim": [rho, u, v, p]}, or {"segments": [...], "ends":
+# [[end0, speed], ...]}: segment k holds the ghost cells whose centre (along
+# the side: y on x-sides, x on y-sides) lies below end0 + speed * t.
+# Discontinuous initial data crossing cells: each cell takes the state at its
+# centre; zero slopes.
+# ---------------------------------------------------------------------------
+
+def _inflow(prim):
+    return {"type": "inflow", "prim": [float(x) for x in prim]}
+
+
+def _piecewise_2d(nx, ny, x0, x1, y0, y1, region, states, gamma, order, bc, name, t_end, tau, cfl, **scheme_kw):
+    """region(X, Y) -> index into states (rho, u, v, p) at the cell centres."""
+    m = GAUSS_M[order]
+    dx, dy, xc, yc = _grid2(nx, ny, x0, x1, y0, y1)
+    X, Y = np.meshgrid(xc, yc)
+    q = region(X, Y)
+    S = np.asarray(states, dtype=np.float64)
+    rho, u, v, p = (S[q, k] for k in range(4))
+    avg = _cons(rho, u, v, p, gamma, 2)
+    return {"name": name,
+            "grid": {"dim": 2, "nx": nx, "ny": ny, "x0": x0, "x1": x1, "y0": y0, "y1": y1, "bc": bc},
+            "scheme": default_scheme(order, gamma=gamma, tau=tau, cfl=cfl, **scheme_kw),
+            "state": {"avg": avg, "sx": np.zeros((4, m, ny, nx)), "sy": np.zeros((4, m, ny, nx))},
+            "run": {"nsteps": -1, "dt": 0.0, "t_end": t_end}}
+
+
+# Mach 10 shock at 60 degrees to the wall (Sec. 4.8)
+DMR_PRE = (1.4, 0.0, 0.0, 1.0)
+DMR_POST = (8.0, 8.25 * math.cos(math.pi / 6), -8.25 * math.sin(math.pi / 6), 116.5)
+
+
+def double_mach(ny=240, order=5, t_end=0.2, cfl=0.5):
+    """[0, 4] x [0, 1], 4 ny x ny cells.  The shock meets the bottom at
+    x = 1/6 and stands at x = 1/6 + (y + 20 t)/sqrt(3).  Left: post-shock
+    inflow; right: transmissive; bottom: post-shock for x < 1/6, reflecting
+    wall beyond; top: post-shock behind the exact shock position, pre-shock
+    ahead of it (a breakpoint moving at 20/sqrt(3))."""
+    r3 = math.sqrt(3.0)
+    bc = [_inflow(DMR_POST), "transmissive",
+          {"segments": [_inflow(DMR_POST), "reflective"], "ends": [[1.0 / 6.0, 0.0]]},
+          {"segments": [_inflow(DMR_POST), _inflow(DMR_PRE)], "ends": [[1.0 / 6.0 + 1.0 / r3, 20.0 / r3]]}]
+    region = lambda X, Y: np.where(X < 1.0 / 6.0 + Y / r3, 1, 0)
+    return _piecewise_2d(4 * ny, ny, 0.0, 4.0, 0.0, 1.0, region, [DMR_PRE, DMR_POST], 1.4, order, bc,
+                         f"double_mach_n{ny}_o{order}", t_end, "inviscid", cfl)
+
+
+def viscous_shock_tube(nx=500, order=5, t_end=1.0, re=200.0, cfl=0.5):
+    """[0, 1] x [0, 0.5], nx x nx/2 cells; a membrane at x = 0.5 separates
+    (120, 0, 0, 120/gamma) from (1.2, 0, 0, 1.2/gamma); mu = 1/Re, Pr = 1.
+    No-slip adiabatic walls left, right and bottom; symmetry (slip) on top."""
+    g = 1.4
+    bc = ["noslip", "noslip", "noslip", "reflective"]
+    region = lambda X, Y: np.where(X < 0.5, 0, 1)
+    return _piecewise_2d(nx, nx // 2, 0.0, 1.0, 0.0, 0.5, region, [(120.0, 0.0, 0.0, 120.0 / g), (1.2, 0.0, 0.0, 1.2 / g)],
+                         g, order, bc, f"viscous_shock_tube_n{nx}_o{order}", t_end, "viscous", cfl, mu=1.0 / re,
+                         prandtl=1.0)
+
+
+JETS = {
+    # Sec. 4.10: (domain x1, y1), jet band on the left side, jet state, t_end, cells
+    80: dict(x1=2.0, y1=1.0, band=(0.45, 0.55), jet=(5.0, 30.0, 0.0, 0.4127), t_end=0.07, nx=448),
+    2000: dict(x1=1.0, y1=0.5, band=(0.2, 0.3), jet=(5.0, 800.0, 0.0, 0.4127), t_end=1e-3, nx=800),
+}
+JET_AMBIENT = (0.5, 0.0, 0.0, 0.4127)
+
+
+def jet(mach=80, nx=None, order=5, cfl=0.5):
+    """Ambient gas (gamma = 5/3) at rest; the left side prescribes the jet
+    state inside the band and the ambient state outside it; the other sides
+    are outflow (transmissive)."""
+    d = JETS[mach]
+    nx = nx or d["nx"]
+    ny = nx // 2
+    bc = [{"segments": [_inflow(JET_AMBIENT), _inflow(d["jet"]), _inflow(JET_AMBIENT)],
+           "ends": [[d["band"][0], 0.0], [d["band"][1], 0.0]]}, "transmissive", "transmissive", "transmissive"]
+    region = lambda X, Y: np.zeros(X.shape, dtype=int)
+    return _piecewise_2d(nx, ny, 0.0, d["x1"], 0.0, d["y1"], region, [JET_AMBIENT], 5.0 / 3.0, order, bc,
+                         f"jet_mach{mach}_n{nx}_o{order}", d["t_end"], "inviscid", cfl)
+
+
 def _spectral_velocity(seed, n, kmax, urms):
     """Solenoidal random-phase field on the unit periodic square: stream
     function modes on integer wavevectors 1 <= |k| <= kmax with shell energy
