@@ -46,19 +46,53 @@ typedef enum {
   CGKS_EBUDGET = 6          /* batch: the job does not fit the memory budget or the slot table */
 } cgks_status;
 
-enum { CGKS_BC_PERIODIC = 0, CGKS_BC_TRANSMISSIVE = 1, CGKS_BC_REFLECTIVE = 2 };
+/* Boundary kinds of a side.  Transmissive, reflective and no-slip ghosts
+ * mirror the interior cells: reflective (slip) walls negate the normal
+ * momentum, no-slip adiabatic walls both momentum components (the wall sees
+ * zero velocity and, the temperature being mirrored, no heat flux; the
+ * walls of the viscous shock tube, Sec. 4.9).  A prescribed state (inflow)
+ * fills the ghosts with that state and zero slopes (the jets' nozzle and
+ * the post-shock inflow of the double Mach reflection, Sec. 4.8, 4.10).  A
+ * segmented side applies different kinds along the side, with breakpoints
+ * that may move at constant speed (the double Mach reflection's bottom and
+ * its top boundary, which follows the exact shock). */
+enum {
+  CGKS_BC_PERIODIC = 0,
+  CGKS_BC_TRANSMISSIVE = 1,
+  CGKS_BC_REFLECTIVE = 2,
+  CGKS_BC_NOSLIP = 3,
+  CGKS_BC_INFLOW = 4,       /* prescribed state: side[k].prim[0] */
+  CGKS_BC_SEGMENTED = 5     /* side[k] */
+};
 enum { CGKS_TAU_ZERO = 0, CGKS_TAU_INVISCID = 1, CGKS_TAU_VISCOUS = 2 };
 enum { CGKS_FP64 = 0, CGKS_FP32_FLUX = 1 };
 
+#define CGKS_MAX_SEGMENTS 3
+
+/* One side split along its coordinate (y on the x-sides, x on the y-sides;
+ * absolute coordinates).  Segment k < nseg - 1 holds the ghost cells whose
+ * centre lies below end0[k] + speed[k] t (the first such k, t the time the
+ * ghosts are filled for: the start of the step, or of its second stage);
+ * the last segment holds the rest.  Strengths of ghost faces beyond a
+ * prescribed state are zero (its ghosts are uniform). */
+typedef struct {
+  int nseg;                                   /* 1..CGKS_MAX_SEGMENTS */
+  int type[CGKS_MAX_SEGMENTS];                /* TRANSMISSIVE, REFLECTIVE, NOSLIP or INFLOW */
+  double prim[CGKS_MAX_SEGMENTS][4];          /* INFLOW: rho, u, v, p (1-D: rho, u, p); rho, p > 0 */
+  double end0[CGKS_MAX_SEGMENTS - 1];
+  double speed[CGKS_MAX_SEGMENTS - 1];
+} cgks_bc_side;
+
 /* Uniform grid.  dim = 1: ny must be 1 and bc[2], bc[3] are ignored.
  * nx, ny >= 5 (the widest stencil); a periodic direction must be periodic on
- * both ends.  Transmissive and reflective ghosts mirror the interior cells
- * (reflective walls also negate the normal momentum). */
+ * both ends (periodic sides cannot be segmented).  side[k] is read only when
+ * bc[k] is CGKS_BC_INFLOW (segment 0's state) or CGKS_BC_SEGMENTED. */
 typedef struct {
   int dim;                  /* 1 or 2 */
   int nx, ny;               /* cells per direction */
   double x0, x1, y0, y1;    /* domain [x0, x1] x [y0, y1] */
   int bc[4];                /* x-lo, x-hi, y-lo, y-hi: CGKS_BC_* */
+  cgks_bc_side side[4];
 } cgks_grid_desc;
 
 /* Scheme parameters (Sec. 3.1, 3.2 and 4).  order 5, 7, 9 uses m = 2, 3, 4

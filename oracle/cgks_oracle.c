@@ -1228,6 +1228,19 @@ static double cfl_dt(const orc_params* P, const grid_t* g) {
       if (s > smax) smax = s;
       if (W[0] < rmin) rmin = W[0];
     }
+  /* prescribed boundary states enter through the boundary faces every step:
+   * their signal speed bounds the step too (reading of the CFL condition) */
+  for (int k = 0; k < (D == 2 ? 4 : 2); ++k) {
+    if (P->bc[k] != 5) continue;
+    const orc_side* S = &P->side[k];
+    for (int q = 0; q < S->nseg; ++q) {
+      if (S->type[q] != 4) continue;
+      const double* w = S->prim[q];
+      double u = w[1], v = (D == 2) ? w[2] : 0.0, pr = (D == 2) ? w[3] : w[2];
+      double sp = sqrt(u * u + v * v) + sqrt(P->gamma * pr / w[0]);
+      if (sp > smax) smax = sp;
+    }
+  }
   double h = (D == 2 && g->dy < g->dx) ? g->dy : g->dx;
   double dt = h / smax;
   if (P->tau_model == 2 && P->mu > 0.0) {

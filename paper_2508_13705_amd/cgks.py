@@ -14,7 +14,9 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.environ.get("CGKS_LIB", os.path.join(_HERE, "libcgks.so"))
 
 OK, EINVAL, ENOMEM, EHIP, ENONPHYSICAL, ESTATE, EBUDGET = range(7)
-BC = {"periodic": 0, "transmissive": 1, "reflective": 2}
+BC = {"periodic": 0, "transmissive": 1, "reflective": 2, "noslip": 3}
+BC_INFLOW, BC_SEGMENTED = 4, 5
+MAX_SEGMENTS = 3
 TAU = {"zero": 0, "inviscid": 1, "viscous": 2}
 PRECISION = {"fp64": 0, "fp32_flux": 1}
 GAUSS_M = {5: 2, 7: 3, 9: 4}
@@ -34,10 +36,51 @@ class CgksError(RuntimeError):
         self.status = status
 
 
+class BcSide(ctypes.Structure):
+    _fields_ = [("nseg", ctypes.c_int), ("type", ctypes.c_int * MAX_SEGMENTS),
+                ("prim", (ctypes.c_double * 4) * MAX_SEGMENTS),
+                ("end0", ctypes.c_double * (MAX_SEGMENTS - 1)), ("speed", ctypes.c_double * (MAX_SEGMENTS - 1))]
+
+
 class GridDesc(ctypes.Structure):
     _fields_ = [("dim", ctypes.c_int), ("nx", ctypes.c_int), ("ny", ctypes.c_int),
                 ("x0", ctypes.c_double), ("x1", ctypes.c_double), ("y0", ctypes.c_double), ("y1", ctypes.c_double),
-                ("bc", ctypes.c_int * 4)]
+                ("bc", ctypes.c_int * 4), ("side", BcSide * 4)]
+
+
+_SEG_KIND = {"transmissive": 1, "reflective": 2, "noslip": 3, "inflow": BC_INFLOW}
+
+
+def bc_code(spec, side):
+    """Code of one side for cgks_grid_desc.bc; a prescribed state or a
+    segmented side also fills ``side``.  ``spec``: "periodic",
+    "transmissive", "reflective", "noslip", {"type": "inflow", "prim": [rho,
+    u, v, p]} (1-D: [rho, u, p]), or {"segments": [...], "ends": [[end0,
+    speed], ...]} (segment k < last: cell centres below end0 + speed t)."""
+    if isinstance(spec, str):
+        return BC[spec]
+    if "segments" not in spec:
+        if spec.get("type") != "inflow":
+            raise ValueError(f"unknown boundary {spec}")
+        side.nseg = 1
+        side.type[0] = BC_INFLOW
+        for v, x in enumerate(spec["prim"]):
+            side.prim[0][v] = float(x)
+        return BC_INFLOW
+    segs, ends = spec["segments"], spec.get("ends", [])
+    side.nseg = len(segs)
+    for k, sg in enumerate(segs[:MAX_SEGMENTS]):
+        kind = sg if isinstance(sg, str) else sg["type"]
+        side.type[k] = _SEG_KIND[kind]
+        if kind == "inflow":
+            for v, x in enumerate(sg["prim"]):
+                side.prim[k][v] = float(x)
+    for k, (e, c) in enumerate(ends[:MAX_SEGMENTS - 1]):
+        side.end0[k] = float(e)
+        side.speed[k] = float(c)
+    if len(ends) != len(segs) - 1:
+        side.nseg = 0      # rejected by the library
+    return BC_SEGMENTED
 
 
 class SchemeDesc(ctypes.Structure):
@@ -132,7 +175,7 @@ def descriptors(problem, precision="fp64"):
     gd.x0, gd.x1 = g["x0"], g["x1"]
     gd.y0, gd.y1 = g.get("y0", 0.0), g.get("y1", 1.0)
     for k in range(4):
-        gd.bc[k] = BC[g["bc"][k]] if k < len(g["bc"]) else 0
+        gd.bc[k] = bc_code(g["bc"][k], gd.side[k]) if k < len(g["bc"]) else 0
     sd = SchemeDesc()
     sd.order = s["order"]
     sd.gamma = s.get("gamma", 1.4)

@@ -31,17 +31,19 @@ __global__ void k_init_sigma(Geo g, int which, double gam, const double* U, doub
   }
 }
 
-__global__ void k_bc_state(Geo g, double* U) {
-  bc_state_at(g, U, blockIdx.x * blockDim.x + threadIdx.x, blockIdx.y);
+// code: the time the ghosts are for (bc_time)
+__global__ void k_bc_state(Geo g, const BcTable* T, const Header* hdr, int code, double* U) {
+  bc_state_at(g, T, bc_time(hdr, code), U, blockIdx.x * blockDim.x + threadIdx.x, blockIdx.y);
 }
 
-__global__ void k_bc_sigma(Geo g, int which, const double* sxn, double* sxo, const double* syn, double* syo) {
-  bc_sigma_at(g, which, sxn, sxo, syn, syo, blockIdx.x * blockDim.x + threadIdx.x, blockIdx.y);
+__global__ void k_bc_sigma(Geo g, const BcTable* T, const Header* hdr, int which, const double* sxn, double* sxo,
+                           const double* syn, double* syo) {
+  bc_sigma_at(g, T, bc_time(hdr, 1), which, sxn, sxo, syn, syo, blockIdx.x * blockDim.x + threadIdx.x, blockIdx.y);
 }
 
-__global__ void k_dt(Header* hdr, const double* part, double dt_fixed, double cfl, double t_end, double h, double mu,
+__global__ void k_dt(Header* hdr, const double* part, double sbc, double dt_fixed, double cfl, double t_end, double h, double mu,
                      int viscous) {
-  dt_block(hdr, part, dt_fixed, cfl, t_end, h, mu, viscous, 0, nullptr);
+  dt_block(hdr, part, sbc, dt_fixed, cfl, t_end, h, mu, viscous, 0, nullptr);
 }
 
 // Block (x, y) of a 2-D grid as the dispatcher orders it (x fastest) goes to
@@ -116,10 +118,11 @@ struct Marks {
 static inline void tick(Marks* mk, hipStream_t st) {
   if (mk) mk->tick(st);
 }
-hipError_t launch_bc_state(const cgks_plan* p, double* U, hipStream_t st, Marks* mk = nullptr) {
+hipError_t launch_bc_state(const cgks_plan* p, const Bufs& b, double* U, int code, hipStream_t st,
+                           Marks* mk = nullptr) {
   const Geo& g = p->g;
   dim3 grid((g.NX + 255) / 256, g.NY);
-  hipLaunchKernelGGL(k_bc_state, grid, dim3(256), 0, st, g, U);
+  hipLaunchKernelGGL(k_bc_state, grid, dim3(256), 0, st, g, b.bct, b.hdr, code, U);
   tick(mk, st);
   return hipGetLastError();
 }
@@ -127,10 +130,10 @@ hipError_t launch_bc_state(const cgks_plan* p, double* U, hipStream_t st, Marks*
 hipError_t launch_bc_sigma(const cgks_plan* p, const Bufs& b, hipStream_t st, Marks* mk = nullptr) {
   const Geo& g = p->g;
   dim3 gx((g.NX + 1 + 255) / 256, g.NY);
-  hipLaunchKernelGGL(k_bc_sigma, gx, dim3(256), 0, st, g, 0, b.sxn, b.sxo, b.syn, b.syo);
+  hipLaunchKernelGGL(k_bc_sigma, gx, dim3(256), 0, st, g, b.bct, b.hdr, 0, b.sxn, b.sxo, b.syn, b.syo);
   if (g.dim == 2) {
     dim3 gy((g.NY + 1 + 255) / 256, g.NX);
-    hipLaunchKernelGGL(k_bc_sigma, gy, dim3(256), 0, st, g, 1, b.sxn, b.sxo, b.syn, b.syo);
+    hipLaunchKernelGGL(k_bc_sigma, gy, dim3(256), 0, st, g, b.bct, b.hdr, 1, b.sxn, b.sxo, b.syn, b.syo);
   }
   tick(mk, st);
   return hipGetLastError();
@@ -192,16 +195,16 @@ hipError_t enqueue_step(const cgks_plan* p, const Bufs& b, double dt, double cfl
   const Geo& g = p->g;
   const double h = g.dim == 2 ? fmin(p->dx, p->dy) : p->dx;
   tick(mk, st);
-  hipLaunchKernelGGL(k_dt, dim3(1), dim3(256), 0, st, b.hdr, b.part, dt, cfl, t_end, h, p->C.mu,
+  hipLaunchKernelGGL(k_dt, dim3(1), dim3(256), 0, st, b.hdr, b.part, p->bct.smax, dt, cfl, t_end, h, p->C.mu,
                      p->C.tau_model == CGKS_TAU_VISCOUS ? 1 : 0);
   tick(mk, st);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   if ((e = launch_bc_sigma(p, b, st, mk)) != hipSuccess) return e;
-  if ((e = launch_bc_state(p, b.U, st, mk)) != hipSuccess) return e;
+  if ((e = launch_bc_state(p, b, b.U, 1, st, mk)) != hipSuccess) return e;
   e = p->precision == CGKS_FP64 ? launch_stage<double>(p, b, 1, st, mk) : launch_stage<float>(p, b, 1, st, mk);
   if (e != hipSuccess) return e;
-  if ((e = launch_bc_state(p, b.S, st, mk)) != hipSuccess) return e;
+  if ((e = launch_bc_state(p, b, b.S, 2, st, mk)) != hipSuccess) return e;
   return p->precision == CGKS_FP64 ? launch_stage<double>(p, b, 2, st, mk) : launch_stage<float>(p, b, 2, st, mk);
 }
 
@@ -275,8 +278,27 @@ cgks_status cgks_plan_create(const cgks_grid_desc* gd, const cgks_scheme_desc* s
   if (gd->nx < 5 || (gd->dim == 2 && gd->ny < 5)) return fail(CGKS_EINVAL, "need at least 5 cells per direction");
   if (gd->dim == 1 && gd->ny != 1) return fail(CGKS_EINVAL, "1-D grids need ny = 1");
   if (!(gd->x1 > gd->x0) || (gd->dim == 2 && !(gd->y1 > gd->y0))) return fail(CGKS_EINVAL, "empty domain");
-  for (int k = 0; k < (gd->dim == 2 ? 4 : 2); ++k)
-    if (gd->bc[k] < 0 || gd->bc[k] > 2) return fail(CGKS_EINVAL, "unknown boundary condition");
+  for (int k = 0; k < (gd->dim == 2 ? 4 : 2); ++k) {
+    const int b = gd->bc[k];
+    if (b < CGKS_BC_PERIODIC || b > CGKS_BC_SEGMENTED) return fail(CGKS_EINVAL, "unknown boundary condition");
+    if (b != CGKS_BC_INFLOW && b != CGKS_BC_SEGMENTED) continue;
+    const cgks_bc_side& S = gd->side[k];
+    const int ns = b == CGKS_BC_INFLOW ? 1 : S.nseg;
+    if (ns < 1 || ns > CGKS_MAX_SEGMENTS) return fail(CGKS_EINVAL, "a segmented side needs 1 to 3 segments");
+    for (int q = 0; q < ns; ++q) {
+      const int ty = b == CGKS_BC_INFLOW ? CGKS_BC_INFLOW : S.type[q];
+      if (ty < CGKS_BC_TRANSMISSIVE || ty > CGKS_BC_INFLOW) return fail(CGKS_EINVAL, "unknown segment kind");
+      if (ty == CGKS_BC_INFLOW) {
+        const double* w = S.prim[q];
+        const double rho = w[0], pr = gd->dim == 2 ? w[3] : w[2];
+        for (int v = 0; v < 4; ++v)
+          if (!std::isfinite(w[v])) return fail(CGKS_EINVAL, "prescribed state must be finite");
+        if (!(rho > 0.0) || !(pr > 0.0)) return fail(CGKS_EINVAL, "prescribed state needs rho > 0 and p > 0");
+      }
+    }
+    for (int q = 0; q + 1 < ns; ++q)
+      if (!std::isfinite(S.end0[q]) || !std::isfinite(S.speed[q])) return fail(CGKS_EINVAL, "segment ends must be finite");
+  }
   if ((gd->bc[0] == CGKS_BC_PERIODIC) != (gd->bc[1] == CGKS_BC_PERIODIC))
     return fail(CGKS_EINVAL, "periodic x needs both ends periodic");
   if (gd->dim == 2 && (gd->bc[2] == CGKS_BC_PERIODIC) != (gd->bc[3] == CGKS_BC_PERIODIC))
@@ -305,6 +327,46 @@ cgks_status cgks_plan_create(const cgks_grid_desc* gd, const cgks_scheme_desc* s
   g.cells = (size_t)g.NX * g.NY;
   p->dx = (gd->x1 - gd->x0) / gd->nx;
   p->dy = gd->dim == 2 ? (gd->y1 - gd->y0) / gd->ny : 1.0;
+  // sides with a prescribed state or segments: one table (kernels see code
+  // SEGMENTED); prescribed states in conservative variables
+  p->bct.x0 = gd->x0;
+  p->bct.y0 = gd->dim == 2 ? gd->y0 : 0.0;
+  p->bct.dx = p->dx;
+  p->bct.dy = p->dy;
+  for (int k = 0; k < 4; ++k) {
+    if (g.bc[k] != CGKS_BC_INFLOW && g.bc[k] != CGKS_BC_SEGMENTED) continue;
+    const cgks_bc_side& S = gd->side[k];
+    BcSide& T = p->bct.side[k];
+    T.nseg = g.bc[k] == CGKS_BC_INFLOW ? 1 : S.nseg;
+    for (int q = 0; q < T.nseg; ++q) {
+      T.type[q] = g.bc[k] == CGKS_BC_INFLOW ? CGKS_BC_INFLOW : S.type[q];
+      if (T.type[q] != CGKS_BC_INFLOW) continue;
+      const double* w = S.prim[q];
+      const double gm1 = sd->gamma - 1.0;
+      if (gd->dim == 2) {
+        T.cons[q][0] = w[0];
+        T.cons[q][1] = w[0] * w[1];
+        T.cons[q][2] = w[0] * w[2];
+        T.cons[q][3] = w[3] / gm1 + 0.5 * w[0] * (w[1] * w[1] + w[2] * w[2]);
+      } else {
+        T.cons[q][0] = w[0];
+        T.cons[q][1] = w[0] * w[1];
+        T.cons[q][2] = w[2] / gm1 + 0.5 * w[0] * w[1] * w[1];
+      }
+    }
+    for (int q = 0; q < T.nseg; ++q) {
+      if (T.type[q] != CGKS_BC_INFLOW) continue;
+      const double* w = S.prim[q];
+      const double u = w[1], v = gd->dim == 2 ? w[2] : 0.0, pr = gd->dim == 2 ? w[3] : w[2];
+      const double sp = sqrt(u * u + v * v) + sqrt(sd->gamma * pr / w[0]);
+      if (sp > p->bct.smax) p->bct.smax = sp;
+    }
+    for (int q = 0; q + 1 < T.nseg; ++q) {
+      T.end0[q] = S.end0[q];
+      T.speed[q] = S.speed[q];
+    }
+    g.bc[k] = CGKS_BC_SEGMENTED;
+  }
   Consts& C = p->C;
   C.gamma = sd->gamma;
   C.Kd = 2.0 / (sd->gamma - 1.0);
@@ -350,6 +412,7 @@ cgks_status cgks_plan_create(const cgks_grid_desc* gd, const cgks_scheme_desc* s
   }
   p->off_part = o; o += up(2 * p->max_parts);
   p->off_hdr = o; o += 32;
+  p->off_bct = o; o += up((sizeof(BcTable) + 7) / 8);
   p->work_words = o;
   *out = p;
   return CGKS_OK;
@@ -411,7 +474,8 @@ cgks_status cgks_init_state(const cgks_plan* p, void* d_state, void* d_work, con
   hh.magic = kMagic;
   hh.active = 1;
   HIP_TRY(hipMemcpyAsync(b.hdr, &hh, sizeof(hh), hipMemcpyHostToDevice, st));
-  HIP_TRY(launch_bc_state(p, b.U, st));
+  HIP_TRY(hipMemcpyAsync((void*)b.bct, &p->bct, sizeof(BcTable), hipMemcpyHostToDevice, st));
+  HIP_TRY(launch_bc_state(p, b, b.U, 0, st));
   if (h_sigma_x) {
     std::vector<double> sx(p->sig_x_words, 0.0), sy(p->sig_y_words, 0.0);
     for (int j = 0; j < ny; ++j)

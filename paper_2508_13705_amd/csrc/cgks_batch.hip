@@ -31,6 +31,7 @@ struct BJob {
   Consts C;
   Bufs B;
   double dt_fixed, cfl, t_end, h;
+  double sbc;              // largest |U| + c of the job's prescribed boundary states
   long long max_steps;
   int viscous, M, slot, pad;
   int ax, ay, as;          // 256-wide segments per row: sigma x-faces, sigma y-faces, state rows
@@ -81,7 +82,7 @@ __global__ __launch_bounds__(256) void kb_dt(const BTab* tab) {
   const int n = tab->njobs;
   for (int j = blockIdx.x; j < n; j += gridDim.x) {
     const BJob J = tab->jobs[j];
-    dt_block(J.B.hdr, J.B.part, J.dt_fixed, J.cfl, J.t_end, J.h, J.C.mu, J.viscous, J.max_steps,
+    dt_block(J.B.hdr, J.B.part, J.sbc, J.dt_fixed, J.cfl, J.t_end, J.h, J.C.mu, J.viscous, J.max_steps,
              tab->stat + J.slot);
   }
 }
@@ -91,16 +92,18 @@ __global__ __launch_bounds__(256) void kb_prep(const BTab* tab, int remap) {
   for_items(tab, PH_PREP, remap, [&](const BJob& J, int k) {
     if (!J.B.hdr->active) return;
     if (k < J.nsx) {
-      bc_sigma_at(J.g, 0, J.B.sxn, J.B.sxo, J.B.syn, J.B.syo, (k % J.ax) * 256 + threadIdx.x, k / J.ax);
+      bc_sigma_at(J.g, J.B.bct, bc_time(J.B.hdr, 1), 0, J.B.sxn, J.B.sxo, J.B.syn, J.B.syo,
+                  (k % J.ax) * 256 + threadIdx.x, k / J.ax);
       return;
     }
     k -= J.nsx;
     if (k < J.nsy) {
-      bc_sigma_at(J.g, 1, J.B.sxn, J.B.sxo, J.B.syn, J.B.syo, (k % J.ay) * 256 + threadIdx.x, k / J.ay);
+      bc_sigma_at(J.g, J.B.bct, bc_time(J.B.hdr, 1), 1, J.B.sxn, J.B.sxo, J.B.syn, J.B.syo,
+                  (k % J.ay) * 256 + threadIdx.x, k / J.ay);
       return;
     }
     k -= J.nsy;
-    bc_state_at(J.g, J.B.U, (k % J.as) * 256 + threadIdx.x, k / J.as);
+    bc_state_at(J.g, J.B.bct, bc_time(J.B.hdr, 1), J.B.U, (k % J.as) * 256 + threadIdx.x, k / J.as);
   });
 }
 
@@ -108,7 +111,7 @@ __global__ __launch_bounds__(256) void kb_prep(const BTab* tab, int remap) {
 __global__ __launch_bounds__(256) void kb_bcs(const BTab* tab, int remap) {
   for_items(tab, PH_BCS, remap, [&](const BJob& J, int k) {
     if (!J.B.hdr->active) return;
-    bc_state_at(J.g, J.B.S, (k % J.as) * 256 + threadIdx.x, k / J.as);
+    bc_state_at(J.g, J.B.bct, bc_time(J.B.hdr, 2), J.B.S, (k % J.as) * 256 + threadIdx.x, k / J.as);
   });
 }
 
@@ -431,6 +434,7 @@ cgks_status cgks_batch_add(cgks_batch* b, const cgks_plan* p, void* d_state, voi
   J.cfl = cfl;
   J.t_end = t_end;
   J.h = p->g.dim == 2 ? fmin(p->dx, p->dy) : p->dx;
+  J.sbc = p->bct.smax;
   J.max_steps = max_steps;
   J.viscous = p->C.tau_model == CGKS_TAU_VISCOUS ? 1 : 0;
   J.M = p->g.m;

@@ -69,6 +69,7 @@ inline cgks_status check_private(const void* kernel, size_t limit, const char* w
 struct Header {
   double t;
   double dt;
+  double tn;       // start time of the current step (t before its dt was added)
   unsigned long long smax_bits;
   unsigned long long rmin_bits;
   unsigned long long steps;
@@ -80,6 +81,22 @@ struct Header {
   int pad[14];
 };
 static_assert(sizeof(Header) <= 256, "header");
+
+// Segmented sides (and prescribed states), as the plan normalises them:
+// segment k < nseg - 1 holds the ghost cells whose centre along the side is
+// below end0[k] + speed[k] t; cons is a prescribed state in conservative
+// variables.  Kept in the work buffer, so a job carries its own copy.
+struct BcSide {
+  int nseg;
+  int type[3];
+  double cons[3][4];
+  double end0[3], speed[3];
+};
+struct BcTable {
+  double x0, y0, dx, dy;   // cell centres: x0 + (i + 1/2) dx, y0 + (j + 1/2) dy
+  double smax;             // largest |U| + c of the prescribed states (0: none)
+  BcSide side[4];
+};
 
 // Per-job progress record of a batch, written by the dt phase each step.
 struct JobStat {
@@ -123,6 +140,7 @@ struct Bufs {
   double* lvy;
   double* part;   // per-block [max(|U|+c), min(rho)] of the last reduction
   Header* hdr;
+  const BcTable* bct;
 };
 
 }  // namespace
@@ -133,8 +151,9 @@ struct cgks_plan {
   int precision;
   double dx, dy;
   size_t state_words, sig_x_words, sig_y_words;
-  size_t off_S, off_A, off_sxo, off_sxn, off_syo, off_syn, off_lvx, off_lvy, off_part, off_hdr, work_words;
+  size_t off_S, off_A, off_sxo, off_sxn, off_syo, off_syn, off_lvx, off_lvy, off_part, off_hdr, off_bct, work_words;
   size_t max_parts;
+  BcTable bct;     // copied into the work buffer by cgks_init_state
 };
 
 namespace {
@@ -153,6 +172,7 @@ Bufs bufs(const cgks_plan* p, void* d_state, void* d_work) {
   b.lvy = w + p->off_lvy;
   b.part = w + p->off_part;
   b.hdr = (Header*)(w + p->off_hdr);
+  b.bct = (const BcTable*)(w + p->off_bct);
   return b;
 }
 
@@ -184,20 +204,68 @@ __device__ __forceinline__ int src_face(int F, int n, int lo, int hi) {
 // (periodic).  Mirrored: averages copied, the slope normal to the mirror
 // negated, slopes along Gauss lines crossing the mirror taken at the mirrored
 // Gauss point; a reflective wall also makes the normal momentum odd.
-__device__ __forceinline__ void bc_state_at(const Geo& g, double* U, int I, int J) {
+// Time the ghosts are filled for: 0 the initial state (t), 1 the first stage
+// and the strengths (the step's start), 2 the second stage (start + dt/2).
+__device__ __forceinline__ double bc_time(const Header* hdr, int code) {
+  return code == 0 ? hdr->t : (code == 1 ? hdr->tn : hdr->tn + 0.5 * hdr->dt);
+}
+
+// Kind of side s for the ghosts whose centre along the side is c, at time
+// t; a prescribed state is returned through cons.
+__device__ __forceinline__ int side_kind(const Geo& g, const BcTable* T, int s, double c, double t,
+                                         const double*& cons) {
+  // selected, not indexed: a runtime index into a kernel's private copy of
+  // the grid descriptor would put that copy in scratch memory
+  const int b = s == 0 ? g.bc[0] : (s == 1 ? g.bc[1] : (s == 2 ? g.bc[2] : g.bc[3]));
+  if (b != CGKS_BC_SEGMENTED) return b;
+  const BcSide& S = T->side[s];
+  int k = 0;
+  while (k < S.nseg - 1 && !(c < S.end0[k] + S.speed[k] * t)) ++k;
+  cons = S.cons[k];
+  return S.type[k];
+}
+
+// Sign a wall gives component v of a mirrored ghost (normal momentum: nv_n).
+__device__ __forceinline__ double wall_sign(int kind, int v, int nv_n, int D) {
+  if (kind == CGKS_BC_REFLECTIVE) return v == nv_n ? -1.0 : 1.0;
+  if (kind == CGKS_BC_NOSLIP) return (v >= 1 && v <= D) ? -1.0 : 1.0;
+  return 1.0;
+}
+
+// Ghost cell (I, J) (padded indices) at time tb.  A ghost row of a y-side
+// takes that side's rule at the column's centre; its source cell, or an
+// x-ghost of an interior row, takes the x-side rule at the row's centre
+// (corners compose both).  Mirrored ghosts copy the averages, negate the
+// normal slope and reverse the order of the tangential line slopes; walls
+// add their momentum signs.  A prescribed state gives that state and zero
+// slopes.
+__device__ __forceinline__ void bc_state_at(const Geo& g, const BcTable* T, double tb, double* U, int I, int J) {
   if (I >= g.NX) return;
   const int i = I - H, j = (g.dim == 2) ? J - H : 0;
   const bool gx = (i < 0 || i >= g.nx), gy = (g.dim == 2) && (j < 0 || j >= g.ny);
   if (!gx && !gy) return;
-  int mx, my = 0;
-  const int si = src_cell(i, g.nx, g.bc[0], g.bc[1], mx);
-  const int sj = (g.dim == 2) ? src_cell(j, g.ny, g.bc[2], g.bc[3], my) : 0;
-  const bool rx = mx && (g.bc[i < 0 ? 0 : 1] == CGKS_BC_REFLECTIVE);
-  const bool ry = my && (g.bc[j < 0 ? 2 : 3] == CGKS_BC_REFLECTIVE);
+  const double* cons = nullptr;
+  int my = 0, sj = j, ky = CGKS_BC_PERIODIC;
+  if (gy) {
+    ky = side_kind(g, T, j < 0 ? 2 : 3, T->x0 + (i + 0.5) * T->dx, tb, cons);
+    if (ky != CGKS_BC_INFLOW) sj = src_cell(j, g.ny, g.bc[2], g.bc[3], my);
+  }
+  int mx = 0, si = i, kx = CGKS_BC_PERIODIC;
+  if (ky != CGKS_BC_INFLOW && gx) {
+    kx = side_kind(g, T, i < 0 ? 0 : 1, g.dim == 2 ? T->y0 + (sj + 0.5) * T->dy : 0.0, tb, cons);
+    if (kx != CGKS_BC_INFLOW) si = src_cell(i, g.nx, g.bc[0], g.bc[1], mx);
+  }
+  const bool fixed = ky == CGKS_BC_INFLOW || kx == CGKS_BC_INFLOW;
   for (int v = 0; v < g.nv; ++v) {
-    double odd = 1.0;
-    if (rx && v == 1) odd = -odd;
-    if (ry && v == 2) odd = -odd;
+    const double odd = (mx ? wall_sign(kx, v, 1, g.dim) : 1.0) * (my ? wall_sign(ky, v, 2, g.dim) : 1.0);
+    if (fixed) {   // a prescribed state, seen through a y-mirror when the x-side prescribes it
+      U[g.avg(v, i, j)] = odd * cons[v];
+      for (int l = 0; l < g.m; ++l) {
+        U[g.sx(v, l, i, j)] = 0.0;
+        if (g.dim == 2) U[g.sy(v, l, i, j)] = 0.0;
+      }
+      continue;
+    }
     U[g.avg(v, i, j)] = odd * U[g.avg(v, si, sj)];
     for (int l = 0; l < g.m; ++l) {
       const int lx = my ? g.m - 1 - l : l;   // x-slope lines are horizontal: mirrored by a y-mirror
@@ -212,24 +280,55 @@ __device__ __forceinline__ void bc_state_at(const Geo& g, double* U, int I, int 
 
 
 // Commit the strengths computed in the previous step (new -> old) and fill
-// the ghost faces and ghost rows/columns of the old set.
-__device__ __forceinline__ void bc_sigma_at(const Geo& g, int which, const double* sxn, double* sxo,
-                                            const double* syn, double* syo, int a, int b) {
+// the ghost faces and ghost rows/columns of the old set at time tb.  Faces
+// beyond a prescribed state are zero (its ghosts are uniform); in a ghost row
+// (column) a face is judged by the cell that starts at it.
+__device__ __forceinline__ void bc_sigma_at(const Geo& g, const BcTable* T, double tb, int which,
+                                            const double* sxn, double* sxo, const double* syn, double* syo,
+                                            int a, int b) {
+  const double* cons = nullptr;
   if (which == 0) {
     // x-faces: a = F + H in [0, NX], b = row J
     if (a > g.NX) return;
     const int F = a - H, j = (g.dim == 2) ? b - H : 0;
-    int my = 0;
-    const int sj = (g.dim == 2) ? src_cell(j, g.ny, g.bc[2], g.bc[3], my) : 0;
-    const int sF = src_face(F, g.nx, g.bc[0], g.bc[1]);
+    int my = 0, sj = j;
+    if (g.dim == 2 && (j < 0 || j >= g.ny)) {
+      if (side_kind(g, T, j < 0 ? 2 : 3, T->x0 + (F + 0.5) * T->dx, tb, cons) == CGKS_BC_INFLOW) {
+        sxo[g.sgx(j, F)] = 0.0;
+        return;
+      }
+      sj = src_cell(j, g.ny, g.bc[2], g.bc[3], my);
+    }
+    int sF = F;
+    if (F < 0 || F > g.nx) {
+      if (side_kind(g, T, F < 0 ? 0 : 1, g.dim == 2 ? T->y0 + (sj + 0.5) * T->dy : 0.0, tb, cons) ==
+          CGKS_BC_INFLOW) {
+        sxo[g.sgx(j, F)] = 0.0;
+        return;
+      }
+      sF = src_face(F, g.nx, g.bc[0], g.bc[1]);
+    }
     sxo[g.sgx(j, F)] = sxn[g.sgx(sj, sF)];
   } else {
     // y-faces: a = G + H in [0, NY], b = column I
     if (a > g.NY) return;
     const int G = a - H, i = b - H;
-    int mx = 0;
-    const int si = src_cell(i, g.nx, g.bc[0], g.bc[1], mx);
-    const int sG = src_face(G, g.ny, g.bc[2], g.bc[3]);
+    int mx = 0, si = i;
+    if (i < 0 || i >= g.nx) {
+      if (side_kind(g, T, i < 0 ? 0 : 1, T->y0 + (G + 0.5) * T->dy, tb, cons) == CGKS_BC_INFLOW) {
+        syo[g.sgy(i, G)] = 0.0;
+        return;
+      }
+      si = src_cell(i, g.nx, g.bc[0], g.bc[1], mx);
+    }
+    int sG = G;
+    if (G < 0 || G > g.ny) {
+      if (side_kind(g, T, G < 0 ? 2 : 3, T->x0 + (si + 0.5) * T->dx, tb, cons) == CGKS_BC_INFLOW) {
+        syo[g.sgy(i, G)] = 0.0;
+        return;
+      }
+      sG = src_face(G, g.ny, g.bc[2], g.bc[3]);
+    }
     syo[g.sgy(i, G)] = syn[g.sgy(si, sG)];
   }
 }
@@ -287,7 +386,9 @@ __device__ __forceinline__ bool cell_speed(const double* W, int D, double gam, d
 // One block: reduce the speed partials, then dt, the active flag, time and
 // step count; max_steps > 0 stops the run after that many steps.  The
 // optional progress record gets t, dt, steps and the status.
-__device__ void dt_block(Header* hdr, const double* part, double dt_fixed, double cfl, double t_end, double h,
+// sbc: largest |U| + c of prescribed boundary states, which enter through
+// the boundary faces every step and so bound the step like the cells do.
+__device__ void dt_block(Header* hdr, const double* part, double sbc, double dt_fixed, double cfl, double t_end, double h,
                          double mu, int viscous, long long max_steps, JobStat* stat) {
   __shared__ double red[2][256];
   __syncthreads();
@@ -310,7 +411,7 @@ __device__ void dt_block(Header* hdr, const double* part, double dt_fixed, doubl
   if (threadIdx.x != 0) return;
   double dt = dt_fixed;
   if (!(dt > 0.0)) {
-    dt = cfl * h / red[0][0];
+    dt = cfl * h / fmax(red[0][0], sbc);
     if (viscous && mu > 0.0) {
       const double dv = cfl * h * h * red[1][0] / (4.0 * mu);
       if (dv < dt) dt = dv;
@@ -325,6 +426,7 @@ __device__ void dt_block(Header* hdr, const double* part, double dt_fixed, doubl
   }
   hdr->dt = dt;
   hdr->active = active;
+  hdr->tn = hdr->t;   // the step's start: boundary data of its stages are taken at tn and tn + dt/2
   if (active) {
     hdr->t += dt;
     hdr->steps += 1;

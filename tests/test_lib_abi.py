@@ -50,6 +50,11 @@ def test_plan_sizes_match_layout():
     (lambda g, s: g.update(bc=["periodic", "transmissive", "periodic", "periodic"]), "periodic"),
     (lambda g, s: s.update(prandtl=0.0), "prandtl"),
     (lambda g, s: s.update(sigma_thres=0.0), "sigma_thres"),
+    (lambda g, s: g["bc"].__setitem__(0, {"type": "inflow", "prim": [-1.0, 0.0, 0.0, 1.0]}), "rho > 0"),
+    (lambda g, s: g["bc"].__setitem__(0, {"type": "inflow", "prim": [1.0, 0.0, 0.0, 0.0]}), "p > 0"),
+    (lambda g, s: g["bc"].__setitem__(2, {"segments": ["reflective", "noslip"], "ends": []}), "segments"),
+    (lambda g, s: g["bc"].__setitem__(2, {"segments": ["reflective", "noslip"], "ends": [[float("nan"), 0.0]]}),
+     "finite"),
 ])
 def test_plan_rejects_bad_descriptors(mutate, frag):
     pb = workloads.quadrant_2d(workloads.CONFIG3, 12, 7, nsteps=1)
@@ -88,3 +93,9 @@ def test_batch_calls_reject_null_batch():
     assert L.cgks_batch_launch(None, None) == cgks.EINVAL
     assert L.cgks_batch_remove(None, 0) == cgks.EINVAL
     assert L.cgks_batch_destroy(None) == cgks.OK
+
+
+def test_plan_accepts_wall_inflow_and_moving_sides():
+    for pb in (workloads.double_mach(12), workloads.viscous_shock_tube(20), workloads.jet(80, 24)):
+        p = _plan(pb)
+        assert p.work_bytes > 0
