@@ -101,3 +101,23 @@ def test_batch_with_boundaries_equals_alone(precision):
         alone = cgks.Solver(pb, precision=precision)
         alone.step(k)
         _same(s.read(), alone.read())
+
+
+def test_noslip_order7_breakdown_matches_oracle():
+    """The viscous shock tube's no-slip bottom at Re = 200 and 500 cells
+    across (tau/dt ~ 50), order 7: the mirrored no-slip ghosts make the cells
+    by the wall at the diaphragm nonphysical within 21 steps, in the oracle
+    as here; both stop on the same step (a physical outcome, recorded by the
+    sticky nonphysical flag)."""
+    from paper_2508_13705_amd import cgks
+    g = 1.4
+    reg = lambda X, Y: np.where(X < 0.5, 0, 1)
+    pb = W._piecewise_2d(500, 6, 0.0, 1.0, 0.0, 6 / 500, reg, [(120.0, 0.0, 0.0, 120.0 / g), (1.2, 0.0, 0.0, 1.2 / g)],
+                         g, 7, ["noslip", "noslip", "noslip", "reflective"], "vst_strip", 0.0, "viscous", 0.5,
+                         mu=1.0 / 200, prandtl=1.0)
+    ref = oracle.run(pb, nsteps=40, t_end=0.0)
+    s = cgks.Solver(pb)
+    s.step(40)
+    got = s.read(sync_only=True)
+    assert ref["status"] == 4 and got["status"] == cgks.ENONPHYSICAL
+    assert got["steps"] == ref["stats"]["steps"]
