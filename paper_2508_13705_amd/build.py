@@ -11,6 +11,10 @@ OBJ = os.path.join(HERE, "_build")
 SOURCES = ["cgks.hip", "cgks_batch.hip"]
 
 HIPCC_FLAGS = ["-O3", "--offload-arch=gfx950", "-std=c++17", "-fPIC",
+               # multiply-adds fused only within a source expression: every
+               # kernel that inlines the same device function then does the
+               # same arithmetic (batched jobs equal the jobs alone, bit for bit)
+               "-ffp-contract=on",
                # no packed FP32 instructions anywhere in this library
                "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 

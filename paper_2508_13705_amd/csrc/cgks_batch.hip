@@ -72,9 +72,13 @@ __device__ __forceinline__ void for_items(const BTab* tab, int ph, int remap, F&
   const int n = tab->njobs;
   const int* pre = tab->pre + (size_t)ph * (tab->cap + 1);
   for (int item = lb; item < total; item += G) {
-    const int j = find_job(pre, n, item);
-    const BJob J = tab->jobs[j];   // a private copy: the tile's stores cannot alias it
-    f(J, item - pre[j]);
+    // the job and tile are the same for the whole block: made wave-uniform,
+    // the job descriptor comes through scalar loads instead of occupying
+    // vector registers
+    const int j = __builtin_amdgcn_readfirstlane(find_job(pre, n, item));
+    const int k = __builtin_amdgcn_readfirstlane(item - pre[j]);
+    const BJob& J = tab->jobs[j];
+    f(J, k);
   }
 }
 
@@ -123,9 +127,9 @@ __global__ __launch_bounds__(256) void kb_lines(const BTab* tab, int stage, int 
     const double* Uin = stage == 1 ? J.B.U : J.B.S;
     const int bx = k % J.ltx, by = k / J.ltx;
     switch (J.M) {
-      case 2: lines_tile<2>(J.g, J.C, Uin, J.B.sxo, J.B.syo, J.B.lvx, J.B.lvy, bx, by, sm); break;
-      case 3: lines_tile<3>(J.g, J.C, Uin, J.B.sxo, J.B.syo, J.B.lvx, J.B.lvy, bx, by, sm); break;
-      default: lines_tile<4>(J.g, J.C, Uin, J.B.sxo, J.B.syo, J.B.lvx, J.B.lvy, bx, by, sm); break;
+      case 2: lines_tile<2, true>(J.g, J.C, Uin, J.B.sxo, J.B.syo, J.B.lvx, J.B.lvy, bx, by, sm); break;
+      case 3: lines_tile<3, true>(J.g, J.C, Uin, J.B.sxo, J.B.syo, J.B.lvx, J.B.lvy, bx, by, sm); break;
+      default: lines_tile<4, true>(J.g, J.C, Uin, J.B.sxo, J.B.syo, J.B.lvx, J.B.lvy, bx, by, sm); break;
     }
   });
 }
@@ -139,7 +143,7 @@ __global__ __launch_bounds__(256, 1) void kb_face(const BTab* tab, int remap) {
     const int nbx = J.fnb[DIR][0], nby = J.fnb[DIR][1];
     // neighbours along x first (x-faces: normal-first, y-faces: tangential-first)
     const int bx = DIR == 0 ? k % nbx : k / nby, by = DIR == 0 ? k / nbx : k % nby;
-    face2d_tile<DIR, STAGE, M, T, false>(J.g, J.C, J.B, smem, bx, by, nbx, nby);
+    face2d_tile<DIR, STAGE, M, T, false, 32, false>(J.g, J.C, J.B, smem, bx, by, nbx, nby);
   });
 }
 

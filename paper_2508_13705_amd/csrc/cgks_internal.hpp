@@ -448,6 +448,17 @@ __device__ void dt_block(Header* hdr, const double* part, double sbc, double dt_
 // 2-D Step 1 (Sec. 3.3): tangential ASE-DFF in each column (row) gives the
 // line averages of the cell on the horizontal (vertical) Gauss lines.
 // ---------------------------------------------------------------------------
+// The thread index as a value the compiler cannot prove loop-invariant.  In
+// the persistent batched kernels a tile body sits inside the job loop; with
+// the plain index the compiler hoists every lane decomposition of the tile
+// out of that loop and holds it in registers through all phases.  The empty
+// asm statement emits no instruction.
+__device__ __forceinline__ int tile_tid() {
+  int t = threadIdx.x;
+  asm volatile("" : "+v"(t));
+  return t;
+}
+
 // Step 1 over a tile of LT_X x LT_Y cells (x fastest; block of 256 threads,
 // one cell each) with its inputs staged in LDS: the cell averages on the
 // tile and a border of two cells, the cell-averaged normal gradients (line
@@ -469,7 +480,7 @@ struct LinesLds {
 };
 static_assert(LT_X * LT_Y == 256, "one cell per thread");
 
-template <int M>
+template <int M, bool PERSIST = false>
 __device__ __forceinline__ void lines_tile(const Geo& g, const Consts& C, const double* U, const double* sxo,
                                            const double* syo, double* lvx, double* lvy, int bx, int by,
                                            double* sm) {
@@ -481,7 +492,7 @@ __device__ __forceinline__ void lines_tile(const Geo& g, const Consts& C, const 
   double* sx = sy + L::NSY;
   __syncthreads();   // a persistent caller's previous tile has finished with the LDS
   const int i0 = -H + bx * LT_X, j0 = -H + by * LT_Y;
-  const int tid = threadIdx.x;
+  const int tid = PERSIST ? tile_tid() : (int)threadIdx.x;
   auto ci = [&](int i) { return i < -H ? -H : (i > g.nx + H - 1 ? g.nx + H - 1 : i); };
   auto cj = [&](int j) { return j < -H ? -H : (j > g.ny + H - 1 ? g.ny + H - 1 : j); };
   double wq[4];
@@ -652,7 +663,7 @@ template <typename T> struct FaceWaves {
 // with a barrier so the LDS of the previous tile is free).  SU: staging passes
 // whose loads are issued together (all of them where registers allow; the
 // persistent batched kernels keep more per-job state live and take fewer).
-template <int DIR, int STAGE, int M, typename T, bool PR, int SU = 32>
+template <int DIR, int STAGE, int M, typename T, bool PR, int SU = 32, bool PERSIST = false>
 __device__ void face2d_tile(const Geo& g, const Consts& C, const Bufs& B, unsigned char* smem, int bx, int by,
                             int nbx, int nby) {
   using TL = Tile<M>;
@@ -660,6 +671,8 @@ __device__ void face2d_tile(const Geo& g, const Consts& C, const Bufs& B, unsign
   const Header* hdr = B.hdr;
   __syncthreads();
   if (!hdr->active) return;
+  // persistent callers: an index the compiler cannot hoist out of their loop
+  const int tx = PERSIST ? tile_tid() : (int)threadIdx.x;
   const double dt = hdr->dt;
   T* s2v = (T*)smem;
   T* s2d = (T*)(smem + Lds<M, T>::s2v);
@@ -710,7 +723,7 @@ __device__ void face2d_tile(const Geo& g, const Consts& C, const Bufs& B, unsign
     // walk the planes (array, variable, Gauss line), PPP planes per pass
     constexpr int PL = NR * NCS, PPP = 256 / PL, NPL = 2 * 4 * M;
     static_assert(PPP >= 1, "a plane fits one pass");
-    const int tid = threadIdx.x;
+    const int tid = tx;
     const int lp = tid / PL < PPP ? tid / PL : PPP - 1;   // lanes past the last plane slot repeat it
     const int e = tid % PL;
     const int cc = DIR == 0 ? e % NCS : e / NR, r = DIR == 0 ? e / NCS : e % NR;
@@ -731,7 +744,7 @@ __device__ void face2d_tile(const Geo& g, const Consts& C, const Bufs& B, unsign
     // normal strengths of the staged faces, and the tangential DFF factors of
     // the Step 3 states (cell F0-1+c, line T0+r): one item of each per lane
     static_assert(NR * NSG <= 256 && NC * NT <= 256, "one pass");
-    const int it = threadIdx.x;
+    const int it = tx;
     {
       const int k = it < NR * NSG ? it : 0;
       const int ff = DIR == 0 ? k % NSG : k / NR, r = DIR == 0 ? k / NSG : k % NR;
@@ -757,7 +770,7 @@ __device__ void face2d_tile(const Geo& g, const Consts& C, const Bufs& B, unsign
   // recomputes a valid item of the tile (c = r = 1, l = 0) and stores nothing.
   constexpr int NA = NC * NR * M;
   for (int base = 0; base < NA; base += 256) {
-    const int it = base + (int)threadIdx.x;
+    const int it = base + tx;
     int c, r, l;
     if (DIR == 0) { c = it % NC; r = (it / NC) % NR; l = it / (NC * NR); }
     else { r = it % NR; c = (it / NR) % NC; l = it / (NC * NR); }
@@ -796,14 +809,19 @@ __device__ void face2d_tile(const Geo& g, const Consts& C, const Bufs& B, unsign
 
   // ---- Steps 3-4 at every face Gauss point: one Gauss point per thread ----
   static_assert(NB <= 256, "one Gauss point per thread of a 256-thread block");
-  // as in Step 2, lanes without a Gauss point of their own compute the
-  // tile's first one (f = r = l = 0, always inside the grid) and store nothing
-  const int it = threadIdx.x;
+  // as in Step 2, lanes without a Gauss point of their own compute one of the
+  // tile's (f = r = 0 at their wave's node l, always inside the grid) and
+  // store nothing
+  const int it = tx;
   int f, r, l;
   if (DIR == 0) { f = it % NF; r = (it / NF) % NT; l = it / (NF * NT); }
   else { r = it % NT; f = (it / NT) % NF; l = it / (NF * NT); }
+  // a wave holds one Gauss node when NF NT is a multiple of 64 (m = 2, 4):
+  // l is then wave-uniform, and the tangential-fit weights of that node are
+  // scalar loads
+  if ((NF * NT) % 64 == 0) l = __builtin_amdgcn_readfirstlane(l);
   const bool own = it < NB && F0 + f <= nmax && T0 + r < tmax;
-  if (!own) { f = 0; r = 0; l = 0; }
+  if (!own) { f = 0; r = 0; }   // keeps l: Gauss point (0, 0, l) lies in the tile
   {
     const int nf = F0 + f, t = T0 + r;
     T Wk[2][6][4];
@@ -870,7 +888,7 @@ __device__ void face2d_tile(const Geo& g, const Consts& C, const Bufs& B, unsign
 
   // ---- strengths of this step (stage 1): mean over the Gauss points ----
   if (STAGE == 1) {
-    for (int it = threadIdx.x; it < NF * NT; it += blockDim.x) {
+    for (int it = tx; it < NF * NT; it += blockDim.x) {
       const int f = DIR == 0 ? it % NF : it / NT, r = DIR == 0 ? it / NF : it % NT;
       const int nf = F0 + f, t = T0 + r;
       if (nf > nmax || t >= tmax) continue;
@@ -883,7 +901,7 @@ __device__ void face2d_tile(const Geo& g, const Consts& C, const Bufs& B, unsign
   // ---- cell update of this direction ----
   const double ihn = 1.0 / hn;
   constexpr int NFT = (NF - 1) * NT;   // updated cells of the tile
-  for (int it = threadIdx.x; it < (NF - 1) * NT * 4; it += blockDim.x) {
+  for (int it = tx; it < (NF - 1) * NT * 4; it += blockDim.x) {
     int ci, r, v;
     if (DIR == 0) { ci = it % (NF - 1); r = (it / (NF - 1)) % NT; v = it / ((NF - 1) * NT); }
     else { r = it % NT; ci = (it / NT) % (NF - 1); v = it / ((NF - 1) * NT); }
@@ -934,7 +952,7 @@ __device__ void face2d_tile(const Geo& g, const Consts& C, const Bufs& B, unsign
   if (DIR == 1) {
     __syncthreads();
     // health and (stage 2) the speed reduction for the next time step
-    const int it = threadIdx.x;
+    const int it = tx;
     bool valid = false;
     double s = 0.0, rr = 1.0;
     if (it < (NF - 1) * NT) {

@@ -55,7 +55,7 @@ def test_parity_with_oracle(name, make, nsteps, precision, tol):
     assert got["status"] == ref["status"] == 0
     assert got["steps"] == nsteps
     # FP32-flux states give slightly different CFL steps
-    assert abs(got["t"] - ref["t"]) <= (1e-12 if precision == "fp64" else 1e-6) * ref["t"]
+    assert abs(got["t"] - ref["t"]) <= (1e-12 if precision == "fp64" else 1e-5) * ref["t"]
     e = _relerr(got["avg"], ref["avg"])
     _say(f"  rel-L1 {e:.3e} (bar {tol:g})")
     assert e <= tol, e
