@@ -118,14 +118,18 @@ def bench_batch_1d(jobs, steps, precision, graph_steps=10):
     B.commit()
     tuning = B.tune(1)
     B.capture(graph_steps)
+    B.launch()        # the first replays upload the graph
     B.launch()
     st0 = B.poll()
     reps = max(1, steps // graph_steps)
+    # timed: the replays until the stream drains; the progress records are
+    # read afterwards (building the per-job dicts can meet a Python GC pause)
     t0 = time.perf_counter()
     for _ in range(reps):
         B.launch()
-    st1 = B.poll()
+    stream.synchronize()
     el = time.perf_counter() - t0
+    st1 = B.poll()
     upd = sum(cells[k] * (st1[k]["steps"] - st0[k]["steps"]) for k in cells)
     active = sum(1 for k in cells if st1[k]["status"] == 0)
     nonphys = sum(1 for k in cells if st1[k]["status"] == 2)

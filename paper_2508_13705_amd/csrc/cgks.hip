@@ -82,7 +82,8 @@ __global__ __launch_bounds__(256, FaceWaves<T>::value) void k_face2d(Geo g, Cons
 template <int STAGE, typename T, bool PR>
 __global__ __launch_bounds__(256) void k_stage1d(Geo g, Consts C, Bufs B) {
   __shared__ double res[256][12];
-  stage1d_seg<STAGE, T, PR>(g, C, B, res, blockIdx.x, gridDim.x);
+  __shared__ __align__(16) unsigned char sm[Lds1D<T>::total];
+  stage1d_seg<STAGE, T, PR>(g, C, B, res, sm, blockIdx.x, gridDim.x);
 }
 
 __global__ void k_reduce(Geo g, double gam, const double* U, Bufs B) {
@@ -170,7 +171,7 @@ template <typename T, bool PR>
 hipError_t launch_stage_pr(const cgks_plan* p, const Bufs& b, int stage, hipStream_t st, Marks* mk) {
   const Geo& g = p->g;
   if (g.dim == 1) {
-    dim3 grid((g.nx + 254) / 255);
+    dim3 grid((g.nx + S1_CELLS - 1) / S1_CELLS);
     if (stage == 1) hipLaunchKernelGGL((k_stage1d<1, T, PR>), grid, dim3(256), 0, st, g, p->C, b);
     else hipLaunchKernelGGL((k_stage1d<2, T, PR>), grid, dim3(256), 0, st, g, p->C, b);
     tick(mk, st);
@@ -402,7 +403,7 @@ cgks_status cgks_plan_create(const cgks_grid_desc* gd, const cgks_scheme_desc* s
   {
     // partials: the initial reduction grid, the 1-D stage grid, the 2-D y-face grid
     size_t a = (size_t)((g.nx + 255) / 256) * (g.dim == 2 ? g.ny : 1);
-    size_t b1 = (size_t)((g.nx + 254) / 255);
+    size_t b1 = (size_t)((g.nx + S1_CELLS - 1) / S1_CELLS);
     size_t c = 0;
     if (g.dim == 2) {
       const int NT = g.m == 2 ? 8 : (g.m == 3 ? 5 : 4);

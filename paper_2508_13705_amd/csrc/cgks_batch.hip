@@ -151,8 +151,9 @@ __global__ __launch_bounds__(256, 1) void kb_face(const BTab* tab, int remap) {
 template <int STAGE, typename T>
 __global__ __launch_bounds__(256) void kb_stage1d(const BTab* tab, int remap) {
   __shared__ double res[256][12];
+  __shared__ __align__(16) unsigned char sm[Lds1D<T>::total];
   for_items(tab, PH_S1D, remap,
-            [&](const BJob& J, int k) { stage1d_seg<STAGE, T, false>(J.g, J.C, J.B, res, k, J.nseg); });
+            [&](const BJob& J, int k) { stage1d_seg<STAGE, T, false>(J.g, J.C, J.B, res, sm, k, J.nseg); });
 }
 
 // Kernel slots of the persistent launches (grid sizes are per slot).
@@ -178,6 +179,7 @@ struct cgks_batch {
   BJob* djobs = nullptr;
   int* dpre = nullptr;
   JobStat* dstat = nullptr;
+  JobStat* hstat = nullptr;  // pinned host copy of the progress records (cgks_batch_poll)
   size_t off_stat = 0, table_bytes = 0;
   std::vector<unsigned char> staging;
   hipStream_t cap_stream = nullptr;
@@ -309,7 +311,7 @@ void fill_counts(BJob& J) {
     J.nseg = 0;
   } else {
     J.fnb[0][0] = J.fnb[0][1] = J.fnb[1][0] = J.fnb[1][1] = 0;
-    J.nseg = (g.nx + 254) / 255;
+    J.nseg = (g.nx + S1_CELLS - 1) / S1_CELLS;
   }
 }
 
@@ -378,7 +380,9 @@ cgks_status cgks_batch_create(int dim, int precision, int max_jobs, size_t hbm_b
     e = precision == CGKS_FP64 ? occupancy<double>(b) : occupancy<float>(b);
   }
   if (e == hipSuccess) e = hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipHostMalloc((void**)&b->hstat, sizeof(JobStat) * max_jobs, hipHostMallocDefault);
   if (e != hipSuccess) {
+    if (b->cap_stream) hipStreamDestroy(b->cap_stream);
     if (b->dmem) hipFree(b->dmem);
     delete b;
     return fail(CGKS_EHIP, std::string("batch create: ") + hipGetErrorString(e));
@@ -391,6 +395,8 @@ cgks_status cgks_batch_create(int dim, int precision, int max_jobs, size_t hbm_b
   try {
     b->staging.assign(b->table_bytes, 0);
   } catch (...) {
+    hipHostFree(b->hstat);
+    hipStreamDestroy(b->cap_stream);
     hipFree(b->dmem);
     delete b;
     return fail(CGKS_ENOMEM, "batch staging");
@@ -404,6 +410,7 @@ cgks_status cgks_batch_destroy(cgks_batch* b) {
   if (!b) return CGKS_OK;
   drop_graph(b);
   if (b->cap_stream) hipStreamDestroy(b->cap_stream);
+  if (b->hstat) hipHostFree(b->hstat);
   if (b->dmem) hipFree(b->dmem);
   delete b;
   return CGKS_OK;
@@ -554,8 +561,9 @@ cgks_status cgks_batch_launch(cgks_batch* b, void* stream) {
 cgks_status cgks_batch_poll(cgks_batch* b, cgks_job_status* out, void* stream) {
   if (!b || !out) return fail(CGKS_EINVAL, "NULL argument");
   hipStream_t st = (hipStream_t)stream;
-  std::vector<JobStat> hs(b->cap);
-  HIP_TRY(hipMemcpyAsync(hs.data(), b->dstat, sizeof(JobStat) * b->cap, hipMemcpyDeviceToHost, st));
+  // into pinned memory (a copy into pageable memory goes through a staging buffer)
+  const JobStat* hs = b->hstat;
+  HIP_TRY(hipMemcpyAsync(b->hstat, b->dstat, sizeof(JobStat) * b->cap, hipMemcpyDeviceToHost, st));
   HIP_TRY(hipStreamSynchronize(st));
   for (int k = 0; k < b->cap; ++k) {
     out[k].in_use = b->busy[k];

@@ -972,47 +972,98 @@ __device__ void face2d_tile(const Geo& g, const Consts& C, const Bufs& B, unsign
 
 
 // ---------------------------------------------------------------------------
-// 1-D stage kernel: one thread per face; each reconstructs its two cells.
-// A block owns faces F0..F0+255 and updates cells F0..F0+254.
+// 1-D stage kernel.  A block owns faces F0 .. F0+S1_FACES-1 and updates cells
+// F0 .. F0+S1_FACES-2.  Phases, separated by barriers: the segment's inputs
+// to LDS in one batch of loads; one thread per cell reconstructs both of its
+// faces (cells F0-1 .. F0+S1_FACES-1, one per thread); one thread per face
+// takes its two states and computes the flux; the update.
 // ---------------------------------------------------------------------------
+constexpr int S1_FACES = 255;                  // faces per block
+constexpr int S1_CELLS = S1_FACES - 1;         // updated cells per block
+constexpr int S1_NS = S1_FACES + 5;            // staged cells F0-3 .. F0+S1_FACES+1
+constexpr int S1_NG = S1_FACES + 6;            // staged faces F0-3 .. F0+S1_FACES+2
+// LDS of a segment (bytes, for element type T): averages and h-scaled slopes
+// [v][S1_NS] (T), strengths [S1_NG] (double), reconstructions [cell][side][k][v] (T)
+template <typename T> struct Lds1D {
+  static constexpr size_t avg = 0;
+  static constexpr size_t slo = avg + 3 * S1_NS * sizeof(T);
+  static constexpr size_t sig = (slo + 3 * S1_NS * sizeof(T) + 7) / 8 * 8;
+  static constexpr size_t rec = sig + S1_NG * sizeof(double);
+  static constexpr size_t total = rec + 256 * 18 * sizeof(T);
+};
+
 template <int STAGE, typename T, bool PR>
-__device__ void stage1d_seg(const Geo& g, const Consts& C, const Bufs& B, double (*res)[12], int seg, int nseg) {
+__device__ void stage1d_seg(const Geo& g, const Consts& C, const Bufs& B, double (*res)[12], unsigned char* sm,
+                            int seg, int nseg) {
   const Header* hdr = B.hdr;
   __syncthreads();
   if (!hdr->active) return;
   const double dt = hdr->dt;
-  constexpr int NFB = 256;
-  const int F0 = seg * (NFB - 1);
-  const int f = threadIdx.x;
-  const int F = F0 + f;
+  const int F0 = seg * S1_CELLS;
+  const int t = threadIdx.x;
   const double* Uin = STAGE == 1 ? B.U : B.S;
   const double h = C.dx;
-  // wave-uniform, as in the 2-D tile: lanes past the last face compute the
-  // last face again and store nothing
-  const bool own = F <= g.nx;
-  const int Fc = own ? F : g.nx;
+  T* sa = (T*)(sm + Lds1D<T>::avg);
+  T* ss = (T*)(sm + Lds1D<T>::slo);
+  double* sg = (double*)(sm + Lds1D<T>::sig);
+  T* rc = (T*)(sm + Lds1D<T>::rec);
+  // ---- inputs: staged cell c at F0-3+c, face q at F0-3+q (clamped into the
+  // stored grid; no owned item reads a clamped entry); all lanes load ----
+  auto clampc = [&](int x) { return x < -H ? -H : (x > g.nx + H - 1 ? g.nx + H - 1 : x); };
+#pragma unroll
+  for (int base = 0; base < 3 * S1_NS; base += 256) {
+    const int k = base + t < 3 * S1_NS ? base + t : 3 * S1_NS - 1;
+    const int v = k / S1_NS, c = k % S1_NS;
+    const int cell = clampc(F0 - 3 + c);
+    const T a = T(Uin[g.avg(v, cell, 0)]);
+    const T sl = T(h * Uin[g.sx(v, 0, cell, 0)]);
+    if (base + t < 3 * S1_NS) { sa[v * S1_NS + c] = a; ss[v * S1_NS + c] = sl; }
+  }
+#pragma unroll
+  for (int base = 0; base < S1_NG; base += 256) {
+    const int q = base + t < S1_NG ? base + t : S1_NG - 1;
+    const int face = F0 - 3 + q;
+    const double sv = B.sxo[g.sgx(0, face < -H ? -H : (face > g.nx + H ? g.nx + H : face))];
+    if (base + t < S1_NG) sg[q] = sv;
+  }
+  __syncthreads();
+  // ---- reconstruction: cell F0-1+t (staged index t+2), both faces ----
+  {
+    double s[6];
+#pragma unroll
+    for (int q = 0; q < 6; ++q) s[q] = sg[t + q];           // faces cell-2 .. cell+3
+    const Cascade cs = cascade(s, C.order, C.thres);
+    T d[3][9];
+#pragma unroll
+    for (int v = 0; v < 3; ++v) {
+#pragma unroll
+      for (int k = 0; k < 5; ++k) d[v][k] = sa[v * S1_NS + t + k];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) d[v][5 + k] = ss[v * S1_NS + t + (k < 2 ? k : k + 1)];   // cells -2, -1, +1, +2
+    }
+    T out[2][3][3];
+    recon_faces<T, 3>(d, cs, C, out);
+#pragma unroll
+    for (int sd = 0; sd < 2; ++sd)
+#pragma unroll
+      for (int k = 0; k < 3; ++k)
+#pragma unroll
+        for (int v = 0; v < 3; ++v) rc[((t * 2 + sd) * 3 + k) * 3 + v] = out[sd][k][v];
+  }
+  __syncthreads();
+  // ---- flux: face F0+f, one per thread (wave-uniform: lanes without a face
+  // of their own compute the block's last face and store nothing) ----
+  const int f = t;
+  const int F = F0 + f;
+  const bool own = f < S1_FACES && F <= g.nx;
+  const int fc = own ? f : (g.nx - F0 < S1_FACES - 1 ? g.nx - F0 : S1_FACES - 1);
+  const int Fc = F0 + fc;
   {
     T Wk[2][6][4];
 #pragma unroll
     for (int sd = 0; sd < 2; ++sd) {
       const int cell = Fc - 1 + sd;
-      double s[6];
-#pragma unroll
-      for (int q = 0; q < 6; ++q) s[q] = B.sxo[g.sgx(0, cell - 2 + q)];
-      const Cascade cs = cascade(s, C.order, C.thres);
-      T d[3][9];
-#pragma unroll
-      for (int v = 0; v < 3; ++v) {
-#pragma unroll
-        for (int k = 0; k < 5; ++k) d[v][k] = T(Uin[g.avg(v, cell + k - 2, 0)]);
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-          const int o = k < 2 ? k - 2 : k - 1;
-          d[v][5 + k] = T(h * Uin[g.sx(v, 0, cell + o, 0)]);
-        }
-      }
-      T out[2][3][3];
-      recon_faces<T, 3>(d, cs, C, out);
+      const int tc = fc + sd;                  // its reconstruction slot
       const int side = sd == 0 ? 0 : 1;   // left state: +1/2 face of cell F-1; right: -1/2 face of cell F
 #pragma unroll
       for (int v = 0; v < 4; ++v)
@@ -1020,14 +1071,14 @@ __device__ void stage1d_seg(const Geo& g, const Consts& C, const Bufs& B, double
         for (int dd = 0; dd < 6; ++dd) Wk[sd][dd][v] = T(0);
 #pragma unroll
       for (int v = 0; v < 3; ++v) {
-        Wk[sd][0][v] = out[side][0][v];
-        Wk[sd][1][v] = out[side][1][v] / T(h);
-        Wk[sd][3][v] = out[side][2][v] / T(h * h);
+        Wk[sd][0][v] = rc[((tc * 2 + side) * 3 + 0) * 3 + v];
+        Wk[sd][1][v] = rc[((tc * 2 + side) * 3 + 1) * 3 + v] / T(h);
+        Wk[sd][3][v] = rc[((tc * 2 + side) * 3 + 2) * 3 + v] / T(h * h);
       }
       if (!positive_state<T, 1>(Wk[sd][0])) {
 #pragma unroll
         for (int v = 0; v < 3; ++v) {
-          Wk[sd][0][v] = T(Uin[g.avg(v, cell, 0)]);
+          Wk[sd][0][v] = sa[v * S1_NS + cell - (F0 - 3)];
           Wk[sd][1][v] = T(0);
           Wk[sd][3][v] = T(0);
         }
@@ -1056,7 +1107,7 @@ __device__ void stage1d_seg(const Geo& g, const Consts& C, const Bufs& B, double
   const int i = F0 + f;  // cell
   bool valid = false;
   double s = 0.0, rr = 1.0;
-  if (f < NFB - 1 && i < g.nx) {
+  if (f < S1_CELLS && i < g.nx) {
     const double ih = 1.0 / h;
     double W[3];
     // every load before the first store (the arrays are distinct, which the
