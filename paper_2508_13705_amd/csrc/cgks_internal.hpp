@@ -499,36 +499,79 @@ __device__ __forceinline__ void lines_tile(const Geo& g, const Consts& C, const 
 #pragma unroll
   for (int l = 0; l < M; ++l) wq[l] = kGw[M][l];
   // staging (entries outside the stored grid are clamped into it; no cell
-  // that computes line values reads them)
-  for (int k = tid; k < L::NAVG; k += 256) {
-    const int v = k / (L::BY * L::BX), xx = k % L::BX, yy = (k / L::BX) % L::BY;
-    avg[k] = U[g.avg(v, ci(i0 - 2 + xx), cj(j0 - 2 + yy))];
-  }
-  for (int k = tid; k < L::NGY; k += 256) {
-    const int v = k / (L::BY * LT_X), xx = k % LT_X, yy = (k / LT_X) % L::BY;
-    const int i = ci(i0 + xx), j = cj(j0 - 2 + yy);
-    double a = 0.0;
+  // that computes line values reads them).  Each array's loads are issued
+  // together (fixed pass counts; lanes past the end load a valid entry and
+  // store nothing), then written to LDS.
+  constexpr int PA = (L::NAVG + 255) / 256, PGY = (L::NGY + 255) / 256, PGX = (L::NGX + 255) / 256;
+  constexpr int PSY = (L::NSY + 255) / 256, PSX = (L::NSX + 255) / 256;
+  {
+    double ra[PA];
 #pragma unroll
-    for (int l = 0; l < M; ++l) a += wq[l] * U[g.sy(v, l, i, j)];
-    gy[k] = a;
-  }
-  for (int k = tid; k < L::NGX; k += 256) {
-    const int v = k / (LT_Y * L::BX), xx = k % L::BX, yy = (k / L::BX) % LT_Y;
-    const int i = ci(i0 - 2 + xx), j = cj(j0 + yy);
-    double a = 0.0;
+    for (int p = 0; p < PA; ++p) {
+      const int k = tid + 256 * p < L::NAVG ? tid + 256 * p : L::NAVG - 1;
+      const int v = k / (L::BY * L::BX), xx = k % L::BX, yy = (k / L::BX) % L::BY;
+      ra[p] = U[g.avg(v, ci(i0 - 2 + xx), cj(j0 - 2 + yy))];
+    }
 #pragma unroll
-    for (int l = 0; l < M; ++l) a += wq[l] * U[g.sx(v, l, i, j)];
-    gx[k] = a;
+    for (int p = 0; p < PA; ++p)
+      if (tid + 256 * p < L::NAVG) avg[tid + 256 * p] = ra[p];
   }
-  for (int k = tid; k < L::NSY; k += 256) {   // faces contiguous in memory along gg
-    const int gg = k % L::SYN, xx = k / L::SYN;
-    const int G = j0 - 2 + gg;
-    sy[k] = syo[g.sgy(ci(i0 + xx), G < -H ? -H : (G > g.ny + H ? g.ny + H : G))];
+  {
+    double ra[PGY][4];
+#pragma unroll
+    for (int p = 0; p < PGY; ++p) {
+      const int k = tid + 256 * p < L::NGY ? tid + 256 * p : L::NGY - 1;
+      const int v = k / (L::BY * LT_X), xx = k % LT_X, yy = (k / LT_X) % L::BY;
+      const int i = ci(i0 + xx), j = cj(j0 - 2 + yy);
+#pragma unroll
+      for (int l = 0; l < M; ++l) ra[p][l] = U[g.sy(v, l, i, j)];
+    }
+#pragma unroll
+    for (int p = 0; p < PGY; ++p) {
+      double a = 0.0;
+#pragma unroll
+      for (int l = 0; l < M; ++l) a += wq[l] * ra[p][l];
+      if (tid + 256 * p < L::NGY) gy[tid + 256 * p] = a;
+    }
   }
-  for (int k = tid; k < L::NSX; k += 256) {
-    const int ff = k % L::SXN, yy = k / L::SXN;
-    const int F = i0 - 2 + ff;
-    sx[k] = sxo[g.sgx(cj(j0 + yy), F < -H ? -H : (F > g.nx + H ? g.nx + H : F))];
+  {
+    double ra[PGX][4];
+    double rs[PSY], rt[PSX];
+#pragma unroll
+    for (int p = 0; p < PGX; ++p) {
+      const int k = tid + 256 * p < L::NGX ? tid + 256 * p : L::NGX - 1;
+      const int v = k / (LT_Y * L::BX), xx = k % L::BX, yy = (k / L::BX) % LT_Y;
+      const int i = ci(i0 - 2 + xx), j = cj(j0 + yy);
+#pragma unroll
+      for (int l = 0; l < M; ++l) ra[p][l] = U[g.sx(v, l, i, j)];
+    }
+#pragma unroll
+    for (int p = 0; p < PSY; ++p) {   // faces contiguous in memory along gg
+      const int k = tid + 256 * p < L::NSY ? tid + 256 * p : L::NSY - 1;
+      const int gg = k % L::SYN, xx = k / L::SYN;
+      const int G = j0 - 2 + gg;
+      rs[p] = syo[g.sgy(ci(i0 + xx), G < -H ? -H : (G > g.ny + H ? g.ny + H : G))];
+    }
+#pragma unroll
+    for (int p = 0; p < PSX; ++p) {
+      const int k = tid + 256 * p < L::NSX ? tid + 256 * p : L::NSX - 1;
+      const int ff = k % L::SXN, yy = k / L::SXN;
+      const int F = i0 - 2 + ff;
+      rt[p] = sxo[g.sgx(cj(j0 + yy), F < -H ? -H : (F > g.nx + H ? g.nx + H : F))];
+    }
+#pragma unroll
+    for (int p = 0; p < PGX; ++p) {
+      double a = 0.0;
+#pragma unroll
+      for (int l = 0; l < M; ++l) a += wq[l] * ra[p][l];
+      if (tid + 256 * p < L::NGX) gx[tid + 256 * p] = a;
+    }
+#pragma unroll
+    for (int p = 0; p < PSY; ++p)
+      if (tid + 256 * p < L::NSY) sy[tid + 256 * p] = rs[p];
+#pragma unroll
+    for (int p = 0; p < PSX; ++p)
+      if (tid + 256 * p < L::NSX) sx[tid + 256 * p] = rt[p];
   }
   __syncthreads();
   const int xx = tid % LT_X, yy = tid / LT_X;
