@@ -393,11 +393,29 @@ __device__ void dt_block(Header* hdr, const double* part, double sbc, double dt_
   __shared__ double red[2][256];
   __syncthreads();
   const int np = hdr->nparts;
-  double sm = 0.0, rm = INFINITY;
-  for (int k = threadIdx.x; k < np; k += blockDim.x) {
-    sm = fmax(sm, part[2 * k]);
-    rm = fmin(rm, part[2 * k + 1]);
+  // eight (speed, rate) pairs in flight per lane; max and min are exact, so
+  // the order of the reduction does not matter
+  constexpr int UR = 8;
+  const int bd = blockDim.x;
+  double smu[UR], rmu[UR];
+#pragma unroll
+  for (int u = 0; u < UR; ++u) { smu[u] = 0.0; rmu[u] = INFINITY; }
+  int k = threadIdx.x;
+  for (; k + (UR - 1) * bd < np; k += UR * bd) {
+    double2 q[UR];
+#pragma unroll
+    for (int u = 0; u < UR; ++u) q[u] = ((const double2*)part)[k + u * bd];
+#pragma unroll
+    for (int u = 0; u < UR; ++u) { smu[u] = fmax(smu[u], q[u].x); rmu[u] = fmin(rmu[u], q[u].y); }
   }
+  for (; k < np; k += bd) {
+    const double2 q = ((const double2*)part)[k];
+    smu[0] = fmax(smu[0], q.x);
+    rmu[0] = fmin(rmu[0], q.y);
+  }
+  double sm = smu[0], rm = rmu[0];
+#pragma unroll
+  for (int u = 1; u < UR; ++u) { sm = fmax(sm, smu[u]); rm = fmin(rm, rmu[u]); }
   red[0][threadIdx.x] = sm;
   red[1][threadIdx.x] = rm;
   __syncthreads();
