@@ -14,11 +14,13 @@ one persistent launch per phase for the whole batch in a captured hipGraph,
 against the same jobs stepped one at a time by the single-grid path, and
 (b) the serving loop on a Poisson trace of 2-D jobs (side 128-2048, orders
 5/7/9, smooth or four-quadrant data, 50-500 steps) under an HBM budget:
-p50/p99 latency and throughput.
+p50/p99 latency and throughput, (c) the wall and inflow workloads at the
+paper's meshes to their end times, and (d) one GPU's share of the 2048^2 grid
+cut into 8 slabs (2048 x 256, the shape a multi-GPU run would give each GPU).
 
 Prints one JSON line.  Usage:
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--n 2048] [--cpu-seconds 20]
-                    [--batch-steps 40] [--serve-jobs 24]
+                    [--batch-steps 40] [--serve-jobs 24] [--boundaries 1] [--shard-parts 8]
 """
 import argparse
 import hashlib
@@ -55,6 +57,8 @@ def parse():
     ap.add_argument("--serve-jobs", type=int, default=24, help="jobs in the serving trace (0: skip)")
     ap.add_argument("--serve-load", type=float, default=0.6, help="offered load of the serving trace")
     ap.add_argument("--boundaries", type=int, default=1, help="run the wall/inflow workloads to their end times (0: skip)")
+    ap.add_argument("--shard-parts", type=int, default=8,
+                    help="also time one GPU's slab of the grid split this many ways (0: skip)")
     ap.add_argument("--pmc-probe", action="store_true",
                     help="for hardware-counter runs: one step of each path, then a device copy of "
                          "COPY_BYTES (the calibration of the byte counters); prints nothing else")
@@ -154,6 +158,31 @@ def bench_batch_1d(jobs, steps, precision, graph_steps=10):
             "single_grid_sequential": {"value": upd1 / el1 if el1 > 0 else None, "jobs": len(sample),
                                        "steps_each": graph_steps},
             "speedup_vs_single_grid": (upd / el) / (upd1 / el1) if upd1 > 0 else None}
+
+
+def bench_shard(problem, parts, steps, warmup, full):
+    """One GPU's share of the 2-D grid split into `parts` slabs along y, at its
+    real shape (n x n/parts cells, periodic in x).  The y ghosts come from the
+    transmissive fill, the stand-in for the halo exchange that a multi-GPU
+    run would do before each stage; the exchange and the all-reduce of the
+    time step are not run.  Reports the slab's step time and its time per
+    cell against the whole grid's."""
+    n = problem["grid"]["nx"]
+    ny = n // parts
+    g = dict(problem["grid"], ny=ny, y1=problem["grid"]["y0"] + (problem["grid"]["y1"] - problem["grid"]["y0"]) * ny / n,
+             bc=["periodic", "periodic", "transmissive", "transmissive"])
+    st = problem["state"]
+    pb = dict(problem, name=f"{problem['name']}_slab{ny}", grid=g,
+              state={"avg": st["avg"][:, :ny].copy(), "sx": st["sx"][:, :, :ny].copy(), "sy": st["sy"][:, :, :ny].copy()})
+    out = {"workload": f"{n}x{ny} slab (1/{parts} of the {n}x{n} grid), periodic in x, transmissive y ghosts "
+                       f"standing in for the halo exchange", "parts": parts}
+    for precision in ("fp32_flux", "fp64"):
+        el, per, h, stt = time_path(pb, precision, steps, warmup)
+        ms = 1e3 * el / steps
+        out[precision] = {"ms_per_step": ms, "cell_updates_per_s": n * ny * steps / el,
+                          "time_per_cell_vs_full_grid": (ms / (n * ny)) / (full[precision] / (n * n)),
+                          "status": stt["status"]}
+    return out
 
 
 def bench_serving(jobs, load, ref_rate, precision="fp32_flux"):
@@ -315,6 +344,9 @@ def main():
         "kernel_ms": {"fp32_flux": p["avg_ms"], "fp64": q["avg_ms"]},
         "health": {"fp32_flux": p["health"], "fp64": q["health"]},
     }
+    if a.shard_parts > 1:
+        full = {k: 1e3 * res[k]["elapsed"] / res[k]["steps"] for k in res}
+        out["shard"] = bench_shard(problem, a.shard_parts, 10, 2, full)
     if a.batch_steps > 0:
         out["batch_1d"] = {prec: bench_batch_1d(a.batch_jobs, a.batch_steps, prec) for prec in ("fp64", "fp32_flux")}
     if a.serve_jobs > 0:
