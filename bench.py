@@ -1,7 +1,7 @@
 """Throughput of the ASE-DFF compact GKS hot path on one MI355X.
 
 Workload: 2-D compressible Navier-Stokes turbulence on a periodic 2048^2 grid,
-9th order (4 Gauss points per face), viscous collision time, CFL 0.5; seeded
+9th order (4 Gauss points per face), viscous collision time, CFL 0.2; seeded
 solenoidal random-phase velocity with a k^-5/3 shell spectrum (1 <= |k| <= 32),
 Mach 0.3, uniform density and pressure.  A step is one full two-stage step of
 every cell (reconstruction, interface flux, update of cell averages and
@@ -336,7 +336,7 @@ def main():
         "dtype": "f32 reconstruction/flux, f64 accumulation",
         "data": "synthetic",
         "config": {"workload": f"2-D Navier-Stokes turbulence {n}x{n} periodic, order 9 (m=4), viscous tau "
-                               f"mu=1e-4, Pr=0.72, Mach 0.3, k^-5/3 spectrum 1<=|k|<=32, CFL 0.5, seed 4",
+                               f"mu=1e-4, Pr=0.72, Mach 0.3, k^-5/3 spectrum 1<=|k|<=32, CFL 0.2, seed 4",
                    "cells": cells, "order": 9},
         "roofline": roof("fp32_flux"),
         "fp64": {"value": cells * q["steps"] / q["elapsed"], "ms_per_step": 1e3 * q["elapsed"] / q["steps"],

@@ -1005,9 +1005,9 @@ static void faces_1d(const orc_params* P, grid_t* g, double dt, double* out, cou
 }
 
 /* Weights of the first and second derivative, at Gauss point l of the middle
- * row, of the least-squares polynomial of degree q-1 = min(3m-1, 8) through
+ * row, of the least-squares polynomial of degree q-1 = min(2m+1, 8) through
  * the values at the m Gauss points of rows -1, 0, +1 (node r*m+q' at
- * xi = r-1+x_q'); for m = 2, 3 it is the interpolant (A22).  Built once, in
+ * xi = r-1+x_q'); for m = 2 it is the interpolant (A22).  Built once, in
  * long double, from the normal equations in the scaled variable xi/1.5.
  * Units: derivatives in xi. */
 typedef struct { int m; double d1[4][12], d2[4][12]; } tanw_t;
@@ -1021,7 +1021,7 @@ static const tanw_t* tangential_weights(int m) {
     double xg[4], wg[4];
     orc_gauss_legendre(m, xg, wg);
     const int n = 3 * m;
-    const int q = (n < 9) ? n : 9;
+    const int q = (2 * m + 2 < 9) ? 2 * m + 2 : 9;
     const long double sc = 1.5L;
     long double X[12], B[9][18];
     for (int r = 0; r < 3; ++r) for (int k = 0; k < m; ++k) X[r * m + k] = ((long double)(r - 1) + (long double)xg[k]) / sc;

@@ -124,12 +124,12 @@ def gauss(m):
 
 def tangential_weights(m):
     """First/second xi-derivative at Gauss point l of the middle row of the
-    least-squares polynomial of degree min(3m-1, 8) through the m Gauss points
-    of rows -1, 0, +1 (3m points; the interpolant for m = 2, 3)."""
+    least-squares polynomial of degree min(2m+1, 8) through the m Gauss points
+    of rows -1, 0, +1 (3m points; the interpolant for m = 2)."""
     xg, _ = gauss(m)
     X = [mp.mpf(r - 1) + xg[q] for r in range(3) for q in range(m)]
     n = len(X)
-    q = min(n, 9)
+    q = min(2 * m + 2, 9)              # coefficients: degree + 1
     V = mp.matrix([[x ** k for k in range(q)] for x in X])
     P = (V.T * V) ** -1 * V.T          # q x n: coefficients per datum
     d1 = [[mp.mpf(0)] * n for _ in range(m)]
@@ -211,7 +211,7 @@ def main():
                     lines.append("    {" + ", ".join(fmt(w) for w in eval_row(C, gx[m][0][l], 0)) + "},")
             lines.append("  },")
         lines.append("};")
-    lines.append("// Tangential derivative weights [m][l][r*m+q] (Sec. 3.3 Step 3, least squares of degree min(3m-1, 8)), units of xi")
+    lines.append("// Tangential derivative weights [m][l][r*m+q] (Sec. 3.3 Step 3, least squares of degree min(2m+1, 8)), units of xi")
     for name, idx in (("kT1", 0), ("kT2", 1)):
         lines.append(f"__constant__ double {name}[5][4][12] = {{")
         for m in range(5):

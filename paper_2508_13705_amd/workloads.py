@@ -402,11 +402,19 @@ def _eval_shifted(coef, KX, KY, sx, sy, n):
 
 
 def turbulence_2d(seed=4, n=2048, order=9, nsteps=500, kmax=32, mach=0.3, mu=1e-4, prandtl=0.72, gamma=1.4,
-                  cfl=0.5, quad=5):
+                  cfl=0.2, quad=5):
     """Decaying 2-D turbulence on the periodic unit square: rho = 1, p = 1/gamma
     (sound speed 1), solenoidal velocity with u_rms = Mach.  Cell averages by
     quad x quad Gauss quadrature of the band-limited field, line slopes from
-    point values at the face Gauss points."""
+    point values at the face Gauss points.
+
+    CFL 0.2, the paper's number for its viscous case (Sec. 4.9).  At CFL 0.5
+    this smooth vortical flow does not stay stable.  With the Prandtl-number
+    fix and a collision time of about one step (2048^2 with mu = 1e-4), it
+    goes nonphysical near step 200; the oracle breaks down on the same step
+    as the GPU path; with Pr 1 the same field runs on.  The paper runs CFL
+    0.5 only on problems with shocks, and uses a far smaller step for its
+    smooth accuracy tests."""
     m = GAUSS_M[order]
     xg, _ = gauss_legendre(m)
     qx, qw = gauss_legendre(quad)

@@ -101,6 +101,33 @@ def test_turbulence_2048_order9(precision, tol):
     _check_2d(pb, precision, samples, periodic=True, tol=tol)
 
 
+def test_turbulence_2048_500_steps_fp32_flux_error():
+    """The whole turbulence run (2048^2, order 9, Pr 0.72, 500 steps at CFL
+    0.2): both precisions stay physical, and the FP32-flux state stays within
+    1e-5 (rel-L1, averages and h-scaled slopes) of the FP64 path, which the
+    windows above pin to the oracle step by step.  Both runs take the FP64
+    path's first CFL step as a fixed step, so they are compared at one time."""
+    from paper_2508_13705_amd import cgks
+    pb = _turbulence_2048()
+    h = 1.0 / pb["grid"]["nx"]
+    probe = cgks.Solver(pb, precision="fp64")
+    probe.step(1)
+    dt = probe.read(sync_only=True)["t"]
+    del probe
+    _say(f"turbulence 2048^2: 500 steps of dt {dt:.4e}, FP32-flux against FP64")
+    runs = {p: cgks.Solver(pb, precision=p) for p in ("fp64", "fp32_flux")}
+    for s in runs.values():
+        s.step(500, dt=dt)
+    a, b = runs["fp32_flux"].read(), runs["fp64"].read()
+    assert a["status"] == b["status"] == 0 and a["steps"] == b["steps"] == 500
+    norm = np.abs(b["avg"]).reshape(4, -1).sum(axis=1)
+    e = (np.abs(a["avg"] - b["avg"]).reshape(4, -1).sum(axis=1) / norm).max()
+    m = b["sx"].shape[1]
+    es = max((h * np.abs(a[k] - b[k]).reshape(4, -1).sum(axis=1) / (m * norm)).max() for k in ("sx", "sy"))
+    _say(f"  rel-L1 averages {e:.3e}, slopes {es:.3e} (bar 1e-5)")
+    assert e <= 1e-5 and es <= 1e-5, (e, es)
+
+
 @pytest.mark.parametrize("precision", ["fp64", "fp32_flux"])
 def test_quadrant_1024_order7(precision):
     """Four-quadrant Riemann data (the 1024^2 order-7 workload): windows on
@@ -113,14 +140,16 @@ def test_quadrant_1024_order7(precision):
     _check_2d(pb, precision, samples, periodic=False, tol=1e-10 if precision == "fp64" else 1e-3)
 
 
-def test_riemann_batch_4096_sampled_jobs():
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-10), ("fp32_flux", 1e-3)])
+def test_riemann_batch_4096_sampled_jobs(precision, tol):
     """The full 4096-job 1-D batch, 10 captured batch steps; sampled jobs are
-    rerun by the oracle for the steps they took."""
+    rerun by the oracle (FP64) for the steps they took.  FP32-flux is held to
+    the loose bar of discontinuous data and its error is reported."""
     from paper_2508_13705_amd import cgks
     probs = W.riemann_batch(seed=2, count=4096)
-    _say("4096-job 1-D batch, fp64, 10 steps")
-    B = cgks.Batch(1, "fp64", max_jobs=4096)
-    sol = [cgks.Solver(pb) for pb in probs]
+    _say(f"4096-job 1-D batch, {precision}, 10 steps")
+    B = cgks.Batch(1, precision, max_jobs=4096)
+    sol = [cgks.Solver(pb, precision=precision) for pb in probs]
     slots = [B.add(s, max_steps=10, t_end=pb["run"]["t_end"]) for s, pb in zip(sol, probs)]
     B.commit()
     B.capture(5)
@@ -130,6 +159,7 @@ def test_riemann_batch_4096_sampled_jobs():
     rng = np.random.default_rng(11)
     picks = list(rng.choice(4096, size=8, replace=False))
     picks.append(int(np.argmax([pb["grid"]["nx"] for pb in probs])))     # the largest job
+    worst = 0.0
     for k in picks:
         pb, s, sl = probs[k], sol[k], slots[k]
         got = s.read()
@@ -140,8 +170,9 @@ def test_riemann_batch_4096_sampled_jobs():
             continue
         norm = np.abs(ref["avg"]).sum(axis=1)
         e = (np.abs(got["avg"] - ref["avg"]).sum(axis=1) / norm).max()
-        assert e <= 1e-10, (k, e)
-    _say(f"  {len(picks)} sampled jobs match the oracle")
+        worst = max(worst, e)
+        assert e <= tol, (k, e)
+    _say(f"  {len(picks)} sampled jobs match the oracle, worst rel-L1 {worst:.3e} (bar {tol:g})")
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32_flux"])

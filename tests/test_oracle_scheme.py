@@ -194,7 +194,7 @@ def test_le_blanc_is_reported_not_silently_wrong():
 def test_cfl_half_is_stable_2d(order, n, steps):
     """The paper runs every order at CFL 0.5 (abstract, Sec. 4).  Smooth 2-D
     data stays bounded for many steps at CFL 0.5 with the Step 3 tangential
-    fit of degree min(3m-1, 8) (A22); the degree-11 interpolant for m = 4
+    fit of degree min(2m+1, 8) (A22); the degree-11 interpolant for m = 4
     blows up within a dozen steps here."""
     pb = W.fourier_2d(5, n, order, nsteps=steps, cfl=0.5)
     r = oracle.run(pb)
