@@ -460,7 +460,8 @@ static void flux_point(const orc_params* P, int D, const double Wl[6][4], const 
    * standard gas-kinetic correction, A18): the time integral q of the heat
    * flux int (u-U0)/2 ((u-U0)^2 + (v-V0)^2 + xi^2) f in the frame of the
    * equilibrium velocity, with the flux's own terms and weights, enters the
-   * energy flux as (1/Pr - 1) q.  Parity unpinned beyond invariants. */
+   * energy flux as (1/Pr - 1) q.  Pinned by the decay of an entropy wave,
+   * whose rate must scale as 1/Pr (Fourier heat conduction). */
   double mheat[10] = {0};
   const int prandtl_fix = (P->prandtl != 1.0);
   if (prandtl_fix) {

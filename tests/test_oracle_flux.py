@@ -178,7 +178,8 @@ def test_tau_models():
 
 
 def test_prandtl_fix_invariants():
-    """Prandtl fix of the energy flux (not in the paper, parity unpinned):
+    """Prandtl fix of the energy flux (not in the paper; its rate is pinned in
+    test_oracle_prandtl.py):
     no effect at Pr = 1 or in a uniform state, only the energy flux changes,
     and the change is proportional to (1/Pr - 1)."""
     rng = np.random.default_rng(4)
