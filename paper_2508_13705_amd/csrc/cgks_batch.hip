@@ -50,7 +50,8 @@ struct BTab {
 };
 
 // Largest j in [0, n) with pre[j] <= item (pre[0] = 0, pre[n] = total).
-__device__ __forceinline__ int find_job(const int* pre, int n, int item) {
+template <class P>
+__device__ __forceinline__ int find_job(P pre, int n, int item) {
   int lo = 0, hi = n;
   while (hi - lo > 1) {
     const int mid = (lo + hi) >> 1;
@@ -70,7 +71,7 @@ __device__ __forceinline__ void for_items(const BTab* tab, int ph, int remap, F&
   int lb = blockIdx.x;
   if (remap) lb = (blockIdx.x & 7) * (G >> 3) + (blockIdx.x >> 3);   // G is a multiple of 8
   const int n = tab->njobs;
-  const int* pre = tab->pre + (size_t)ph * (tab->cap + 1);
+  const gptr<const int> pre = glb((const int*)tab->pre) + (size_t)ph * (tab->cap + 1);
   for (int item = lb; item < total; item += G) {
     // the job and tile are the same for the whole block: made wave-uniform,
     // the job descriptor comes through scalar loads instead of occupying
@@ -149,7 +150,7 @@ __global__ __launch_bounds__(256, 1) void kb_face(const BTab* tab, int remap) {
 
 // One stage of the 1-D scheme over the segments of every job.
 template <int STAGE, typename T>
-__global__ __launch_bounds__(256) void kb_stage1d(const BTab* tab, int remap) {
+__global__ __launch_bounds__(256, 2) void kb_stage1d(const BTab* tab, int remap) {
   __shared__ double res[256][12];
   __shared__ __align__(16) unsigned char sm[Lds1D<T>::total];
   for_items(tab, PH_S1D, remap,

@@ -143,6 +143,18 @@ struct Bufs {
   const BcTable* bct;
 };
 
+// Pointers into device memory typed as such.  Kernel arguments are known to
+// point to global memory, pointers read from memory (the batched job table)
+// are not; loads and stores through the latter would be FLAT instructions,
+// which also count against the LDS counter, so every wait for an LDS read
+// would wait for the global accesses in flight as well.
+template <typename T>
+using gptr = __attribute__((address_space(1))) T*;
+template <typename T>
+__device__ __forceinline__ gptr<T> glb(T* p) {
+  return (gptr<T>)p;
+}
+
 }  // namespace
 
 struct cgks_plan {
@@ -367,9 +379,10 @@ __device__ __forceinline__ void reduce_speed(const Bufs& B, double s, double r, 
   __syncthreads();
   if (threadIdx.x == 0) {
     for (int k = 1; k < nw; ++k) { sm = fmax(sm, red[0][k]); rm = fmin(rm, red[1][k]); }
-    B.part[2 * bid] = sm;
-    B.part[2 * bid + 1] = rm;
-    if (bid == 0) B.hdr->nparts = nparts;
+    const gptr<double> part = glb(B.part);
+    part[2 * bid] = sm;
+    part[2 * bid + 1] = rm;
+    if (bid == 0) glb(B.hdr)->nparts = nparts;
   }
 }
 
@@ -503,6 +516,8 @@ __device__ __forceinline__ void lines_tile(const Geo& g, const Consts& C, const 
                                            const double* syo, double* lvx, double* lvy, int bx, int by,
                                            double* sm) {
   using L = LinesLds;
+  const gptr<const double> Ug = glb(U), sxg = glb(sxo), syg = glb(syo);
+  const gptr<double> lvxg = glb(lvx), lvyg = glb(lvy);
   double* avg = sm;
   double* gy = avg + L::NAVG;
   double* gx = gy + L::NGY;
@@ -528,7 +543,7 @@ __device__ __forceinline__ void lines_tile(const Geo& g, const Consts& C, const 
     for (int p = 0; p < PA; ++p) {
       const int k = tid + 256 * p < L::NAVG ? tid + 256 * p : L::NAVG - 1;
       const int v = k / (L::BY * L::BX), xx = k % L::BX, yy = (k / L::BX) % L::BY;
-      ra[p] = U[g.avg(v, ci(i0 - 2 + xx), cj(j0 - 2 + yy))];
+      ra[p] = Ug[g.avg(v, ci(i0 - 2 + xx), cj(j0 - 2 + yy))];
     }
 #pragma unroll
     for (int p = 0; p < PA; ++p)
@@ -542,7 +557,7 @@ __device__ __forceinline__ void lines_tile(const Geo& g, const Consts& C, const 
       const int v = k / (L::BY * LT_X), xx = k % LT_X, yy = (k / LT_X) % L::BY;
       const int i = ci(i0 + xx), j = cj(j0 - 2 + yy);
 #pragma unroll
-      for (int l = 0; l < M; ++l) ra[p][l] = U[g.sy(v, l, i, j)];
+      for (int l = 0; l < M; ++l) ra[p][l] = Ug[g.sy(v, l, i, j)];
     }
 #pragma unroll
     for (int p = 0; p < PGY; ++p) {
@@ -561,21 +576,21 @@ __device__ __forceinline__ void lines_tile(const Geo& g, const Consts& C, const 
       const int v = k / (LT_Y * L::BX), xx = k % L::BX, yy = (k / L::BX) % LT_Y;
       const int i = ci(i0 - 2 + xx), j = cj(j0 + yy);
 #pragma unroll
-      for (int l = 0; l < M; ++l) ra[p][l] = U[g.sx(v, l, i, j)];
+      for (int l = 0; l < M; ++l) ra[p][l] = Ug[g.sx(v, l, i, j)];
     }
 #pragma unroll
     for (int p = 0; p < PSY; ++p) {   // faces contiguous in memory along gg
       const int k = tid + 256 * p < L::NSY ? tid + 256 * p : L::NSY - 1;
       const int gg = k % L::SYN, xx = k / L::SYN;
       const int G = j0 - 2 + gg;
-      rs[p] = syo[g.sgy(ci(i0 + xx), G < -H ? -H : (G > g.ny + H ? g.ny + H : G))];
+      rs[p] = syg[g.sgy(ci(i0 + xx), G < -H ? -H : (G > g.ny + H ? g.ny + H : G))];
     }
 #pragma unroll
     for (int p = 0; p < PSX; ++p) {
       const int k = tid + 256 * p < L::NSX ? tid + 256 * p : L::NSX - 1;
       const int ff = k % L::SXN, yy = k / L::SXN;
       const int F = i0 - 2 + ff;
-      rt[p] = sxo[g.sgx(cj(j0 + yy), F < -H ? -H : (F > g.nx + H ? g.nx + H : F))];
+      rt[p] = sxg[g.sgx(cj(j0 + yy), F < -H ? -H : (F > g.nx + H ? g.nx + H : F))];
     }
 #pragma unroll
     for (int p = 0; p < PGX; ++p) {
@@ -615,7 +630,7 @@ __device__ __forceinline__ void lines_tile(const Geo& g, const Consts& C, const 
 #pragma unroll
     for (int l = 0; l < M; ++l)
 #pragma unroll
-      for (int v = 0; v < 4; ++v) lvx[g.lv(v, l, i, j)] = out[l][v];
+      for (int v = 0; v < 4; ++v) lvxg[g.lv(v, l, i, j)] = out[l][v];
   }
   // y-face line values: row j, columns i-2..i+2, needed for i in [-1, nx]
   if (i >= -1 && i <= g.nx && j <= g.ny + 2) {
@@ -638,7 +653,7 @@ __device__ __forceinline__ void lines_tile(const Geo& g, const Consts& C, const 
 #pragma unroll
     for (int l = 0; l < M; ++l)
 #pragma unroll
-      for (int v = 0; v < 4; ++v) lvy[g.lv(v, l, i, j)] = out[l][v];
+      for (int v = 0; v < 4; ++v) lvyg[g.lv(v, l, i, j)] = out[l][v];
   }
 }
 
@@ -729,7 +744,7 @@ __device__ void face2d_tile(const Geo& g, const Consts& C, const Bufs& B, unsign
                             int nbx, int nby) {
   using TL = Tile<M>;
   constexpr int NF = TL::NF, NT = TL::NT, NC = TL::NC, NR = TL::NR;
-  const Header* hdr = B.hdr;
+  const gptr<const Header> hdr = glb((const Header*)B.hdr);
   __syncthreads();
   if (!hdr->active) return;
   // persistent callers: an index the compiler cannot hoist out of their loop
@@ -756,10 +771,11 @@ __device__ void face2d_tile(const Geo& g, const Consts& C, const Bufs& B, unsign
   const int F0 = bx * (NF - 1);
   const int T0 = by * NT;
   const double hn = DIR == 0 ? C.dx : C.dy, ht = DIR == 0 ? C.dy : C.dx;
-  const double* Uin = STAGE == 1 ? B.U : B.S;
-  const double* LV = DIR == 0 ? B.lvx : B.lvy;
-  const double* sgN = DIR == 0 ? B.sxo : B.syo;   // normal-face strengths
-  const double* sgT = DIR == 0 ? B.syo : B.sxo;   // tangential-face strengths
+  const gptr<const double> Uin = glb((const double*)(STAGE == 1 ? B.U : B.S));
+  const gptr<const double> LV = glb((const double*)(DIR == 0 ? B.lvx : B.lvy));
+  const gptr<const double> sgN = glb((const double*)(DIR == 0 ? B.sxo : B.syo));   // normal-face strengths
+  const gptr<const double> sgT = glb((const double*)(DIR == 0 ? B.syo : B.sxo));   // tangential-face strengths
+  const gptr<double> Ug = glb(B.U), Sg = glb(B.S), Ag = glb(B.A);
   const int gcomp[4] = {0, DIR == 0 ? 1 : 2, DIR == 0 ? 2 : 1, 3};
   auto gi = [&](int n, int t) { return DIR == 0 ? n : t; };
   auto gj = [&](int n, int t) { return DIR == 0 ? t : n; };
@@ -791,7 +807,7 @@ __device__ void face2d_tile(const Geo& g, const Consts& C, const Bufs& B, unsign
     const bool slot = tid < PPP * PL;
     const int n = clampi(F0 - 3 + cc, -H, nmax + H - 1), t = clampi(T0 - 1 + r, -H, tmax + H - 1);
     const size_t cell = g.cell(gi(n, t), gj(n, t));
-    const double* slope = Uin + (size_t)g.nv * g.cells + (DIR == 0 ? 0 : (size_t)g.nv * g.m * g.cells);
+    const gptr<const double> slope = Uin + (size_t)g.nv * g.cells + (DIR == 0 ? 0 : (size_t)g.nv * g.m * g.cells);
 #pragma unroll SU
     for (int p0 = 0; p0 < NPL; p0 += PPP) {
       const int pl = p0 + lp < NPL ? p0 + lp : NPL - 1;
@@ -955,7 +971,7 @@ __device__ void face2d_tile(const Geo& g, const Consts& C, const Bufs& B, unsign
       if (nf > nmax || t >= tmax) continue;
       double s = 0.0;
       for (int l = 0; l < M; ++l) s += res[16 * NB + gp(f, r, l)];
-      (DIR == 0 ? B.sxn : B.syn)[sgn_idx(t, nf)] = s / M;
+      (DIR == 0 ? glb(B.sxn) : glb(B.syn))[sgn_idx(t, nf)] = s / M;
     }
   }
 
@@ -980,33 +996,33 @@ __device__ void face2d_tile(const Geo& g, const Consts& C, const Bufs& B, unsign
         dF += w * (rb(v, l) - ra(v, l));
         dA += w * (rb(4 + v, l) - ra(4 + v, l));
       }
-      const double base = DIR == 0 ? B.U[ia] : B.S[ia];
-      const double abase = DIR == 0 ? B.U[ia] : B.A[ia];
+      const double base = DIR == 0 ? Ug[ia] : Sg[ia];
+      const double abase = DIR == 0 ? Ug[ia] : Ag[ia];
       const double snew = base - dF * ihn;
-      B.S[ia] = snew;
-      B.A[ia] = abase - dA * ihn;
+      Sg[ia] = snew;
+      Ag[ia] = abase - dA * ihn;
       if (DIR == 1) fin[v * NFT + ci * NT + r] = snew;
       for (int l = 0; l < M; ++l) {
         const size_t is = DIR == 0 ? g.sx(v, l, i, j) : g.sy(v, l, i, j);
-        B.S[is] = (rb(8 + v, l) - ra(8 + v, l)) * ihn;
-        B.A[is] = (rb(12 + v, l) - ra(12 + v, l)) * ihn;
+        Sg[is] = (rb(8 + v, l) - ra(8 + v, l)) * ihn;
+        Ag[is] = (rb(12 + v, l) - ra(12 + v, l)) * ihn;
       }
     } else {
       // every load before the first store: U and A are distinct arrays, but
       // the compiler cannot know it and would otherwise wait for each load
       double aslope[M];
 #pragma unroll
-      for (int l = 0; l < M; ++l) aslope[l] = B.A[DIR == 0 ? g.sx(v, l, i, j) : g.sy(v, l, i, j)];
-      const double base = DIR == 0 ? B.A[ia] : B.U[ia];
+      for (int l = 0; l < M; ++l) aslope[l] = Ag[DIR == 0 ? g.sx(v, l, i, j) : g.sy(v, l, i, j)];
+      const double base = DIR == 0 ? Ag[ia] : Ug[ia];
       double dA = 0.0;
       for (int l = 0; l < M; ++l) dA += kGw[M][l] * (rb(v, l) - ra(v, l));
       const double unew = base - dA * ihn;
-      B.U[ia] = unew;
+      Ug[ia] = unew;
       if (DIR == 1) fin[v * NFT + ci * NT + r] = unew;
 #pragma unroll
       for (int l = 0; l < M; ++l) {
         const size_t is = DIR == 0 ? g.sx(v, l, i, j) : g.sy(v, l, i, j);
-        B.U[is] = aslope[l] + (rb(4 + v, l) - ra(4 + v, l)) * ihn;
+        Ug[is] = aslope[l] + (rb(4 + v, l) - ra(4 + v, l)) * ihn;
       }
     }
   }
@@ -1056,13 +1072,14 @@ template <typename T> struct Lds1D {
 template <int STAGE, typename T, bool PR>
 __device__ void stage1d_seg(const Geo& g, const Consts& C, const Bufs& B, double (*res)[12], unsigned char* sm,
                             int seg, int nseg) {
-  const Header* hdr = B.hdr;
+  const gptr<const Header> hdr = glb((const Header*)B.hdr);
   __syncthreads();
   if (!hdr->active) return;
   const double dt = hdr->dt;
   const int F0 = seg * S1_CELLS;
   const int t = threadIdx.x;
-  const double* Uin = STAGE == 1 ? B.U : B.S;
+  const gptr<const double> Uin = glb((const double*)(STAGE == 1 ? B.U : B.S));
+  const gptr<double> Ug = glb(B.U), Sg = glb(B.S), Ag = glb(B.A);
   const double h = C.dx;
   T* sa = (T*)(sm + Lds1D<T>::avg);
   T* ss = (T*)(sm + Lds1D<T>::slo);
@@ -1084,7 +1101,7 @@ __device__ void stage1d_seg(const Geo& g, const Consts& C, const Bufs& B, double
   for (int base = 0; base < S1_NG; base += 256) {
     const int q = base + t < S1_NG ? base + t : S1_NG - 1;
     const int face = F0 - 3 + q;
-    const double sv = B.sxo[g.sgx(0, face < -H ? -H : (face > g.nx + H ? g.nx + H : face))];
+    const double sv = glb(B.sxo)[g.sgx(0, face < -H ? -H : (face > g.nx + H ? g.nx + H : face))];
     if (base + t < S1_NG) sg[q] = sv;
   }
   __syncthreads();
@@ -1161,7 +1178,7 @@ __device__ void stage1d_seg(const Geo& g, const Consts& C, const Bufs& B, double
         res[f][3 + v] = (4.0 / 3.0) * (fo.W0[v] - 2.0 * fo.Wh[v] + fo.W1[v]);
       }
     }
-    if (STAGE == 1) B.sxn[g.sgx(0, F)] = fo.sigma;
+    if (STAGE == 1) glb(B.sxn)[g.sgx(0, F)] = fo.sigma;
     }
   }
   __syncthreads();
@@ -1176,8 +1193,8 @@ __device__ void stage1d_seg(const Geo& g, const Consts& C, const Bufs& B, double
     double in0[3], in1[3];
 #pragma unroll
     for (int v = 0; v < 3; ++v) {
-      in0[v] = STAGE == 1 ? B.U[g.avg(v, i, 0)] : B.A[g.avg(v, i, 0)];
-      in1[v] = STAGE == 1 ? 0.0 : B.A[g.sx(v, 0, i, 0)];
+      in0[v] = STAGE == 1 ? Ug[g.avg(v, i, 0)] : Ag[g.avg(v, i, 0)];
+      in1[v] = STAGE == 1 ? 0.0 : Ag[g.sx(v, 0, i, 0)];
     }
 #pragma unroll
     for (int v = 0; v < 3; ++v) {
@@ -1185,14 +1202,14 @@ __device__ void stage1d_seg(const Geo& g, const Consts& C, const Bufs& B, double
       if (STAGE == 1) {
         const double u0 = in0[v];
         W[v] = u0 - (res[f + 1][v] - res[f][v]) * ih;
-        B.S[ia] = W[v];
-        B.A[ia] = u0 - (res[f + 1][3 + v] - res[f][3 + v]) * ih;
-        B.S[is] = (res[f + 1][6 + v] - res[f][6 + v]) * ih;
-        B.A[is] = (res[f + 1][9 + v] - res[f][9 + v]) * ih;
+        Sg[ia] = W[v];
+        Ag[ia] = u0 - (res[f + 1][3 + v] - res[f][3 + v]) * ih;
+        Sg[is] = (res[f + 1][6 + v] - res[f][6 + v]) * ih;
+        Ag[is] = (res[f + 1][9 + v] - res[f][9 + v]) * ih;
       } else {
         W[v] = in0[v] - (res[f + 1][v] - res[f][v]) * ih;
-        B.U[ia] = W[v];
-        B.U[is] = in1[v] + (res[f + 1][3 + v] - res[f][3 + v]) * ih;
+        Ug[ia] = W[v];
+        Ug[is] = in1[v] + (res[f + 1][3 + v] - res[f][3 + v]) * ih;
       }
     }
     rr = W[0];
