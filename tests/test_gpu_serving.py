@@ -15,15 +15,20 @@ def _trace():
     return tr
 
 
-def test_each_result_is_the_same_alone_and_in_the_mix():
+@pytest.mark.parametrize("lanes", [(512, 1024), (24, 40)], ids=["one-lane", "three-lanes"])
+def test_each_result_is_the_same_alone_and_in_the_mix(lanes):
+    """With lane limits (24, 40) the 16-64 sided jobs spread over three
+    lanes, whose graphs run concurrently on their own streams."""
     from paper_2508_13705_amd import cgks, serving
     tr = _trace()
     sizes = sorted(serving.job_bytes(j, "fp64") for j in tr)
     budget = sum(sizes[-3:])       # about three jobs at a time: admission must wait for memory
-    print(f"\n[serving] {len(tr)} jobs, budget {budget} bytes", flush=True)
+    print(f"\n[serving] {len(tr)} jobs, budget {budget} bytes, lanes {lanes}", flush=True)
     loop = serving.ServingLoop(2, "fp64", hbm_budget=budget, max_jobs=6, graph_steps=3, prep_workers=2,
-                               keep_results=True)
+                               keep_results=True, lane_sides=lanes)
     rep = loop.run(tr)
+    used = {sum(1 for m in lanes if r["job"]["n"] > m) for r in rep["records"]}
+    assert len(used) == (1 if lanes == (512, 1024) else 3)
     print("[serving] p50 %.3f s p99 %.3f s, max running %d" % (rep["latency_p50_s"], rep["latency_p99_s"],
                                                                 rep["max_running"]), flush=True)
     assert rep["jobs"] == len(tr) and rep["rejected"] == 0
