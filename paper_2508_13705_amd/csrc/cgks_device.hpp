@@ -444,15 +444,27 @@ CGKS_HD void gks_flux(const T (&Wl)[6][4], const T (&Wr)[6][4], double dt, const
   // equilibrium part; interface values keep the full quadratic)
   const double r0 = double(rho0);
   double ex[2] = {0.0, 0.0};   // exp(-dt/(2 tau)), exp(-dt/tau); 0 when tau = 0
+  double emh = 0.0;             // expm1(-dt/(2 tau))
 #pragma unroll
   for (int w = 0; w < 2; ++w) {
     const double d = w == 0 ? 0.5 * dt : dt;
     double E0 = 0.0, E1 = 0.0;
     if (tau > 0.0) {
-      const double x = d * itau;
-      const double e = exp(-x);
+      // the full step's exponentials from the half step's: exp(-2x) =
+      // exp(-x)^2 and expm1(-2x) = expm1(-x) (2 + expm1(-x)), free of
+      // cancellation for small x
+      double e, em;
+      if (w == 0) {
+        const double x = d * itau;
+        e = exp(-x);
+        em = expm1(-x);
+        emh = em;
+      } else {
+        e = ex[0] * ex[0];
+        em = emh * (2.0 + emh);
+      }
       ex[w] = e;
-      E0 = -tau * expm1(-x);
+      E0 = -tau * em;
       E1 = tau * tau - tau * (tau + d) * e;
     }
     double* Fo = w == 0 ? o.Fh : o.F1;
