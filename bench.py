@@ -404,20 +404,34 @@ def main():
         "kernel_ms": {"fp32_flux": p["avg_ms"], "fp64": q["avg_ms"]},
         "health": {"fp32_flux": p["health"], "fp64": q["health"]},
     }
+    def section(name, fn):
+        # a failure in a secondary measurement is recorded, not fatal: the
+        # headline line above is printed regardless
+        try:
+            out[name] = fn()
+        except Exception as e:          # noqa: BLE001
+            print(f"[bench] {name} failed: {e!r}", file=sys.stderr, flush=True)
+            out[name] = {"error": repr(e)}
+
     if a.shard_parts > 1:
         full = {k: 1e3 * res[k]["elapsed"] / res[k]["steps"] for k in res}
-        out["shard"] = bench_shard(problem, a.shard_parts, 10, 2, full)
-    if a.batch_steps > 0:
-        out["batch_1d"] = {prec: bench_batch_1d(a.batch_jobs, a.batch_steps, prec) for prec in ("fp64", "fp32_flux")}
-        ref64 = out["batch_1d"]["fp64"]["single_grid_sequential"]["value"]
-        for v in out["batch_1d"].values():
+        section("shard", lambda: bench_shard(problem, a.shard_parts, 10, 2, full))
+
+    def batch_1d():
+        r = {prec: bench_batch_1d(a.batch_jobs, a.batch_steps, prec) for prec in ("fp64", "fp32_flux")}
+        ref64 = r["fp64"]["single_grid_sequential"]["value"]
+        for v in r.values():
             v["speedup_vs_single_grid_fp64"] = v["value"] / ref64 if ref64 else None
+        return r
+
+    if a.batch_steps > 0:
+        section("batch_1d", batch_1d)
     if a.serve_jobs > 0:
-        out["serving"] = bench_serving(a.serve_jobs, a.serve_load, value)
+        section("serving", lambda: bench_serving(a.serve_jobs, a.serve_load, value))
     if a.boundaries:
-        out["boundaries"] = bench_boundaries()
-    out["small_1d"] = bench_small_1d()
-    out["cpu_baseline"] = cpu_baseline(a.cpu_seconds)
+        section("boundaries", bench_boundaries)
+    section("small_1d", bench_small_1d)
+    section("cpu_baseline", lambda: cpu_baseline(a.cpu_seconds))
     print(json.dumps(out))
 
 
