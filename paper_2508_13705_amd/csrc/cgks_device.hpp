@@ -45,9 +45,22 @@ template <typename T> CGKS_HD T dev_sqrt(T x);
 template <> CGKS_HD __forceinline__ double dev_sqrt<double>(double x) { return sqrt(x); }
 template <> CGKS_HD __forceinline__ float dev_sqrt<float>(float x) { return sqrtf(x); }
 
-// Reciprocal and reciprocal square root: correctly rounded in double; the
-// hardware approximations (1 ulp) in the FP32 flux variant.
+// Reciprocal and reciprocal square root: in double the hardware reciprocal
+// estimate refined by two Newton steps (within an ulp or two of 1/x; the
+// arguments are positive normal numbers); the hardware approximations (1 ulp)
+// in the FP32 flux variant.
 template <typename T> CGKS_HD __forceinline__ T dev_rcp(T x) { return T(1) / x; }
+template <> CGKS_HD __forceinline__ double dev_rcp<double>(double x) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  double r = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-x, r, 1.0);
+  return fma(r, e, r);
+#else
+  return 1.0 / x;
+#endif
+}
 template <typename T> CGKS_HD __forceinline__ T dev_rsqrt(T x) { return T(1) / dev_sqrt<T>(x); }
 template <> CGKS_HD __forceinline__ float dev_rcp<float>(float x) {
 #if defined(__HIP_DEVICE_COMPILE__)
