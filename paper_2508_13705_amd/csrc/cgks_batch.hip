@@ -78,7 +78,14 @@ __device__ __forceinline__ void for_items(const BTab* tab, int ph, int remap, F&
     // vector registers
     const int j = __builtin_amdgcn_readfirstlane(find_job(pre, n, item));
     const int k = __builtin_amdgcn_readfirstlane(item - pre[j]);
+#if defined(__HIP_DEVICE_COMPILE__)
+    // read through a pointer of global type: scalar loads (through the generic
+    // table pointer they would be FLAT loads, which count against the LDS
+    // counter)
+    const BJob J = glb((const BJob*)tab->jobs)[j];
+#else
     const BJob& J = tab->jobs[j];
+#endif
     f(J, k);
   }
 }
