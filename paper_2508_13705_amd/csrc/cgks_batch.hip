@@ -39,6 +39,10 @@ struct BJob {
   int fnb[2][2];           // face tiles (along normal, along tangential) of x- and y-faces
   int ltx, lty;            // Step 1 tiles along x and y
   int nseg;                // 1-D stage segments
+  // ghost-cell items: every 256-cell segment of the gr ghost rows (2-D), and
+  // of the other rows only the segments holding ghost cells (segment 0 and
+  // segments r0..as-1), sg per row; ns items in all
+  int gr, sg, r0, ns;
 };
 
 struct BTab {
@@ -90,6 +94,22 @@ __device__ __forceinline__ void for_items(const BTab* tab, int ph, int remap, F&
   }
 }
 
+// State item k of job J -> (padded column of this thread, padded row).
+__device__ __forceinline__ void state_item(const BJob& J, int k, int& I, int& Jr) {
+  int seg;
+  if (k < J.gr * J.as) {
+    const int q = k / J.as;
+    Jr = q < H ? q : J.g.NY - 2 * H + q;
+    seg = k % J.as;
+  } else {
+    k -= J.gr * J.as;
+    const int idx = k % J.sg;
+    Jr = (J.gr ? H : 0) + k / J.sg;
+    seg = idx == 0 ? 0 : J.r0 + idx - 1;
+  }
+  I = seg * 256 + (int)threadIdx.x;
+}
+
 __global__ __launch_bounds__(256) void kb_dt(const BTab* tab) {
   const int n = tab->njobs;
   for (int j = blockIdx.x; j < n; j += gridDim.x) {
@@ -115,7 +135,9 @@ __global__ __launch_bounds__(256) void kb_prep(const BTab* tab, int remap) {
       return;
     }
     k -= J.nsy;
-    bc_state_at(J.g, J.B.bct, bc_time(J.B.hdr, 1), J.B.U, (k % J.as) * 256 + threadIdx.x, k / J.as);
+    int I, Jr;
+    state_item(J, k, I, Jr);
+    bc_state_at(J.g, J.B.bct, bc_time(J.B.hdr, 1), J.B.U, I, Jr);
   });
 }
 
@@ -123,7 +145,9 @@ __global__ __launch_bounds__(256) void kb_prep(const BTab* tab, int remap) {
 __global__ __launch_bounds__(256) void kb_bcs(const BTab* tab, int remap) {
   for_items(tab, PH_BCS, remap, [&](const BJob& J, int k) {
     if (!J.B.hdr->active) return;
-    bc_state_at(J.g, J.B.bct, bc_time(J.B.hdr, 2), J.B.S, (k % J.as) * 256 + threadIdx.x, k / J.as);
+    int I, Jr;
+    state_item(J, k, I, Jr);
+    bc_state_at(J.g, J.B.bct, bc_time(J.B.hdr, 2), J.B.S, I, Jr);
   });
 }
 
@@ -308,6 +332,10 @@ void fill_counts(BJob& J) {
   J.ay = g.dim == 2 ? (g.NY + 1 + 255) / 256 : 0;
   J.nsy = g.dim == 2 ? J.ay * g.NX : 0;
   J.as = (g.NX + 255) / 256;
+  J.gr = g.dim == 2 ? 2 * H : 0;
+  J.r0 = std::max(1, (g.NX - H) / 256);
+  J.sg = J.as == 1 ? 1 : 1 + (J.as - J.r0);
+  J.ns = J.gr * J.as + (g.NY - J.gr) * J.sg;
   J.ltx = (g.NX + LT_X - 1) / LT_X;
   J.lty = (g.NY + LT_Y - 1) / LT_Y;
   if (g.dim == 2) {
@@ -326,8 +354,8 @@ void fill_counts(BJob& J) {
 long long items(const BJob& J, int ph) {
   switch (ph) {
     case PH_DT: return 1;
-    case PH_PREP: return (long long)J.nsx + J.nsy + (long long)J.as * J.g.NY;
-    case PH_BCS: return (long long)J.as * J.g.NY;
+    case PH_PREP: return (long long)J.nsx + J.nsy + J.ns;
+    case PH_BCS: return J.ns;
     case PH_LINES: return J.g.dim == 2 ? (long long)J.ltx * J.lty : 0;
     case PH_FX2: case PH_FX3: case PH_FX4:
       return J.M == 2 + (ph - PH_FX2) ? (long long)J.fnb[0][0] * J.fnb[0][1] : 0;
