@@ -33,7 +33,9 @@ __global__ void k_init_sigma(Geo g, int which, double gam, const double* U, doub
 
 // code: the time the ghosts are for (bc_time)
 __global__ void k_bc_state(Geo g, const BcTable* T, const Header* hdr, int code, double* U) {
-  bc_state_at(g, T, bc_time(hdr, code), U, blockIdx.x * blockDim.x + threadIdx.x, blockIdx.y);
+  int I, Jr;
+  GhostItems(g).at(g, blockIdx.x, I, Jr);
+  bc_state_at(g, T, bc_time(hdr, code), U, I, Jr);
 }
 
 __global__ void k_bc_sigma(Geo g, const BcTable* T, const Header* hdr, int which, const double* sxn, double* sxo,
@@ -122,7 +124,7 @@ static inline void tick(Marks* mk, hipStream_t st) {
 hipError_t launch_bc_state(const cgks_plan* p, const Bufs& b, double* U, int code, hipStream_t st,
                            Marks* mk = nullptr) {
   const Geo& g = p->g;
-  dim3 grid((g.NX + 255) / 256, g.NY);
+  const dim3 grid(GhostItems(g).count(g));   // the segments that hold ghost cells
   hipLaunchKernelGGL(k_bc_state, grid, dim3(256), 0, st, g, b.bct, b.hdr, code, U);
   tick(mk, st);
   return hipGetLastError();

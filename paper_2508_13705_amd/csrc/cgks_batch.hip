@@ -34,15 +34,12 @@ struct BJob {
   double sbc;              // largest |U| + c of the job's prescribed boundary states
   long long max_steps;
   int viscous, M, slot, pad;
-  int ax, ay, as;          // 256-wide segments per row: sigma x-faces, sigma y-faces, state rows
+  int ax, ay;              // 256-wide segments per row: sigma x-faces, sigma y-faces
   int nsx, nsy;            // PREP items of the sigma x / y parts
   int fnb[2][2];           // face tiles (along normal, along tangential) of x- and y-faces
   int ltx, lty;            // Step 1 tiles along x and y
   int nseg;                // 1-D stage segments
-  // ghost-cell items: every 256-cell segment of the gr ghost rows (2-D), and
-  // of the other rows only the segments holding ghost cells (segment 0 and
-  // segments r0..as-1), sg per row; ns items in all
-  int gr, sg, r0, ns;
+  int ns;                  // ghost-cell items (GhostItems)
 };
 
 struct BTab {
@@ -94,22 +91,6 @@ __device__ __forceinline__ void for_items(const BTab* tab, int ph, int remap, F&
   }
 }
 
-// State item k of job J -> (padded column of this thread, padded row).
-__device__ __forceinline__ void state_item(const BJob& J, int k, int& I, int& Jr) {
-  int seg;
-  if (k < J.gr * J.as) {
-    const int q = k / J.as;
-    Jr = q < H ? q : J.g.NY - 2 * H + q;
-    seg = k % J.as;
-  } else {
-    k -= J.gr * J.as;
-    const int idx = k % J.sg;
-    Jr = (J.gr ? H : 0) + k / J.sg;
-    seg = idx == 0 ? 0 : J.r0 + idx - 1;
-  }
-  I = seg * 256 + (int)threadIdx.x;
-}
-
 __global__ __launch_bounds__(256) void kb_dt(const BTab* tab) {
   const int n = tab->njobs;
   for (int j = blockIdx.x; j < n; j += gridDim.x) {
@@ -136,7 +117,7 @@ __global__ __launch_bounds__(256) void kb_prep(const BTab* tab, int remap) {
     }
     k -= J.nsy;
     int I, Jr;
-    state_item(J, k, I, Jr);
+    GhostItems(J.g).at(J.g, k, I, Jr);
     bc_state_at(J.g, J.B.bct, bc_time(J.B.hdr, 1), J.B.U, I, Jr);
   });
 }
@@ -146,7 +127,7 @@ __global__ __launch_bounds__(256) void kb_bcs(const BTab* tab, int remap) {
   for_items(tab, PH_BCS, remap, [&](const BJob& J, int k) {
     if (!J.B.hdr->active) return;
     int I, Jr;
-    state_item(J, k, I, Jr);
+    GhostItems(J.g).at(J.g, k, I, Jr);
     bc_state_at(J.g, J.B.bct, bc_time(J.B.hdr, 2), J.B.S, I, Jr);
   });
 }
@@ -331,11 +312,7 @@ void fill_counts(BJob& J) {
   J.nsx = J.ax * g.NY;
   J.ay = g.dim == 2 ? (g.NY + 1 + 255) / 256 : 0;
   J.nsy = g.dim == 2 ? J.ay * g.NX : 0;
-  J.as = (g.NX + 255) / 256;
-  J.gr = g.dim == 2 ? 2 * H : 0;
-  J.r0 = std::max(1, (g.NX - H) / 256);
-  J.sg = J.as == 1 ? 1 : 1 + (J.as - J.r0);
-  J.ns = J.gr * J.as + (g.NY - J.gr) * J.sg;
+  J.ns = GhostItems(g).count(g);
   J.ltx = (g.NX + LT_X - 1) / LT_X;
   J.lty = (g.NY + LT_Y - 1) / LT_Y;
   if (g.dim == 2) {

@@ -244,6 +244,33 @@ __device__ __forceinline__ double wall_sign(int kind, int v, int nv_n, int D) {
   return 1.0;
 }
 
+// Items of the ghost-cell fill: the 256-cell segments of the padded rows that
+// hold ghost cells.  Every segment of the 2-D ghost rows (gr of them); of the
+// other rows segment 0 and the segments r0..as-1 of the right-hand ghosts,
+// which can straddle a segment boundary (sg segments per row).
+struct GhostItems {
+  int as, gr, r0, sg;
+  __host__ __device__ explicit GhostItems(const Geo& g)
+      : as((g.NX + 255) / 256), gr(g.dim == 2 ? 2 * H : 0), r0((g.NX - H) / 256 > 1 ? (g.NX - H) / 256 : 1),
+        sg(as == 1 ? 1 : 1 + (as - r0)) {}
+  __host__ __device__ int count(const Geo& g) const { return gr * as + (g.NY - gr) * sg; }
+  // item k -> padded row Jr and the padded column I of this thread
+  __device__ void at(const Geo& g, int k, int& I, int& Jr) const {
+    int seg;
+    if (k < gr * as) {
+      const int q = k / as;
+      Jr = q < H ? q : g.NY - 2 * H + q;
+      seg = k % as;
+    } else {
+      k -= gr * as;
+      const int idx = k % sg;
+      Jr = (gr ? H : 0) + k / sg;
+      seg = idx == 0 ? 0 : r0 + idx - 1;
+    }
+    I = seg * 256 + (int)threadIdx.x;
+  }
+};
+
 // Ghost cell (I, J) (padded indices) at time tb.  A ghost row of a y-side
 // takes that side's rule at the column's centre; its source cell, or an
 // x-ghost of an interior row, takes the x-side rule at the row's centre
