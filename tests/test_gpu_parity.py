@@ -211,3 +211,47 @@ def test_bitwise_reproducible_across_runs(precision):
             del s, junk
         for k in ("avg", "sx", "sy", "sigx", "sigy"):
             assert np.array_equal(outs[0][k], outs[1][k]), (order, k)
+
+
+# Grid sides whose padded width (n + 6) ends just past a 256-cell boundary, or
+# one short of it: the ghost-cell fill covers segment 0 and the segments of
+# the right-hand ghosts, which at n + 6 = 256k + 1 or 256k + 2 straddle two.
+STRADDLE = [250, 251, 252, 507, 508]
+
+
+@pytest.mark.parametrize("n", STRADDLE)
+def test_ghost_segments_periodic_1d(n):
+    pb = W.fourier_1d(n=n, order=5, nsteps=20)
+    got, ref, _ = run_both(pb)
+    assert_parity(got, ref, 1, h=cell(pb))
+
+
+@pytest.mark.parametrize("n", [251, 507])
+def test_ghost_segments_periodic_2d(n):
+    ny = 9
+    pb = W.quadrant_2d(W.random_quadrants(3), n, 7, nsteps=4, bc="periodic", name=f"q_periodic_{n}")
+    pb["grid"]["ny"] = ny
+    pb["grid"]["y1"] = pb["grid"]["y0"] + (pb["grid"]["y1"] - pb["grid"]["y0"]) * ny / n
+    pb["state"] = {k: v[..., :ny, :] for k, v in pb["state"].items()}
+    got, ref, _ = run_both(pb)
+    assert_parity(got, ref, 2, h=cell(pb))
+
+
+def test_ghost_segments_batched_equal_alone():
+    """The same sides as 1-D jobs of one batch: bit-identical to each alone."""
+    from paper_2508_13705_amd import cgks
+    pbs = [W.fourier_1d(n=n, order=5, nsteps=12) for n in STRADDLE]
+    b = cgks.Batch(1, "fp64", max_jobs=len(pbs))
+    sol = [cgks.Solver(pb) for pb in pbs]
+    for s in sol:
+        b.add(s, max_steps=12)
+    b.commit()
+    b.step(12)
+    b.poll()
+    for pb, s in zip(pbs, sol):
+        alone = cgks.Solver(pb)
+        alone.step(12)
+        a, g = alone.read(), s.read()
+        assert g["steps"] == a["steps"] == 12
+        for k in ("avg", "sx", "sigx"):
+            assert np.array_equal(g[k], a[k]), (pb["grid"]["nx"], k)
