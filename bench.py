@@ -393,7 +393,8 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32 reconstruction/flux, f64 accumulation",
+        "dtype": "f32+f64",
+        "dtype_detail": "f32 reconstruction and flux moments, f64 accumulation and time coefficients",
         "data": "synthetic",
         "config": {"workload": f"2-D Navier-Stokes turbulence {n}x{n} periodic, order 9 (m=4), viscous tau "
                                f"mu=1e-4, Pr=0.72, Mach 0.3, k^-5/3 spectrum 1<=|k|<=32, CFL 0.2, seed 4",
