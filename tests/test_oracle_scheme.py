@@ -185,8 +185,20 @@ def test_le_blanc_is_reported_not_silently_wrong():
     r = oracle.run(pb)
     assert r["status"] in (0, 4)
     if r["status"] == 4:
-        assert r["stats"]["steps"] < 10
+        k = r["stats"]["steps"]
+        assert k < 10
         assert r["t"] < pb["run"]["t_end"]
+        g = pb["riemann"]["gamma"]
+
+        def physical(a):
+            p = (g - 1) * (a[2] - 0.5 * a[1] ** 2 / a[0])
+            return bool(np.all(np.isfinite(a)) and np.all(a[0] > 0) and np.all(p > 0))
+
+        # the step that reports it is the first whose stage or final state
+        # is nonphysical (A34: that step completes, then the run stops)
+        prev = oracle.run(pb, nsteps=k - 1)
+        assert prev["status"] == 0 and physical(prev["avg"])
+        assert not physical(r["avg"])
 
 
 @pytest.mark.slow
