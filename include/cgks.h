@@ -118,11 +118,25 @@ typedef struct {
 
 typedef struct cgks_plan cgks_plan;
 
-/* Counters accumulated on the device since cgks_init_state. */
+/* Counters accumulated on the device since cgks_init_state.
+ * Reconstructions are counted once per (cell, Gauss line or node) and stage,
+ * as Algorithm 1 takes them: in 1-D the cells 0..nx-1 and the two ghost cells
+ * beside the boundary faces; in 2-D, per direction, the interior cells of
+ * Step 1 (line values, Sec. 3.3) and of Step 2 on each of the m Gauss lines.
+ * recon_total = steps * 2 * (nx + 2) in 1-D, steps * 2 * 2 nx ny (1 + m) in
+ * 2-D, is split by branch: ao_branch + linear[0] + linear[1] + linear[2]. */
 typedef struct {
   long long nonphysical;        /* cell averages found with rho <= 0 or p <= 0 */
   long long fallbacks;          /* Gauss-point states replaced by the cell average (rho or p <= 0) */
   long long steps;              /* completed steps */
+  long long recon_total;        /* reconstructions taken (see above) */
+  long long dff_lt1;            /* reconstructions in which the DFF of the scheme's full stencil was
+                                   below 1, so the cascade stepped down (Eq. 3.3, Algorithm 1) */
+  long long ao_branch;          /* reconstructions by the AO(5,3) branch (DFF of the 5th-order stencil < 1) */
+  long long linear[3];          /* reconstructions by the linear 5th-, 7th- and 9th-order stencils */
+  long long near_ties;          /* cascade decisions taken with the stencil sum A (Eq. 3.4) within
+                                   1e-12 sigma_thres (FP64) or 1e-5 sigma_thres (FP32-flux) of the
+                                   threshold, where rounding can change the branch */
 } cgks_health;
 
 /* Validate the descriptors and build a plan (host metadata only).
@@ -174,11 +188,29 @@ cgks_status cgks_step_timed(const cgks_plan* plan, void* d_state, void* d_work, 
 const char* cgks_kernel_name(const cgks_plan* plan, int index);
 
 /* Copy the state back (synchronises `stream`).  Any pointer may be NULL.
- * Layouts as in cgks_init_state; h_time, h_steps: scalars.  Returns
- * CGKS_ENONPHYSICAL (after copying) if a nonphysical cell average was seen. */
+ * Layouts as in cgks_init_state; h_time, h_steps: scalars.
+ *   h_grad_x, h_grad_y  [nv][ny][nx] cell-averaged gradients: in 2-D the
+ *              Gauss-weighted means of the line-averaged slopes,
+ *              sum_l w_l h_slope_x[v][l] (Sec. 3.3); in 1-D h_grad_x is the
+ *              cell-averaged slope and h_grad_y is not written.
+ * Returns CGKS_ENONPHYSICAL (after copying) if a nonphysical cell average
+ * was seen. */
 cgks_status cgks_read_state(const cgks_plan* plan, const void* d_state, const void* d_work, double* h_avg,
-                            double* h_slope_x, double* h_slope_y, double* h_sigma_x, double* h_sigma_y,
-                            double* h_time, long long* h_steps, void* stream);
+                            double* h_grad_x, double* h_grad_y, double* h_slope_x, double* h_slope_y,
+                            double* h_sigma_x, double* h_sigma_y, double* h_time, long long* h_steps,
+                            void* stream);
+
+/* Totals of the conserved variables over the interior cells, sum_i W_i (so
+ * h^d times the totals of Sec. 2.2), in FP64: d_sums[0..nv-1] in device
+ * memory (caller-owned), written on `stream` (no host synchronisation, no
+ * allocation; capturable in a hipGraph).  Deterministic: a fixed-order
+ * tree of compensated (double-double) partial sums that depends only on the
+ * grid size, so the same state gives the same bits on every call; the
+ * result is within an ulp or two of the exactly rounded sum.  Uses the
+ * reduction area of d_work, so it must not overlap a step of the same state
+ * on another stream.  Errors: CGKS_EINVAL (NULL pointers), CGKS_EHIP. */
+cgks_status cgks_conservation_sums(const cgks_plan* plan, const void* d_state, void* d_work, double* d_sums,
+                                   void* stream);
 
 /* Device counters (synchronises `stream`); returns CGKS_ENONPHYSICAL when
  * nonphysical > 0. */

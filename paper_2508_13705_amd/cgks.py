@@ -23,8 +23,8 @@ GAUSS_M = {5: 2, 7: 3, 9: 4}
 
 # every symbol include/cgks.h declares
 EXPORTS = ["cgks_plan_create", "cgks_plan_sizes", "cgks_init_state", "cgks_step", "cgks_step_timed",
-           "cgks_kernel_name", "cgks_read_state", "cgks_query_health", "cgks_plan_destroy", "cgks_status_string",
-           "cgks_last_error",
+           "cgks_kernel_name", "cgks_read_state", "cgks_conservation_sums", "cgks_query_health",
+           "cgks_plan_destroy", "cgks_status_string", "cgks_last_error",
            "cgks_batch_create", "cgks_batch_destroy", "cgks_batch_add", "cgks_batch_remove", "cgks_batch_commit",
            "cgks_batch_step", "cgks_batch_capture", "cgks_batch_launch", "cgks_batch_poll", "cgks_batch_info",
            "cgks_batch_set_tuning", "cgks_batch_get_tuning", "cgks_batch_tune"]
@@ -91,7 +91,10 @@ class SchemeDesc(ctypes.Structure):
 
 
 class Health(ctypes.Structure):
-    _fields_ = [("nonphysical", ctypes.c_longlong), ("fallbacks", ctypes.c_longlong), ("steps", ctypes.c_longlong)]
+    _fields_ = [("nonphysical", ctypes.c_longlong), ("fallbacks", ctypes.c_longlong), ("steps", ctypes.c_longlong),
+                ("recon_total", ctypes.c_longlong), ("dff_lt1", ctypes.c_longlong),
+                ("ao_branch", ctypes.c_longlong), ("linear", ctypes.c_longlong * 3),
+                ("near_ties", ctypes.c_longlong)]
 
 
 class JobStatus(ctypes.Structure):
@@ -127,7 +130,9 @@ def lib():
                                       ctypes.POINTER(ctypes.c_int)]
         L.cgks_kernel_name.restype = ctypes.c_char_p
         L.cgks_kernel_name.argtypes = [vp, ctypes.c_int]
-        L.cgks_read_state.argtypes = [vp, vp, vp, dp, dp, dp, dp, dp, dp, ctypes.POINTER(ctypes.c_longlong), vp]
+        L.cgks_read_state.argtypes = [vp, vp, vp, dp, dp, dp, dp, dp, dp, dp, dp,
+                                      ctypes.POINTER(ctypes.c_longlong), vp]
+        L.cgks_conservation_sums.argtypes = [vp, vp, vp, vp, vp]
         L.cgks_query_health.argtypes = [vp, vp, ctypes.POINTER(Health), vp]
         L.cgks_plan_destroy.argtypes = [vp]
         L.cgks_batch_create.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_size_t, ctypes.POINTER(vp)]
@@ -288,24 +293,37 @@ class Solver:
         steps = ctypes.c_longlong()
         if sync_only:
             st = lib().cgks_read_state(self.plan.handle, ctypes.c_void_p(self.state.data_ptr()),
-                                       ctypes.c_void_p(self.work.data_ptr()), None, None, None, None, None,
-                                       ctypes.byref(t), ctypes.byref(steps), _stream_handle(self.stream))
+                                       ctypes.c_void_p(self.work.data_ptr()), None, None, None, None, None, None,
+                                       None, ctypes.byref(t), ctypes.byref(steps), _stream_handle(self.stream))
             if st not in (OK, ENONPHYSICAL):
                 check(st)
             return {"t": t.value, "steps": steps.value, "status": st}
         avg = np.zeros((nv, ny, nx) if dim == 2 else (nv, nx))
+        gx = np.zeros_like(avg)
+        gy = np.zeros_like(avg) if dim == 2 else None
         sx = np.zeros((nv, m, ny, nx) if dim == 2 else (nv, nx))
         sy = np.zeros((nv, m, ny, nx)) if dim == 2 else None
         sgx = np.zeros((ny, nx + 1) if dim == 2 else (nx + 1,))
         sgy = np.zeros((ny + 1, nx)) if dim == 2 else None
         st = lib().cgks_read_state(self.plan.handle, ctypes.c_void_p(self.state.data_ptr()),
-                                   ctypes.c_void_p(self.work.data_ptr()), _dptr(avg), _dptr(sx), _dptr(sy),
-                                   _dptr(sgx), _dptr(sgy), ctypes.byref(t), ctypes.byref(steps),
-                                   _stream_handle(self.stream))
+                                   ctypes.c_void_p(self.work.data_ptr()), _dptr(avg), _dptr(gx), _dptr(gy),
+                                   _dptr(sx), _dptr(sy), _dptr(sgx), _dptr(sgy), ctypes.byref(t),
+                                   ctypes.byref(steps), _stream_handle(self.stream))
         if st not in (OK, ENONPHYSICAL):
             check(st)
-        return {"avg": avg, "sx": sx, "sy": sy, "sigx": sgx, "sigy": sgy, "t": t.value, "steps": steps.value,
-                "status": st}
+        return {"avg": avg, "gx": gx, "gy": gy, "sx": sx, "sy": sy, "sigx": sgx, "sigy": sgy, "t": t.value,
+                "steps": steps.value, "status": st}
+
+    def conservation_sums(self, out=None):
+        """Enqueue the device totals of the conserved variables into ``out`` (a
+        float64 device tensor of nv entries, allocated here if None); returns it."""
+        nv = self.dims[0] + 2
+        if out is None:
+            out = self.torch.empty(nv, dtype=self.torch.float64, device=self.device)
+        check(lib().cgks_conservation_sums(self.plan.handle, ctypes.c_void_p(self.state.data_ptr()),
+                                           ctypes.c_void_p(self.work.data_ptr()), ctypes.c_void_p(out.data_ptr()),
+                                           _stream_handle(self.stream)))
+        return out
 
     def health(self):
         h = Health()
@@ -313,7 +331,9 @@ class Solver:
                                      _stream_handle(self.stream))
         if st not in (OK, ENONPHYSICAL):
             check(st)
-        return {"nonphysical": h.nonphysical, "fallbacks": h.fallbacks, "steps": h.steps, "status": st}
+        return {"nonphysical": h.nonphysical, "fallbacks": h.fallbacks, "steps": h.steps,
+                "recon_total": h.recon_total, "dff_lt1": h.dff_lt1, "ao": h.ao_branch, "linear5": h.linear[0],
+                "linear7": h.linear[1], "linear9": h.linear[2], "near_ties": h.near_ties, "status": st}
 
 
 class Batch:

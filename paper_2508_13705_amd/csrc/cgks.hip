@@ -60,11 +60,11 @@ __device__ __forceinline__ int xcd_block(int b, int n) {
 
 template <int M>
 __global__ __launch_bounds__(256) void k_lines(Geo g, Consts C, const double* U, const double* sxo,
-                                               const double* syo, double* lvx, double* lvy, const Header* hdr) {
+                                               const double* syo, double* lvx, double* lvy, Header* hdr) {
   __shared__ double sm[LinesLds::total];
   if (!hdr->active) return;
   const int lb = xcd_block(blockIdx.y * gridDim.x + blockIdx.x, gridDim.x * gridDim.y);
-  lines_tile<M>(g, C, U, sxo, syo, lvx, lvy, lb % gridDim.x, lb / gridDim.x, sm);
+  lines_tile<M>(g, C, U, sxo, syo, lvx, lvy, hdr, lb % gridDim.x, lb / gridDim.x, sm);
 }
 
 // Grid (tiles along the normal, tiles along the tangential).  x-face tiles
@@ -86,6 +86,14 @@ __global__ __launch_bounds__(256) void k_stage1d(Geo g, Consts C, Bufs B) {
   __shared__ double res[256][12];
   __shared__ __align__(16) unsigned char sm[Lds1D<T>::total];
   stage1d_seg<STAGE, T, PR>(g, C, B, res, sm, blockIdx.x, gridDim.x);
+}
+
+__global__ __launch_bounds__(256) void k_sum1(Geo g, const double* U, DD* part, int nblk) {
+  sums_pass1(g, U, part, nblk, blockIdx.x);
+}
+
+__global__ __launch_bounds__(256) void k_sum2(int nv, const DD* part, int nblk, double* out) {
+  sums_pass2(nv, part, nblk, out);
 }
 
 __global__ void k_reduce(Geo g, double gam, const double* U, Bufs B) {
@@ -382,6 +390,10 @@ cgks_status cgks_plan_create(const cgks_grid_desc* gd, const cgks_scheme_desc* s
   C.ghi = sd->gamma_hi;
   C.glo = sd->gamma_lo;
   C.eps = sd->weno_eps;
+  // near-tie band of the cascade decisions: the strengths entering A carry
+  // the rounding of the flux arithmetic (FP64, or FP32 in the FP32-flux
+  // variant), summed over up to 12 weighted faces
+  C.tie = sd->sigma_thres * (sd->precision == CGKS_FP64 ? 1e-12 : 1e-5);
   C.dx = p->dx;
   C.dy = p->dy;
   C.tau_model = sd->tau_model;
@@ -416,6 +428,11 @@ cgks_status cgks_plan_create(const cgks_grid_desc* gd, const cgks_scheme_desc* s
   p->off_part = o; o += up(2 * p->max_parts);
   p->off_hdr = o; o += 32;
   p->off_bct = o; o += up((sizeof(BcTable) + 7) / 8);
+  {
+    const long long nint = (long long)g.nx * g.ny;
+    p->sum_blocks = (int)((nint + SUM_CHUNK - 1) / SUM_CHUNK);
+    p->off_sum = o; o += up((size_t)p->sum_blocks * nv * 2);
+  }
   p->work_words = o;
   *out = p;
   return CGKS_OK;
@@ -546,8 +563,9 @@ const char* cgks_kernel_name(const cgks_plan* p, int index) {
 }
 
 cgks_status cgks_read_state(const cgks_plan* p, const void* d_state, const void* d_work, double* h_avg,
-                            double* h_slope_x, double* h_slope_y, double* h_sigma_x, double* h_sigma_y,
-                            double* h_time, long long* h_steps, void* stream) {
+                            double* h_grad_x, double* h_grad_y, double* h_slope_x, double* h_slope_y,
+                            double* h_sigma_x, double* h_sigma_y, double* h_time, long long* h_steps,
+                            void* stream) {
   if (!p || !d_state || !d_work) return fail(CGKS_EINVAL, "NULL argument");
   hipStream_t st = (hipStream_t)stream;
   const Geo& g = p->g;
@@ -569,6 +587,16 @@ cgks_status cgks_read_state(const cgks_plan* p, const void* d_state, const void*
           if (h_slope_x) h_slope_x[(((size_t)v * m + l) * ny + j) * nx + i] = hs[g.sx(v, l, i, j)];
           if (g.dim == 2 && h_slope_y) h_slope_y[(((size_t)v * m + l) * ny + j) * nx + i] = hs[g.sy(v, l, i, j)];
         }
+        // cell-averaged gradients: Gauss-weighted means of the line slopes
+        // (1-D: the stored slope itself)
+        double gxs = 0.0, gys = 0.0;
+        for (int l = 0; l < m; ++l) {
+          const double w = g.dim == 2 ? kGw[m][l] : 1.0;
+          gxs += w * hs[g.sx(v, l, i, j)];
+          if (g.dim == 2) gys += w * hs[g.sy(v, l, i, j)];
+        }
+        if (h_grad_x) h_grad_x[((size_t)v * ny + j) * nx + i] = gxs;
+        if (h_grad_y && g.dim == 2) h_grad_y[((size_t)v * ny + j) * nx + i] = gys;
       }
   if (h_sigma_x)
     for (int j = 0; j < ny; ++j)
@@ -593,7 +621,33 @@ cgks_status cgks_query_health(const cgks_plan* p, const void* d_work, cgks_healt
   out->nonphysical = (long long)hh.nonphysical;
   out->fallbacks = (long long)hh.fallbacks;
   out->steps = (long long)hh.steps;
+  // the device counts the branches below the scheme's order; the full
+  // order's count is the rest of the reconstructions taken
+  const Geo& g = p->g;
+  const long long per_stage =
+      g.dim == 2 ? 2ll * g.nx * g.ny * (1 + g.m) : (long long)g.nx + 2;
+  out->recon_total = out->steps * 2 * per_stage;
+  const long long ao = (long long)hh.rec_ao, l5 = (long long)hh.rec_lin5, l7 = (long long)hh.rec_lin7;
+  const int order = p->C.order;
+  out->ao_branch = ao;
+  out->linear[0] = order == 5 ? out->recon_total - ao : l5;
+  out->linear[1] = order == 7 ? out->recon_total - ao - l5 : (order == 9 ? l7 : 0);
+  out->linear[2] = order == 9 ? out->recon_total - ao - l5 - l7 : 0;
+  out->dff_lt1 = ao + (order > 5 ? l5 : 0) + (order > 7 ? l7 : 0);
+  out->near_ties = (long long)hh.ties;
   if (hh.nonphysical) return fail(CGKS_ENONPHYSICAL, "nonphysical cell average");
+  return CGKS_OK;
+}
+
+cgks_status cgks_conservation_sums(const cgks_plan* p, const void* d_state, void* d_work, double* d_sums,
+                                   void* stream) {
+  if (!p || !d_state || !d_work || !d_sums) return fail(CGKS_EINVAL, "NULL argument");
+  hipStream_t st = (hipStream_t)stream;
+  DD* part = (DD*)((double*)d_work + p->off_sum);
+  hipLaunchKernelGGL(k_sum1, dim3(p->sum_blocks), dim3(256), 0, st, p->g, (const double*)d_state, part,
+                     p->sum_blocks);
+  hipLaunchKernelGGL(k_sum2, dim3(1), dim3(256), 0, st, p->g.nv, (const DD*)part, p->sum_blocks, d_sums);
+  HIP_TRY(hipGetLastError());
   return CGKS_OK;
 }
 

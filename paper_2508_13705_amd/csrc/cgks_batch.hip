@@ -140,9 +140,9 @@ __global__ __launch_bounds__(256) void kb_lines(const BTab* tab, int stage, int 
     const double* Uin = stage == 1 ? J.B.U : J.B.S;
     const int bx = k % J.ltx, by = k / J.ltx;
     switch (J.M) {
-      case 2: lines_tile<2, true>(J.g, J.C, Uin, J.B.sxo, J.B.syo, J.B.lvx, J.B.lvy, bx, by, sm); break;
-      case 3: lines_tile<3, true>(J.g, J.C, Uin, J.B.sxo, J.B.syo, J.B.lvx, J.B.lvy, bx, by, sm); break;
-      default: lines_tile<4, true>(J.g, J.C, Uin, J.B.sxo, J.B.syo, J.B.lvx, J.B.lvy, bx, by, sm); break;
+      case 2: lines_tile<2, true>(J.g, J.C, Uin, J.B.sxo, J.B.syo, J.B.lvx, J.B.lvy, J.B.hdr, bx, by, sm); break;
+      case 3: lines_tile<3, true>(J.g, J.C, Uin, J.B.sxo, J.B.syo, J.B.lvx, J.B.lvy, J.B.hdr, bx, by, sm); break;
+      default: lines_tile<4, true>(J.g, J.C, Uin, J.B.sxo, J.B.syo, J.B.lvx, J.B.lvy, J.B.hdr, bx, by, sm); break;
     }
   });
 }

@@ -31,6 +31,7 @@ struct Consts {
   double iKd;                // 1 / Kd
   double c1, c2, mu, prandtl;
   double thres, ghi, glo, eps;
+  double tie;                // |A - thres| <= tie: a cascade decision counted as a near tie
   double dx, dy;
   int tau_model, order, m;
 };
@@ -525,15 +526,21 @@ CGKS_HD void gks_flux(const T (&Wl)[6][4], const T (&Wr)[6][4], double dt, const
 // ---------------------------------------------------------------------------
 struct Cascade {
   int branch;          // 0: AO(5,3); 5, 7, 9: linear stencil of that order
+  bool tie;            // a decision taken with A within the tie band of the threshold
   double al[4];        // AO: DFF of S0, S1, S2 and of the 5th-order stencil
 };
 
 CGKS_HD __forceinline__ double dff_of(double A, double thres) { return (A < thres) ? 1.0 : thres / A; }
 
-CGKS_HD __forceinline__ Cascade cascade(const double* s, int order, double thres) {
+// tie: half-width of the band around the threshold in which a decision
+// counts as a near tie (rounding of the strengths can move A across it).
+// Only the decisions the cascade takes are judged; the DFF values
+// themselves are continuous in A.
+CGKS_HD __forceinline__ Cascade cascade(const double* s, int order, double thres, double tie) {
   Cascade c;
   const double A5 = 2.0 * s[1] + 2.0 * s[2] + 2.0 * s[3] + 2.0 * s[4];
   const double a5 = dff_of(A5, thres);
+  c.tie = fabs(A5 - thres) <= tie;
   if (a5 < 1.0) {
     c.branch = 0;
     c.al[0] = dff_of(2.0 * s[1] + 2.0 * s[2] + s[3], thres);
@@ -544,9 +551,11 @@ CGKS_HD __forceinline__ Cascade cascade(const double* s, int order, double thres
   }
   if (order == 5) { c.branch = 5; return c; }
   const double A7 = s[0] + 2.0 * s[1] + 2.0 * s[2] + 2.0 * s[3] + 2.0 * s[4] + s[5];
+  c.tie = c.tie || fabs(A7 - thres) <= tie;
   if (dff_of(A7, thres) < 1.0) { c.branch = 5; return c; }
   if (order == 7) { c.branch = 7; return c; }
   const double A9 = 2.0 * s[0] + 2.0 * s[1] + 2.0 * s[2] + 2.0 * s[3] + 2.0 * s[4] + 2.0 * s[5];
+  c.tie = c.tie || fabs(A9 - thres) <= tie;
   c.branch = (dff_of(A9, thres) < 1.0) ? 7 : 9;
   return c;
 }

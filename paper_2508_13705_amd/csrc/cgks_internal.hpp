@@ -78,7 +78,11 @@ struct Header {
   unsigned long long magic;
   int active;
   int nparts;      // per-block speed partials written by the last reduction
-  int pad[14];
+  // reconstructions (cell, line) by cascade branch below the scheme's order:
+  // AO(5,3), linear 5th order (orders 7, 9), linear 7th order (order 9);
+  // and cascade decisions taken within the tie band of the threshold
+  unsigned long long rec_ao, rec_lin5, rec_lin7, ties;
+  int pad[6];
 };
 static_assert(sizeof(Header) <= 256, "header");
 
@@ -163,8 +167,10 @@ struct cgks_plan {
   int precision;
   double dx, dy;
   size_t state_words, sig_x_words, sig_y_words;
-  size_t off_S, off_A, off_sxo, off_sxn, off_syo, off_syn, off_lvx, off_lvy, off_part, off_hdr, off_bct, work_words;
+  size_t off_S, off_A, off_sxo, off_sxn, off_syo, off_syn, off_lvx, off_lvy, off_part, off_hdr, off_bct, off_sum,
+      work_words;
   size_t max_parts;
+  int sum_blocks;  // blocks of the conservation-sum reduction (its partials sit at off_sum)
   BcTable bct;     // copied into the work buffer by cgks_init_state
 };
 
@@ -389,6 +395,51 @@ __device__ __forceinline__ double sigma_pair(const double* Wl, const double* Wr,
 
 
 // ---------------------------------------------------------------------------
+// Health tally of a tile's reconstructions.  Each wave counts, by ballot, the
+// reconstructions it owns that took a cascade branch below the scheme's
+// order, and the near ties, into LDS; one thread then adds the tile's
+// nonzero counts to the header.  Reconstructions of the full order are not
+// counted: their number follows from the reconstructions per step, so
+// smooth tiles issue no global atomics.  Every tile reconstructs its halo
+// cells too; only the cells and lines the tile updates are its own, so each
+// reconstruction of the grid is counted once.
+// ---------------------------------------------------------------------------
+struct Tally {
+  unsigned int c[4];   // AO(5,3), linear 5, linear 7, near ties
+};
+
+// before the first tally_add of a tile, separated from it by a barrier
+__device__ __forceinline__ void tally_zero(Tally& t, int tid) {
+  if (tid < 4) t.c[tid] = 0u;
+}
+
+// called by every lane of the block (ballots are per wave)
+__device__ __forceinline__ void tally_add(Tally& t, bool own, int branch, bool tie, int order, int tid) {
+  const unsigned long long m0 = __ballot(own && branch == 0);
+  const unsigned long long m5 = __ballot(own && branch == 5 && order > 5);
+  const unsigned long long m7 = __ballot(own && branch == 7 && order > 7);
+  const unsigned long long mt = __ballot(own && tie);
+  if ((tid & 63) == 0) {
+    if (m0) atomicAdd(&t.c[0], (unsigned int)__popcll(m0));
+    if (m5) atomicAdd(&t.c[1], (unsigned int)__popcll(m5));
+    if (m7) atomicAdd(&t.c[2], (unsigned int)__popcll(m7));
+    if (mt) atomicAdd(&t.c[3], (unsigned int)__popcll(mt));
+  }
+}
+
+// after a barrier that follows the last tally_add of the tile
+__device__ __forceinline__ void tally_flush(const Tally& t, Header* hdr, int tid) {
+  if (tid == 0) {
+    const unsigned int a = t.c[0], b = t.c[1], c = t.c[2], d = t.c[3];
+    if (a) atomicAdd(&hdr->rec_ao, (unsigned long long)a);
+    if (b) atomicAdd(&hdr->rec_lin5, (unsigned long long)b);
+    if (c) atomicAdd(&hdr->rec_lin7, (unsigned long long)c);
+    if (d) atomicAdd(&hdr->ties, (unsigned long long)d);
+  }
+}
+
+
+// ---------------------------------------------------------------------------
 // time step (Sec. 4): reduction of max(|U| + c) and min(rho), then dt
 // ---------------------------------------------------------------------------
 // Block-level max(|U| + c) and min(rho); thread 0 writes the block's partial
@@ -503,6 +554,74 @@ __device__ void dt_block(Header* hdr, const double* part, double sbc, double dt_
 
 
 // ---------------------------------------------------------------------------
+// Conservation totals: sum over the interior cells of each conserved
+// variable in a fixed order, with compensated (double-double) partial sums.
+// Block b of the first pass takes the interior cells b*SUM_CHUNK .. (b+1)*
+// SUM_CHUNK - 1 in row-major order, each thread every 256th of them in
+// ascending order; the block's partials are combined by a fixed pairwise
+// tree.  The second pass, one block, combines the block partials the same
+// way.  The order depends only on the grid size, so results are bitwise
+// reproducible.
+// ---------------------------------------------------------------------------
+constexpr int SUM_CHUNK = 256 * 64;   // interior cells per block of the first pass
+
+struct DD {
+  double hi, lo;
+};
+// error-free sum of two doubles (Knuth's TwoSum), then renormalised
+__device__ __forceinline__ DD dd_add(DD a, DD b) {
+  const double s = a.hi + b.hi;
+  const double bb = s - a.hi;
+  const double e = (a.hi - (s - bb)) + (b.hi - bb);
+  const double lo = e + a.lo + b.lo;
+  const double hi = s + lo;
+  return DD{hi, lo - (hi - s)};
+}
+
+// 256 threads; part[v * nblk + b] receives block b's partial of variable v
+__device__ __forceinline__ void sums_pass1(const Geo& g, const double* U, DD* part, int nblk, int b) {
+  __shared__ DD red[256];
+  const gptr<const double> Ug = glb(U);
+  const long long nint = (long long)g.nx * (g.dim == 2 ? g.ny : 1);
+  const long long k0 = (long long)b * SUM_CHUNK;
+  const long long k1 = k0 + SUM_CHUNK < nint ? k0 + SUM_CHUNK : nint;
+  const int t = threadIdx.x;
+  for (int v = 0; v < g.nv; ++v) {
+    DD acc{0.0, 0.0};
+    for (long long k = k0 + t; k < k1; k += 256) {
+      const int i = (int)(k % g.nx), j = (int)(k / g.nx);
+      acc = dd_add(acc, DD{Ug[g.avg(v, i, j)], 0.0});
+    }
+    red[t] = acc;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+      if (t < w) red[t] = dd_add(red[t], red[t + w]);
+      __syncthreads();
+    }
+    if (t == 0) part[(size_t)v * nblk + b] = red[0];
+    __syncthreads();
+  }
+}
+
+__device__ __forceinline__ void sums_pass2(int nv, const DD* part, int nblk, double* out) {
+  __shared__ DD red[256];
+  const int t = threadIdx.x;
+  for (int v = 0; v < nv; ++v) {
+    DD acc{0.0, 0.0};
+    for (int k = t; k < nblk; k += 256) acc = dd_add(acc, part[(size_t)v * nblk + k]);
+    red[t] = acc;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+      if (t < w) red[t] = dd_add(red[t], red[t + w]);
+      __syncthreads();
+    }
+    if (t == 0) out[v] = red[0].hi + red[0].lo;
+    __syncthreads();
+  }
+}
+
+
+// ---------------------------------------------------------------------------
 // 2-D Step 1 (Sec. 3.3): tangential ASE-DFF in each column (row) gives the
 // line averages of the cell on the horizontal (vertical) Gauss lines.
 // ---------------------------------------------------------------------------
@@ -540,9 +659,10 @@ static_assert(LT_X * LT_Y == 256, "one cell per thread");
 
 template <int M, bool PERSIST = false>
 __device__ __forceinline__ void lines_tile(const Geo& g, const Consts& C, const double* U, const double* sxo,
-                                           const double* syo, double* lvx, double* lvy, int bx, int by,
-                                           double* sm) {
+                                           const double* syo, double* lvx, double* lvy, Header* hdr, int bx,
+                                           int by, double* sm) {
   using L = LinesLds;
+  __shared__ Tally tally;
   const gptr<const double> Ug = glb(U), sxg = glb(sxo), syg = glb(syo);
   const gptr<double> lvxg = glb(lvx), lvyg = glb(lvy);
   double* avg = sm;
@@ -553,6 +673,7 @@ __device__ __forceinline__ void lines_tile(const Geo& g, const Consts& C, const 
   __syncthreads();   // a persistent caller's previous tile has finished with the LDS
   const int i0 = -H + bx * LT_X, j0 = -H + by * LT_Y;
   const int tid = PERSIST ? tile_tid() : (int)threadIdx.x;
+  tally_zero(tally, tid);
   auto ci = [&](int i) { return i < -H ? -H : (i > g.nx + H - 1 ? g.nx + H - 1 : i); };
   auto cj = [&](int j) { return j < -H ? -H : (j > g.ny + H - 1 ? g.ny + H - 1 : j); };
   double wq[4];
@@ -636,6 +757,10 @@ __device__ __forceinline__ void lines_tile(const Geo& g, const Consts& C, const 
   __syncthreads();
   const int xx = tid % LT_X, yy = tid / LT_X;
   const int i = i0 + xx, j = j0 + yy;
+  // the tile's own cells (health tally): interior cells of the tile
+  const bool interior = i >= 0 && i < g.nx && j >= 0 && j < g.ny;
+  int brx = 9, bry = 9;
+  bool tiex = false, tiey = false;
   // x-face line values: column i, rows j-2..j+2, needed for j in [-1, ny]
   if (i <= g.nx + 2 && j >= -1 && j <= g.ny) {
     double d[4][9], s[6];
@@ -651,7 +776,9 @@ __device__ __forceinline__ void lines_tile(const Geo& g, const Consts& C, const 
         d[v][5 + k] = C.dy * gy[(v * L::BY + yy + 2 + o) * LT_X + xx];
       }
     }
-    const Cascade cs = cascade(s, C.order, C.thres);
+    const Cascade cs = cascade(s, C.order, C.thres, C.tie);
+    brx = cs.branch;
+    tiex = cs.tie;
     double out[4][4];
     recon_nodes<double, 4, M>(d, cs, C, out);
 #pragma unroll
@@ -674,7 +801,9 @@ __device__ __forceinline__ void lines_tile(const Geo& g, const Consts& C, const 
         d[v][5 + k] = C.dx * gx[(v * LT_Y + yy) * L::BX + xx + 2 + o];
       }
     }
-    const Cascade cs = cascade(s, C.order, C.thres);
+    const Cascade cs = cascade(s, C.order, C.thres, C.tie);
+    bry = cs.branch;
+    tiey = cs.tie;
     double out[4][4];
     recon_nodes<double, 4, M>(d, cs, C, out);
 #pragma unroll
@@ -682,6 +811,10 @@ __device__ __forceinline__ void lines_tile(const Geo& g, const Consts& C, const 
 #pragma unroll
       for (int v = 0; v < 4; ++v) lvyg[g.lv(v, l, i, j)] = out[l][v];
   }
+  tally_add(tally, interior, brx, tiex, C.order, tid);
+  tally_add(tally, interior, bry, tiey, C.order, tid);
+  __syncthreads();
+  tally_flush(tally, hdr, tid);
 }
 
 
@@ -772,10 +905,12 @@ __device__ void face2d_tile(const Geo& g, const Consts& C, const Bufs& B, unsign
   using TL = Tile<M>;
   constexpr int NF = TL::NF, NT = TL::NT, NC = TL::NC, NR = TL::NR;
   const gptr<const Header> hdr = glb((const Header*)B.hdr);
+  __shared__ Tally tally;
   __syncthreads();
   if (!hdr->active) return;
   // persistent callers: an index the compiler cannot hoist out of their loop
   const int tx = PERSIST ? tile_tid() : (int)threadIdx.x;
+  tally_zero(tally, tx);
   const double dt = hdr->dt;
   T* s2v = (T*)smem;
   T* s2d = (T*)(smem + Lds<M, T>::s2v);
@@ -884,7 +1019,10 @@ __device__ void face2d_tile(const Geo& g, const Consts& C, const Bufs& B, unsign
     double s[6];
 #pragma unroll
     for (int f = 0; f < 6; ++f) s[f] = stg[r * NSG + c + f];
-    const Cascade cs = cascade(s, C.order, C.thres);
+    const Cascade cs = cascade(s, C.order, C.thres, C.tie);
+    // the tile's own reconstructions: the cells it updates on its own lines
+    tally_add(tally, own && c >= 1 && c <= NF - 1 && F0 - 1 + c < nmax && r >= 1 && r <= NT && T0 - 1 + r < tmax,
+              cs.branch, cs.tie, C.order, tx);
     T d[4][9];
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
@@ -910,6 +1048,8 @@ __device__ void face2d_tile(const Geo& g, const Consts& C, const Bufs& B, unsign
     }
   }
   __syncthreads();
+
+  tally_flush(tally, B.hdr, tx);
 
   // ---- Steps 3-4 at every face Gauss point: one Gauss point per thread ----
   static_assert(NB <= 256, "one Gauss point per thread of a 256-thread block");
@@ -963,7 +1103,8 @@ __device__ void face2d_tile(const Geo& g, const Consts& C, const Bufs& B, unsign
 #pragma unroll
           for (int dd = 1; dd < 6; ++dd) Wk[sd][dd][v] = T(0);
         }
-        if (own) atomicAdd((unsigned long long*)&B.hdr->fallbacks, 1ull);
+        // counted once per face: the tile's last face is the next tile's first
+        if (own && (f < NF - 1 || nf == nmax)) atomicAdd((unsigned long long*)&B.hdr->fallbacks, 1ull);
       }
     }
     __syncthreads();   // B3: the Step 2 records are read; the results may overwrite them
@@ -1112,6 +1253,8 @@ __device__ void stage1d_seg(const Geo& g, const Consts& C, const Bufs& B, double
   T* ss = (T*)(sm + Lds1D<T>::slo);
   double* sg = (double*)(sm + Lds1D<T>::sig);
   T* rc = (T*)(sm + Lds1D<T>::rec);
+  __shared__ Tally tally;
+  tally_zero(tally, t);
   // ---- inputs: staged cell c at F0-3+c, face q at F0-3+q (clamped into the
   // stored grid; no owned item reads a clamped entry); all lanes load ----
   auto clampc = [&](int x) { return x < -H ? -H : (x > g.nx + H - 1 ? g.nx + H - 1 : x); };
@@ -1137,7 +1280,14 @@ __device__ void stage1d_seg(const Geo& g, const Consts& C, const Bufs& B, double
     double s[6];
 #pragma unroll
     for (int q = 0; q < 6; ++q) s[q] = sg[t + q];           // faces cell-2 .. cell+3
-    const Cascade cs = cascade(s, C.order, C.thres);
+    const Cascade cs = cascade(s, C.order, C.thres, C.tie);
+    // own reconstructions: the cells the segment updates, and the ghost
+    // cells -1 and nx beside the first and last boundary faces
+    const int cell = F0 - 1 + t;
+    tally_add(tally,
+              (cell >= F0 && cell < F0 + S1_CELLS && cell < g.nx) || (cell == -1 && seg == 0) ||
+                  (cell == g.nx && seg == nseg - 1),
+              cs.branch, cs.tie, C.order, t);
     T d[3][9];
 #pragma unroll
     for (int v = 0; v < 3; ++v) {
@@ -1156,6 +1306,7 @@ __device__ void stage1d_seg(const Geo& g, const Consts& C, const Bufs& B, double
         for (int v = 0; v < 3; ++v) rc[((t * 2 + sd) * 3 + k) * 3 + v] = out[sd][k][v];
   }
   __syncthreads();
+  tally_flush(tally, B.hdr, t);
   // ---- flux: face F0+f, one per thread (wave-uniform: lanes without a face
   // of their own compute the block's last face and store nothing) ----
   const int f = t;
@@ -1187,7 +1338,8 @@ __device__ void stage1d_seg(const Geo& g, const Consts& C, const Bufs& B, double
           Wk[sd][1][v] = T(0);
           Wk[sd][3][v] = T(0);
         }
-        if (own) atomicAdd((unsigned long long*)&B.hdr->fallbacks, 1ull);
+        // counted once per face: the segment's last face is the next one's first
+        if (own && (f < S1_CELLS || F == g.nx)) atomicAdd((unsigned long long*)&B.hdr->fallbacks, 1ull);
       }
     }
     FaceOut fo;
