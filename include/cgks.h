@@ -212,6 +212,19 @@ cgks_status cgks_read_state(const cgks_plan* plan, const void* d_state, const vo
 cgks_status cgks_conservation_sums(const cgks_plan* plan, const void* d_state, void* d_work, double* d_sums,
                                    void* stream);
 
+/* For callers that cannot allocate device memory (code under hipGraph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * totals as cgks_conservation_sums, bit for bit, without d_work.  The block
+ * partials go to a fixed scratch array in the library's device memory
+ * (256 KiB per device, held until the process ends), so grids are limited to
+ * 2^26 interior cells (8192 x 8192).  No allocation of any kind; the first
+ * call on a device resolves the array's address there.  Every call on one
+ * device shares that array: calls that overlap on one device (different
+ * streams, or different host threads) race and must be ordered by the
+ * caller.  Errors: CGKS_EINVAL (NULL pointers, or a grid beyond the limit;
+ * nothing enqueued), CGKS_EHIP. */
+cgks_status cgks_conservation_sums_static(const cgks_plan* plan, const void* d_state, double* d_sums, void* stream);
+
 /* Device counters (synchronises `stream`); returns CGKS_ENONPHYSICAL when
  * nonphysical > 0. */
 cgks_status cgks_query_health(const cgks_plan* plan, const void* d_work, cgks_health* out, void* stream);

@@ -23,7 +23,8 @@ GAUSS_M = {5: 2, 7: 3, 9: 4}
 
 # every symbol include/cgks.h declares
 EXPORTS = ["cgks_plan_create", "cgks_plan_sizes", "cgks_init_state", "cgks_step", "cgks_step_timed",
-           "cgks_kernel_name", "cgks_read_state", "cgks_conservation_sums", "cgks_query_health",
+           "cgks_kernel_name", "cgks_read_state", "cgks_conservation_sums", "cgks_conservation_sums_static",
+           "cgks_query_health",
            "cgks_plan_destroy", "cgks_status_string", "cgks_last_error",
            "cgks_batch_create", "cgks_batch_destroy", "cgks_batch_add", "cgks_batch_remove", "cgks_batch_commit",
            "cgks_batch_step", "cgks_batch_capture", "cgks_batch_launch", "cgks_batch_poll", "cgks_batch_info",
@@ -133,6 +134,7 @@ def lib():
         L.cgks_read_state.argtypes = [vp, vp, vp, dp, dp, dp, dp, dp, dp, dp, dp,
                                       ctypes.POINTER(ctypes.c_longlong), vp]
         L.cgks_conservation_sums.argtypes = [vp, vp, vp, vp, vp]
+        L.cgks_conservation_sums_static.argtypes = [vp, vp, vp, vp]
         L.cgks_query_health.argtypes = [vp, vp, ctypes.POINTER(Health), vp]
         L.cgks_plan_destroy.argtypes = [vp]
         L.cgks_batch_create.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_size_t, ctypes.POINTER(vp)]

@@ -7,6 +7,23 @@
 
 thread_local std::string cgks_g_err;
 
+#include <mutex>
+
+// Scratch of cgks_conservation_sums_static: the block partials of the
+// conservation-sum reduction (double-double, [variable][block]), for callers
+// that cannot allocate.  Each device holds its own copy for the life of the
+// process; host code reaches it only through the address that
+// hipGetSymbolAddress returns on that device (the array's name is a host-side
+// stand-in).  Every call on one device shares it.
+constexpr int kStaticSumBlocks = 4096;   // grids up to 4096 * SUM_CHUNK = 2^26 interior cells
+static __device__ __align__(256) double scratch[(size_t)kStaticSumBlocks * 4 * 2];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices];   // device address of `scratch` per device, once resolved
+}  // namespace
+
 namespace {
 
 // ---------------------------------------------------------------------------
@@ -636,6 +653,36 @@ cgks_status cgks_query_health(const cgks_plan* p, const void* d_work, cgks_healt
   out->dff_lt1 = ao + (order > 5 ? l5 : 0) + (order > 7 ? l7 : 0);
   out->near_ties = (long long)hh.ties;
   if (hh.nonphysical) return fail(CGKS_ENONPHYSICAL, "nonphysical cell average");
+  return CGKS_OK;
+}
+
+cgks_status cgks_conservation_sums_static(const cgks_plan* p, const void* d_state, double* d_sums, void* stream) {
+  if (!p || !d_state || !d_sums) return fail(CGKS_EINVAL, "NULL argument");
+  if (p->sum_blocks > kStaticSumBlocks)
+    return fail(CGKS_EINVAL, "grid too large for the static scratch: at most " +
+                                 std::to_string((long long)kStaticSumBlocks * SUM_CHUNK) + " interior cells");
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return fail(CGKS_EINVAL, "device index out of range");
+  void* ptr = nullptr;
+  {
+    // resolved once per device, with that device current
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+      void* q = nullptr;
+      HIP_TRY(hipGetSymbolAddress(&q, HIP_SYMBOL(scratch)));
+      if (!q) return fail(CGKS_EHIP, "hipGetSymbolAddress returned no address for the scratch array");
+      g_scratch_ptr[dev] = q;
+    }
+    ptr = g_scratch_ptr[dev];
+  }
+  // pass 1 writes every partial pass 2 reads: nothing needs clearing
+  hipStream_t st = (hipStream_t)stream;
+  DD* part = (DD*)ptr;
+  hipLaunchKernelGGL(k_sum1, dim3(p->sum_blocks), dim3(256), 0, st, p->g, (const double*)d_state, part,
+                     p->sum_blocks);
+  hipLaunchKernelGGL(k_sum2, dim3(1), dim3(256), 0, st, p->g.nv, (const DD*)part, p->sum_blocks, d_sums);
+  HIP_TRY(hipGetLastError());
   return CGKS_OK;
 }
 
