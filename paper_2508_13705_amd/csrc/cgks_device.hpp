@@ -174,6 +174,29 @@ CGKS_HD __forceinline__ void mauv(const T* a, const Mom<T>& M, T* out) {
   }
 }
 
+// The same moment vectors for a = 1: the terms of the general form with a
+// zero coefficient are left out (they add exact zeros).
+template <typename T, int D, int AL, int BE>
+CGKS_HD __forceinline__ T mS1(const Mom<T>& M) {
+  if (D == 2) return M.u[AL] * M.v[BE];
+  return M.u[AL];
+}
+
+template <typename T, int D, int AL, int BE>
+CGKS_HD __forceinline__ void mauv1(const Mom<T>& M, T* out) {
+  if (D == 2) {
+    const T g = mS1<T, D, AL, BE>(M);
+    out[0] = g;
+    out[1] = mS1<T, D, AL + 1, BE>(M);
+    out[2] = mS1<T, D, AL, BE + 1>(M);
+    out[3] = T(0.5) * (mS1<T, D, AL + 2, BE>(M) + mS1<T, D, AL, BE + 2>(M) + M.x2 * g);
+  } else {
+    out[0] = M.u[AL];
+    out[1] = M.u[AL + 1];
+    out[2] = T(0.5) * (M.u[AL + 2] + M.x2 * M.u[AL]);
+  }
+}
+
 // micro-coefficients a with <a psi> = b (normalised moments of g): closed-form
 // inverse of the Maxwellian moment matrix, with the frame's constants.
 template <typename T, int D>
@@ -213,6 +236,42 @@ CGKS_HD __forceinline__ void qraw(const T* a, const Mom<T>& M, T* r) {
   }
   r[8] = mSx<T, D, AL + 1, BE>(a, M);
   r[9] = mSx<T, D, AL, BE>(a, M);
+}
+
+// Raw moments of X = u^AL v^BE (a = 1) that the heat flux needs, as qraw.
+template <typename T, int D, int AL, int BE>
+CGKS_HD __forceinline__ void qraw1(const Mom<T>& M, T* r) {
+  r[0] = mS1<T, D, AL + 3, BE>(M);
+  r[1] = mS1<T, D, AL + 2, BE>(M);
+  r[2] = mS1<T, D, AL + 1, BE>(M);
+  r[3] = mS1<T, D, AL, BE>(M);
+  if (D == 2) {
+    r[4] = mS1<T, D, AL + 1, BE + 2>(M);
+    r[5] = mS1<T, D, AL + 1, BE + 1>(M);
+    r[6] = mS1<T, D, AL, BE + 2>(M);
+    r[7] = mS1<T, D, AL, BE + 1>(M);
+  } else {
+    r[4] = r[5] = r[6] = r[7] = T(0);
+  }
+  r[8] = M.x2 * r[2];
+  r[9] = M.x2 * r[3];
+}
+
+// Heat-flux moments over the equilibrium g0 itself (full space, mean (U0,
+// V0), variance s = 1/(2 lam0)), in closed form.  With c = u - U0,
+// w = v - V0, E = (c^2 + w^2 + xi^2)/2, a polynomial
+// a = a0 + a1 u + a2 v + a3 (u^2 + v^2 + xi^2)/2 reads A0 + B1 c + B2 w + a3 E
+// with B1 = a1 + a3 U0 and A0 = a0 + a1 U0 + a2 V0 + a3 (U0^2 + V0^2)/2; the
+// odd central moments of the Gaussian vanish, which leaves
+//   <a c E> = B1 Q2,   <a u c E> = (U0 B1 + A0) Q2 + a3 Q3,   <a v c E> = V0 B1 Q2,
+// Q2 = <c^2 E> = (Kd + 2) s^2 / 2 and Q3 = <c^2 E^2> = (Kd + 2)(Kd + 4) s^3 / 4
+// (Kd = K + D; the same in 1-D, where a = a0 + a1 u + a2 (u^2 + xi^2)/2).
+template <typename T, int D>
+CGKS_HD __forceinline__ void heat_split(const T* a, T U0, T V0, T& B1, T& A0, T& a3) {
+  a3 = D == 2 ? a[3] : a[2];
+  const T a2 = D == 2 ? a[2] : T(0);
+  B1 = a[1] + a3 * U0;
+  A0 = a[0] + a[1] * U0 + a2 * V0 + T(0.5) * a3 * (U0 * U0 + V0 * V0);
 }
 
 // <X (u-U0)/2 ((u-U0)^2 + (v-V0)^2 + xi^2)> from the raw moments of X
@@ -283,16 +342,16 @@ CGKS_HD void gks_flux(const T (&Wl)[6][4], const T (&Wr)[6][4], double dt, const
     const Frame<T> fr = frame<T, D>(U, V, lam, Kd, iKd);
     Mom<T> M;
     moments<T, D>(fr, K, side == 0 ? 1 : -1, M);
-    T e0[4] = {1, 0, 0, 0}, t4[4];
-    mauv<T, D, 0, 0>(e0, M, t4);
+    T t4[4];
+    mauv1<T, D, 0, 0>(M, t4);
 #pragma unroll
     for (int v = 0; v < NV; ++v) Q0[v] += rho * t4[v];
-    mauv<T, D, 1, 0>(e0, M, t4);
+    mauv1<T, D, 1, 0>(M, t4);
 #pragma unroll
     for (int v = 0; v < NV; ++v) NF0[v] += rho * t4[v];
     if (PR) {
       T r10[10];
-      qraw<T, D, 0, 0>(e0, M, r10);
+      qraw1<T, D, 0, 0>(M, r10);
 #pragma unroll
       for (int k = 0; k < 10; ++k) QR0[k] += rho * r10[k];
     }
@@ -402,8 +461,8 @@ CGKS_HD void gks_flux(const T (&Wl)[6][4], const T (&Wr)[6][4], double dt, const
   micro<T, D>(bTT, f0, ATT);
 
   // flux moments of the equilibrium part (normalised)
-  T e0[4] = {1, 0, 0, 0}, F0[4], FA[4], F1[4], Ft[4];
-  mauv<T, D, 1, 0>(e0, M0, F0);
+  T F0[4], FA[4], F1[4], Ft[4];
+  mauv1<T, D, 1, 0>(M0, F0);
   mauv<T, D, 1, 0>(AT, M0, FA);
   mauv<T, D, 2, 0>(an, M0, F1);
   mauv<T, D, 2, 0>(anT, M0, Ft);
@@ -422,26 +481,28 @@ CGKS_HD void gks_flux(const T (&Wl)[6][4], const T (&Wr)[6][4], double dt, const
   // heat-flux moments of the Prandtl fix
   T hA = T(0), hP1 = T(0), hPt = T(0), hN0 = T(0), hN1 = T(0);
   if (PR) {
-    T ra[10], rb[10];
-    qraw<T, D, 0, 0>(AT, M0, ra);
-    hA = qcomb<T, D>(ra, U0, V0);
-    qraw<T, D, 1, 0>(an, M0, ra);
+    // terms over g0: closed forms (heat_split); terms over the half-space
+    // initial states: raw moments, shifted to the frame of (U0, V0)
+    const T s0 = f0.h;
+    const T Q2 = T(0.5) * (Kd + T(2)) * s0 * s0;
+    const T Q3 = T(0.25) * (Kd + T(2)) * (Kd + T(4)) * s0 * s0 * s0;
+    T B1, A0, a3, B1t, A0t, a3t;
+    heat_split<T, D>(AT, U0, V0, B1, A0, a3);
+    hA = B1 * Q2;
+    heat_split<T, D>(an, U0, V0, B1, A0, a3);
+    hP1 = (U0 * B1 + A0) * Q2 + a3 * Q3;
     if (D == 2) {
-      qraw<T, D, 0, 1>(ab[1], M0, rb);
-#pragma unroll
-      for (int k = 0; k < 10; ++k) ra[k] += rb[k];
+      heat_split<T, D>(ab[1], U0, V0, B1t, A0t, a3t);
+      hP1 += V0 * B1t * Q2;
     }
-    hP1 = qcomb<T, D>(ra, U0, V0);
-    qraw<T, D, 1, 0>(anT, M0, ra);
-    qraw<T, D, 0, 0>(ATT, M0, rb);
-#pragma unroll
-    for (int k = 0; k < 10; ++k) ra[k] += rb[k];
+    heat_split<T, D>(anT, U0, V0, B1, A0, a3);
+    hPt = (U0 * B1 + A0) * Q2 + a3 * Q3;
+    heat_split<T, D>(ATT, U0, V0, B1, A0, a3);
+    hPt += B1 * Q2;
     if (D == 2) {
-      qraw<T, D, 0, 1>(atT, M0, rb);
-#pragma unroll
-      for (int k = 0; k < 10; ++k) ra[k] += rb[k];
+      heat_split<T, D>(atT, U0, V0, B1t, A0t, a3t);
+      hPt += V0 * B1t * Q2;
     }
-    hPt = qcomb<T, D>(ra, U0, V0);
     hN0 = qcomb<T, D>(QR0, U0, V0);
     hN1 = qcomb<T, D>(QR1, U0, V0);
   }
