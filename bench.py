@@ -20,7 +20,7 @@ cut into 8 slabs (2048 x 256, the shape a multi-GPU run would give each GPU).
 
 Prints one JSON line.  Usage:
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--n 2048] [--cpu-seconds 20]
-                    [--batch-steps 40] [--serve-jobs 24] [--boundaries 1] [--shard-parts 8]
+                    [--batch-steps 40] [--serve-jobs 200] [--boundaries 1] [--shard-parts 8]
 """
 import argparse
 import hashlib
@@ -35,14 +35,23 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK = {"fp64_alu": 78.6, "fp32_alu": 157.3, "hbm": 8000.0}  # TFLOP/s, TFLOP/s, GB/s (MI355X)
-# Algorithmic FLOPs of one face-kernel launch per cell of the grid (one direction,
-# one stage, 9th order, m = 4, Prandtl fix on): Step-2 share 1728 + Step 3 2304 +
-# four fluxes 29932 + update 144 (paper_2508_13705_amd/csrc/flop_count.cpp).
-FACE_FLOP_PER_CELL = 34108
-# Compulsory HBM bytes of one face-kernel launch per cell (FP64 state words,
-# m = 4): read the stage input (avg 4 + normal slopes 16 + line values 16),
-# read/write the partial averages and accumulator (4 + 4 + 4 + 4) and write the
-# normal slopes of the stage state and accumulator (16 + 16): 84 words.
+# Algorithmic FLOPs of the 2-D path per face Gauss point: the gas-kinetic flux
+# (~2.5k) and the reconstruction and tangential derivatives that feed it
+# (~0.6k).  One face launch (one direction, one stage) handles m Gauss points
+# per cell, so 3.1k * m FLOP per cell and launch (12.4k at order 9).
+ALGO_FLOP_PER_GP = 3100
+# Algorithmic HBM bytes per cell-update (one cell through a whole two-stage
+# step) of a design where each stage reads and writes the state once, stage 1
+# writes an accumulator that stage 2 reads, and the strengths are read and
+# written per face: 6 S + 6 words with S = 4 + 8 m state words per cell
+# (1776 B at order 9 in FP64; 984 B when only the averages stay FP64).
+# 1-D: 6 S + 3 words with S = 6 (312 B FP64, 228 B with FP32 slopes).
+ALGO_BYTES_2D = {"fp64": 1776, "fp32_flux": 984}
+ALGO_BYTES_1D = {"fp64": 312, "fp32_flux": 228}
+# Compulsory HBM bytes of one face launch of this design per cell (FP64
+# words, m = 4): stage input (avg 4 + normal slopes 16 + line values 16),
+# partial averages and accumulator (4 + 4 + 4 + 4), normal slopes of the
+# stage state and accumulator (16 + 16): 84 words.
 FACE_BYTES_PER_CELL = 84 * 8
 
 
@@ -56,8 +65,10 @@ def parse():
     ap.add_argument("--fp64-steps", type=int, default=None, help="timed steps of the FP64 path (default: --steps)")
     ap.add_argument("--batch-jobs", type=int, default=4096)
     ap.add_argument("--batch-steps", type=int, default=40, help="timed batch steps of the 1-D batch (0: skip)")
-    ap.add_argument("--serve-jobs", type=int, default=24, help="jobs in the serving trace (0: skip)")
-    ap.add_argument("--serve-load", type=float, default=0.6, help="offered load of the serving trace")
+    ap.add_argument("--serve-jobs", type=int, default=200, help="jobs in the serving trace (0: skip)")
+    ap.add_argument("--serve-load", type=float, default=0.8, help="offered load of the serving trace")
+    ap.add_argument("--serve-ref-jobs", type=int, default=48,
+                    help="seeded sample of the trace's jobs run alone on the single-grid FP64 path")
     ap.add_argument("--boundaries", type=int, default=1, help="run the wall/inflow workloads to their end times (0: skip)")
     ap.add_argument("--shard-parts", type=int, default=8,
                     help="also time one GPU's slab of the grid split this many ways (0: skip)")
@@ -75,8 +86,8 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(kernel):
-    """HBM bytes per launch from the committed counter summary, if it was taken
+def _profile_entry(field, kernel):
+    """A per-launch figure from the committed counter summary, if it was taken
     on the current kernel source (else None)."""
     p = os.path.join(ROOT, "profiles", "face_kernel_traffic.json")
     if not os.path.exists(p):
@@ -84,7 +95,36 @@ def measured_traffic(kernel):
     d = json.load(open(p))
     if d.get("source_hash") != kernel_source_hash():
         return None
-    return d.get("bytes_per_launch", {}).get(kernel)
+    return d.get(field, {}).get(kernel)
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, calibrated)."""
+    return _profile_entry("bytes_per_launch", kernel)
+
+
+def counted_flops(kernel):
+    """Hardware-counted VALU FLOPs per launch (F32 + F64 add, mul, 2 x fma, trans)."""
+    return _profile_entry("valu_flops_per_launch", kernel)
+
+
+def host_cpu():
+    """The host CPU model and the cores the oracle may use."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        affinity = len(os.sched_getaffinity(0))
+    except AttributeError:
+        affinity = os.cpu_count()
+    return {"model": model, "nproc": affinity, "cpu_count": os.cpu_count(),
+            "omp_num_threads": os.environ.get("OMP_NUM_THREADS")}
 
 
 def time_path(problem, precision, steps, warmup):
@@ -153,8 +193,14 @@ def bench_batch_1d(jobs, steps, precision, graph_steps=10):
         el1 = time.perf_counter() - t0
         h1 = [s.health()["steps"] for s in sample]
     upd1 = sum(s.plan.gd.nx * (b - a) for s, a, b in zip(sample, h0, h1))
+    # HBM roof of the whole batched step: the algorithmic bytes per cell-update
+    # over the measured step time (the stage kernels are ~90% of it)
+    gbs = upd / el * ALGO_BYTES_1D[precision] / 1e9
+    roof = {"bound": "hbm", "achieved": gbs, "peak": PEAK["hbm"], "unit": "GB/s", "frac": gbs / PEAK["hbm"],
+            "algorithmic_bytes_per_cell_update": ALGO_BYTES_1D[precision], "scope": "whole batch step"}
     return {"workload": f"{jobs} 1-D Riemann problems, 200-4000 cells, order 9, CFL 0.5, t_end 0.15, seed 2",
-            "precision": precision, "value": upd / el, "unit": "cell-updates/s", "batch_steps": reps * graph_steps,
+            "precision": precision, "value": upd / el, "unit": "cell-updates/s", "roofline": roof,
+            "batch_steps": reps * graph_steps,
             "ms_per_batch_step": 1e3 * el / (reps * graph_steps), "jobs_active": active, "jobs_nonphysical": nonphys,
             "tuning": tuning,
             "single_grid_sequential": {"value": upd1 / el1 if el1 > 0 else None, "jobs": len(sample),
@@ -212,7 +258,7 @@ def serving_reference(trace, precision="fp64"):
             "job_seconds_p99": float(np.percentile(secs, 99))}
 
 
-def bench_serving(jobs, load, ref_rate, precision="fp32_flux"):
+def bench_serving(jobs, load, ref_rate, precision="fp32_flux", ref_jobs=48):
     """Serving loop on a Poisson trace of 2-D jobs; arrival rate set for an
     offered load `load` of the measured single-grid rate `ref_rate`."""
     from paper_2508_13705_amd import serving
@@ -224,7 +270,9 @@ def bench_serving(jobs, load, ref_rate, precision="fp32_flux"):
     loop = serving.ServingLoop(2, precision, hbm_budget=64 << 30, max_jobs=32, graph_steps=4, prep_workers=4)
     rep = loop.run(trace, log=lambda m: print("[serve]", m, file=sys.stderr, flush=True))
     rep.pop("records")
-    ref = serving_reference(trace, "fp64")
+    # the plain single-grid FP64 path on a seeded sample of the same jobs, one at a time
+    pick = np.random.default_rng(55).choice(len(trace), size=min(ref_jobs, len(trace)), replace=False)
+    ref = serving_reference([trace[k] for k in sorted(pick)], "fp64")
     rep["single_grid_fp64"] = ref
     # over the wall time the served throughput is the arrival rate; per busy
     # second it is the rate the loop sustains
@@ -312,10 +360,11 @@ def cpu_baseline(seconds):
     t0 = time.perf_counter()
     r = oracle.run(pb, nsteps=k)
     el = time.perf_counter() - t0
-    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    cpu = host_cpu()
+    threads = int(cpu["omp_num_threads"] or cpu["nproc"] or 1)
     return {"value": n * n * k / el, "unit": "cell-updates/s", "cores": threads, "kind": "oracle",
             "sample": f"turbulence {n}x{n} periodic, order 9, viscous, {k} steps ({el:.1f} s), "
-                      f"status {r['status']}"}
+                      f"status {r['status']}", "host": cpu}
 
 
 COPY_BYTES = 1 << 30
@@ -365,19 +414,36 @@ def main():
         r = res[prec]
         dom = r["dominant"]
         ms = r["avg_ms"][dom]
-        if "face" in dom:
-            flops = FACE_FLOP_PER_CELL * cells
-            peak = PEAK["fp32_alu"] if prec == "fp32_flux" else PEAK["fp64_alu"]
-            ach = flops / (ms * 1e-3) / 1e12
-            # the FP32 peak counts packed FP32 instructions, which this library
-            # does not emit; unpacked, FP32 issues at the FP64 rate
-            return {"bound": "alu", "kernel": dom, "achieved": ach, "peak": peak, "unit": "TFLOP/s",
-                    "frac": ach / peak, "peak_unpacked": PEAK["fp64_alu"], "frac_unpacked": ach / PEAK["fp64_alu"],
-                    "traffic": measured_traffic(dom.split("_", 1)[1] + "_" + prec),
-                    "avg_ms": ms, "algorithmic_bytes": FACE_BYTES_PER_CELL * cells,
-                    "hbm_frac_algorithmic": FACE_BYTES_PER_CELL * cells / (ms * 1e-3) / 1e9 / PEAK["hbm"]}
-        return {"bound": "hbm", "kernel": dom, "achieved": None, "peak": PEAK["hbm"], "unit": "GB/s", "frac": None,
-                "traffic": None, "avg_ms": ms}
+        step_s = r["elapsed"] / r["steps"]
+        # whole step against the HBM roof: algorithmic bytes per cell-update
+        hbm_step = {"algorithmic_bytes_per_cell_update": ALGO_BYTES_2D[prec],
+                    "achieved_GBps": cells * ALGO_BYTES_2D[prec] / step_s / 1e9,
+                    "frac": cells * ALGO_BYTES_2D[prec] / step_s / 1e9 / PEAK["hbm"]}
+        if "face" not in dom:
+            return {"bound": "hbm", "kernel": dom, "achieved": None, "peak": PEAK["hbm"], "unit": "GB/s",
+                    "frac": None, "traffic": None, "avg_ms": ms, "hbm_step": hbm_step}
+        m = 4
+        flops = ALGO_FLOP_PER_GP * m * cells
+        peak = PEAK["fp32_alu"] if prec == "fp32_flux" else PEAK["fp64_alu"]
+        ach = flops / (ms * 1e-3) / 1e12
+        key = dom.split("_", 1)[1] + "_" + prec
+        traffic = measured_traffic(key)
+        counted = counted_flops(key)
+        out = {"bound": "alu", "kernel": dom, "achieved": ach, "peak": peak, "unit": "TFLOP/s", "frac": ach / peak,
+               "algorithmic_flops": flops, "flops_basis": f"{ALGO_FLOP_PER_GP} per face Gauss point x m=4 x cells",
+               "avg_ms": ms, "traffic": traffic,
+               # the FP32 peak counts packed FP32 instructions, which this
+               # library does not emit; unpacked, FP32 issues at the FP64 rate
+               "peak_unpacked": PEAK["fp64_alu"], "frac_unpacked": ach / PEAK["fp64_alu"],
+               "hbm_launch": {"algorithmic_bytes": FACE_BYTES_PER_CELL * cells,
+                              "frac_algorithmic": FACE_BYTES_PER_CELL * cells / (ms * 1e-3) / 1e9 / PEAK["hbm"],
+                              "frac_measured": (traffic / (ms * 1e-3) / 1e9 / PEAK["hbm"]) if traffic else None},
+               "hbm_step": hbm_step}
+        if counted:
+            out["counted_flops"] = counted
+            out["counted_TFLOPs"] = counted / (ms * 1e-3) / 1e12
+            out["frac_counted_unpacked"] = out["counted_TFLOPs"] / PEAK["fp64_alu"]
+        return out
 
     p = res["fp32_flux"]
     q = res["fp64"]
@@ -428,7 +494,7 @@ def main():
     if a.batch_steps > 0:
         section("batch_1d", batch_1d)
     if a.serve_jobs > 0:
-        section("serving", lambda: bench_serving(a.serve_jobs, a.serve_load, value))
+        section("serving", lambda: bench_serving(a.serve_jobs, a.serve_load, value, ref_jobs=a.serve_ref_jobs))
     if a.boundaries:
         section("boundaries", bench_boundaries)
     section("small_1d", bench_small_1d)
