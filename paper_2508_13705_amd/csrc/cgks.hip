@@ -403,6 +403,7 @@ cgks_status cgks_plan_create(const cgks_grid_desc* gd, const cgks_scheme_desc* s
   C.c2 = sd->c2;
   C.mu = sd->mu;
   C.prandtl = sd->prandtl;
+  C.prfac = 1.0 / sd->prandtl - 1.0;
   C.thres = sd->sigma_thres;
   C.ghi = sd->gamma_hi;
   C.glo = sd->gamma_lo;

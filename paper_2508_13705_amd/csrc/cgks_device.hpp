@@ -30,6 +30,7 @@ struct Consts {
   double gamma, Kd;          // Kd = 2/(gamma-1) = K + D (K internal degrees of freedom)
   double iKd;                // 1 / Kd
   double c1, c2, mu, prandtl;
+  double prfac;              // 1/prandtl - 1: weight of the heat flux in the Prandtl fix
   double thres, ghi, glo, eps;
   double tie;                // |A - thres| <= tie: a cascade decision counted as a near tie
   double dx, dy;
@@ -63,6 +64,18 @@ template <> CGKS_HD __forceinline__ double dev_rcp<double>(double x) {
 #endif
 }
 template <typename T> CGKS_HD __forceinline__ T dev_rsqrt(T x) { return T(1) / dev_sqrt<T>(x); }
+// double: the hardware estimate refined by two Newton steps,
+// y <- y (3 - x y^2) / 2 (positive normal arguments)
+template <> CGKS_HD __forceinline__ double dev_rsqrt<double>(double x) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  double y = __builtin_amdgcn_rsq(x);
+  const double hx = 0.5 * x;
+  y = y * fma(-hx * y, y, 1.5);
+  return y * fma(-hx * y, y, 1.5);
+#else
+  return 1.0 / sqrt(x);
+#endif
+}
 template <> CGKS_HD __forceinline__ float dev_rcp<float>(float x) {
 #if defined(__HIP_DEVICE_COMPILE__)
   return __builtin_amdgcn_rcpf(x);
@@ -197,6 +210,65 @@ CGKS_HD __forceinline__ void mauv1(const Mom<T>& M, T* out) {
   }
 }
 
+// Moment matrix of a weight w = u^AL v^BE: G[k][j] = <w psi_k psi_j> with
+// psi = (1, u, v, (u^2+v^2+xi^2)/2) (1-D: (1, u, (u^2+xi^2)/2)), so that
+// <a w psi> = G a for a = a0 + a1 u + a2 v + a3 (u^2+v^2+xi^2)/2: the same
+// vector mauv gives, at a matrix-vector product per coefficient vector once
+// G is built.  Symmetric; both halves are stored.
+template <typename T> struct Gram {
+  T g[4][4];
+};
+
+template <typename T, int D, int AL, int BE>
+CGKS_HD __forceinline__ void gram(const Mom<T>& M, Gram<T>& G) {
+  if (D == 2) {
+    const T w00 = mS1<T, D, AL, BE>(M), u1 = mS1<T, D, AL + 1, BE>(M), v1 = mS1<T, D, AL, BE + 1>(M);
+    const T u2 = mS1<T, D, AL + 2, BE>(M), v2 = mS1<T, D, AL, BE + 2>(M), uv = mS1<T, D, AL + 1, BE + 1>(M);
+    const T e = T(0.5) * (u2 + v2 + M.x2 * w00);
+    const T ue = T(0.5) * (mS1<T, D, AL + 3, BE>(M) + mS1<T, D, AL + 1, BE + 2>(M) + M.x2 * u1);
+    const T ve = T(0.5) * (mS1<T, D, AL + 2, BE + 1>(M) + mS1<T, D, AL, BE + 3>(M) + M.x2 * v1);
+    const T ee = T(0.25) * (mS1<T, D, AL + 4, BE>(M) + mS1<T, D, AL, BE + 4>(M) +
+                            T(2) * mS1<T, D, AL + 2, BE + 2>(M) + T(2) * M.x2 * (u2 + v2) + M.x4 * w00);
+    G.g[0][0] = w00; G.g[0][1] = u1;  G.g[0][2] = v1;  G.g[0][3] = e;
+    G.g[1][0] = u1;  G.g[1][1] = u2;  G.g[1][2] = uv;  G.g[1][3] = ue;
+    G.g[2][0] = v1;  G.g[2][1] = uv;  G.g[2][2] = v2;  G.g[2][3] = ve;
+    G.g[3][0] = e;   G.g[3][1] = ue;  G.g[3][2] = ve;  G.g[3][3] = ee;
+  } else {
+    const T w00 = M.u[AL], u1 = M.u[AL + 1], u2 = M.u[AL + 2];
+    const T e = T(0.5) * (u2 + M.x2 * w00);
+    const T ue = T(0.5) * (M.u[AL + 3] + M.x2 * u1);
+    const T ee = T(0.25) * (M.u[AL + 4] + T(2) * M.x2 * u2 + M.x4 * w00);
+    G.g[0][0] = w00; G.g[0][1] = u1; G.g[0][2] = e;
+    G.g[1][0] = u1;  G.g[1][1] = u2; G.g[1][2] = ue;
+    G.g[2][0] = e;   G.g[2][1] = ue; G.g[2][2] = ee;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) { G.g[3][k] = T(0); G.g[k][3] = T(0); }
+  }
+}
+
+// out = G a (1-D: the three components; out[3] = 0)
+template <typename T, int D>
+CGKS_HD __forceinline__ void gmul(const Gram<T>& G, const T* a, T* out) {
+  constexpr int NV = D + 2;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    if (k >= NV) { out[k] = T(0); continue; }
+    T s = G.g[k][0] * a[0];
+#pragma unroll
+    for (int j = 1; j < NV; ++j) s += G.g[k][j] * a[j];
+    out[k] = s;
+  }
+}
+
+// out += G a
+template <typename T, int D>
+CGKS_HD __forceinline__ void gmul_add(const Gram<T>& G, const T* a, T* out) {
+  T t[4];
+  gmul<T, D>(G, a, t);
+#pragma unroll
+  for (int k = 0; k < D + 2; ++k) out[k] += t[k];
+}
+
 // micro-coefficients a with <a psi> = b (normalised moments of g): closed-form
 // inverse of the Maxwellian moment matrix, with the frame's constants.
 template <typename T, int D>
@@ -321,7 +393,9 @@ CGKS_HD void gks_flux(const T (&Wl)[6][4], const T (&Wr)[6][4], double dt, const
   for (int q = 0; q < 5; ++q)
 #pragma unroll
     for (int v = 0; v < 4; ++v) dQ[q][v] = T(0);
-  T pside[2], cside[2], un[2], ut[2];
+  // per side: pressure, and the normal and tangential Mach numbers of
+  // Eq. 3.2; the sum of the reciprocal pressures
+  T pside[2], ma[2], mt[2], ipsum = T(0);
   T QR0[10], QR1[10];
   if (PR) {
 #pragma unroll
@@ -336,19 +410,22 @@ CGKS_HD void gks_flux(const T (&Wl)[6][4], const T (&Wr)[6][4], double dt, const
     const T ip = dev_rcp<T>(p), ir = dev_rcp<T>(rho);
     const T lam = T(0.5) * rho * ip;
     pside[side] = p;
-    cside[side] = dev_sqrt<T>(T(C.gamma) * p * ir);
-    un[side] = U;
-    ut[side] = V;
+    ipsum += ip;
+    const T ic = dev_rsqrt<T>(T(C.gamma) * p * ir);   // 1 / sound speed
+    ma[side] = U * ic;
+    mt[side] = V * ic;
     const Frame<T> fr = frame<T, D>(U, V, lam, Kd, iKd);
     Mom<T> M;
     moments<T, D>(fr, K, side == 0 ? 1 : -1, M);
     T t4[4];
-    mauv1<T, D, 0, 0>(M, t4);
+    // <psi_k psi_j> over this half space: <psi> and <u psi> are its columns
+    // 0 and 1, and <a psi> = G a for every derivative below
+    Gram<T> G0;
+    gram<T, D, 0, 0>(M, G0);
 #pragma unroll
-    for (int v = 0; v < NV; ++v) Q0[v] += rho * t4[v];
-    mauv1<T, D, 1, 0>(M, t4);
+    for (int v = 0; v < NV; ++v) Q0[v] += rho * G0.g[v][0];
 #pragma unroll
-    for (int v = 0; v < NV; ++v) NF0[v] += rho * t4[v];
+    for (int v = 0; v < NV; ++v) NF0[v] += rho * G0.g[v][1];
     if (PR) {
       T r10[10];
       qraw1<T, D, 0, 0>(M, r10);
@@ -364,7 +441,7 @@ CGKS_HD void gks_flux(const T (&Wl)[6][4], const T (&Wr)[6][4], double dt, const
 #pragma unroll
       for (int v = 0; v < 4; ++v) b[v] = (v < NV) ? Wk[d][v] * ir : T(0);
       micro<T, D>(b, fr, a);
-      mauv<T, D, 0, 0>(a, M, t4);
+      gmul<T, D>(G0, a, t4);
 #pragma unroll
       for (int v = 0; v < NV; ++v) dQ[q][v] += rho * t4[v];
       if (q == 0) {
@@ -418,65 +495,60 @@ CGKS_HD void gks_flux(const T (&Wl)[6][4], const T (&Wr)[6][4], double dt, const
   // ab index: 2-D 0 n, 1 t, 2 nn, 3 nt, 4 tt; 1-D 0 n, 1 nn
   const T* an = ab[0];
   const T* ann = (D == 2) ? ab[2] : ab[1];
-  T bA[4], AT[4], b1[4], anT[4], atT[4], bTT[4], ATT[4], t4[4];
+  T bA[4], AT[4], b1[4], anT[4], atT[4], bTT[4], ATT[4];
+  // moment matrices of g0 for the weights u, v, u^2, u v: each serves
+  // several coefficient vectors below
+  Gram<T> Gu, Gv;
+  gram<T, D, 1, 0>(M0, Gu);
+  if (D == 2) gram<T, D, 0, 1>(M0, Gv);
   // <an u + at v + A> = 0
-  mauv<T, D, 1, 0>(an, M0, bA);
-  if (D == 2) {
-    mauv<T, D, 0, 1>(ab[1], M0, t4);
-#pragma unroll
-    for (int v = 0; v < 4; ++v) bA[v] += t4[v];
-  }
+  gmul<T, D>(Gu, an, bA);
+  if (D == 2) gmul_add<T, D>(Gv, ab[1], bA);
 #pragma unroll
   for (int v = 0; v < 4; ++v) bA[v] = -bA[v];
   micro<T, D>(bA, f0, AT);
   // <ann u + ant v + anT> = 0, <ant u + att v + atT> = 0
-  mauv<T, D, 1, 0>(ann, M0, b1);
-  if (D == 2) {
-    mauv<T, D, 0, 1>(ab[3], M0, t4);
-#pragma unroll
-    for (int v = 0; v < 4; ++v) b1[v] += t4[v];
-  }
+  gmul<T, D>(Gu, ann, b1);
+  if (D == 2) gmul_add<T, D>(Gv, ab[3], b1);
 #pragma unroll
   for (int v = 0; v < 4; ++v) b1[v] = -b1[v];
   micro<T, D>(b1, f0, anT);
   if (D == 2) {
-    mauv<T, D, 1, 0>(ab[3], M0, b1);
-    mauv<T, D, 0, 1>(ab[4], M0, t4);
+    gmul<T, D>(Gu, ab[3], b1);
+    gmul_add<T, D>(Gv, ab[4], b1);
 #pragma unroll
-    for (int v = 0; v < 4; ++v) b1[v] = -(b1[v] + t4[v]);
+    for (int v = 0; v < 4; ++v) b1[v] = -b1[v];
     micro<T, D>(b1, f0, atT);
   } else {
 #pragma unroll
     for (int v = 0; v < 4; ++v) atT[v] = T(0);
   }
   // <anT u + atT v + ATT> = 0
-  mauv<T, D, 1, 0>(anT, M0, bTT);
-  if (D == 2) {
-    mauv<T, D, 0, 1>(atT, M0, t4);
-#pragma unroll
-    for (int v = 0; v < 4; ++v) bTT[v] += t4[v];
-  }
+  gmul<T, D>(Gu, anT, bTT);
+  if (D == 2) gmul_add<T, D>(Gv, atT, bTT);
 #pragma unroll
   for (int v = 0; v < 4; ++v) bTT[v] = -bTT[v];
   micro<T, D>(bTT, f0, ATT);
 
-  // flux moments of the equilibrium part (normalised)
+  // flux moments of the equilibrium part (normalised): <u psi> is column 0
+  // of Gu; the u^2 and u v weights take matrices of their own
   T F0[4], FA[4], F1[4], Ft[4];
-  mauv1<T, D, 1, 0>(M0, F0);
-  mauv<T, D, 1, 0>(AT, M0, FA);
-  mauv<T, D, 2, 0>(an, M0, F1);
-  mauv<T, D, 2, 0>(anT, M0, Ft);
-  if (D == 2) {
-    mauv<T, D, 1, 1>(ab[1], M0, t4);
 #pragma unroll
-    for (int v = 0; v < 4; ++v) F1[v] += t4[v];
-    mauv<T, D, 1, 1>(atT, M0, t4);
-#pragma unroll
-    for (int v = 0; v < 4; ++v) Ft[v] += t4[v];
+  for (int v = 0; v < 4; ++v) F0[v] = v < NV ? Gu.g[v][0] : T(0);
+  gmul<T, D>(Gu, AT, FA);
+  gmul<T, D>(Gu, ATT, Ft);
+  {
+    Gram<T> Guu;
+    gram<T, D, 2, 0>(M0, Guu);
+    gmul<T, D>(Guu, an, F1);
+    gmul_add<T, D>(Guu, anT, Ft);
   }
-  mauv<T, D, 1, 0>(ATT, M0, t4);
-#pragma unroll
-  for (int v = 0; v < 4; ++v) Ft[v] += t4[v];
+  if (D == 2) {
+    Gram<T> Guv;
+    gram<T, D, 1, 1>(M0, Guv);
+    gmul_add<T, D>(Guv, ab[1], F1);
+    gmul_add<T, D>(Guv, atT, Ft);
+  }
 
   // heat-flux moments of the Prandtl fix
   T hA = T(0), hP1 = T(0), hPt = T(0), hN0 = T(0), hN1 = T(0);
@@ -507,13 +579,14 @@ CGKS_HD void gks_flux(const T (&Wl)[6][4], const T (&Wr)[6][4], double dt, const
     hN1 = qcomb<T, D>(QR1, U0, V0);
   }
 
-  // collision time (Sec. 4)
-  const double pl = double(pside[0]), pr = double(pside[1]);
-  const double jump = fabs(pl - pr) / (pl + pr);
+  // collision time (Sec. 4); the pressure jump in the working precision,
+  // tau and its reciprocal in double (they enter the exponential weights)
+  const T dpT = fabs(pside[0] - pside[1]);
+  const double jump = double(dpT * dev_rcp<T>(pside[0] + pside[1]));
   double tau = 0.0;
   if (C.tau_model == 1) tau = C.c1 * dt + C.c2 * jump * dt;
-  else if (C.tau_model == 2) tau = C.mu / double(p0) + C.c2 * jump * dt;
-  const double itau = tau > 0.0 ? 1.0 / tau : 0.0;
+  else if (C.tau_model == 2) tau = C.mu * double(dev_rcp<T>(p0)) + C.c2 * jump * dt;
+  const double itau = tau > 0.0 ? dev_rcp<double>(tau) : 0.0;
 
   // time integrals (the flux keeps the terms up to first order in t of the
   // equilibrium part; interface values keep the full quadratic)
@@ -555,7 +628,7 @@ CGKS_HD void gks_flux(const T (&Wl)[6][4], const T (&Wr)[6][4], double dt, const
       const double ha = double(hA), hp = double(hP1);
       const double q = r0 * (ha * 0.5 * d * d - tau * ((hp + ha) * d + double(hPt) * 0.5 * d * d) + hp * E1) +
                        double(hN0) * E0 - double(hN1) * E1;
-      Fo[NV - 1] += (1.0 / C.prandtl - 1.0) * q;
+      Fo[NV - 1] += C.prfac * q;
     }
   }
 #pragma unroll
@@ -570,12 +643,11 @@ CGKS_HD void gks_flux(const T (&Wl)[6][4], const T (&Wr)[6][4], double dt, const
               t * e * double(NW1[v]);
     }
   }
-  // discontinuity strength (Eq. 3.2)
+  // discontinuity strength (Eq. 3.2), in the working precision
   {
-    const double dp = fabs(pl - pr);
-    const double mn = double(un[0]) / double(cside[0]) - double(un[1]) / double(cside[1]);
-    const double mt = (D == 2) ? double(ut[0]) / double(cside[0]) - double(ut[1]) / double(cside[1]) : 0.0;
-    o.sigma = dp / pl + dp / pr + mn * mn + mt * mt;
+    const T dn = ma[0] - ma[1];
+    const T dtn = (D == 2) ? mt[0] - mt[1] : T(0);
+    o.sigma = double(dpT * ipsum + dn * dn + dtn * dtn);
   }
 }
 

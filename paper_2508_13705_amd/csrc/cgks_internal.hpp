@@ -895,6 +895,14 @@ template <typename T> struct FaceWaves {
   static constexpr int value = sizeof(T) == 8 ? 1 : 2;
 };
 
+// Step 3 tangential-fit weights in the working precision (float copies of
+// the tables for the FP32-flux variant: no conversion per use)
+template <typename T, int K>
+__device__ __forceinline__ T tanw(int m, int l, int k) {
+  if (sizeof(T) == 4) return T(K == 1 ? kT1f[m][l][k] : kT2f[m][l][k]);
+  return T(K == 1 ? kT1[m][l][k] : kT2[m][l][k]);
+}
+
 // One tile (bx, by) of nbx x nby; callable from a persistent loop (starts
 // with a barrier so the LDS of the previous tile is free).  SU: staging passes
 // whose loads are issued together (all of them where registers allow; the
@@ -1085,7 +1093,7 @@ __device__ void face2d_tile(const Geo& g, const Consts& C, const Bufs& B, unsign
         for (int rr = 0; rr < 3; ++rr)
 #pragma unroll
           for (int q = 0; q < M; ++q) {
-            const T w1 = T(kT1[M][l][rr * M + q]), w2 = T(kT2[M][l][rr * M + q]);
+            const T w1 = tanw<T, 1>(M, l, rr * M + q), w2 = tanw<T, 2>(M, l, rr * M + q);
             const T val = s2v[I2(r + rr, c, q, sd, v)];
             a1 += w1 * val;
             a2 += w2 * val;

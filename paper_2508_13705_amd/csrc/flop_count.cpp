@@ -65,6 +65,7 @@ int main() {
   gks_flux<Fl, 2, false>(Wl, Wr, 1e-4, C, o);
   printf("flux2d (Pr = 1) flops %lld\n", flops());
   C.prandtl = 0.72;
+  C.prfac = 1.0 / C.prandtl - 1.0;
   reset();
   gks_flux<Fl, 2, true>(Wl, Wr, 1e-4, C, o);
   // the time combination in double: 2 flux integrals x 4 components x ~14 ops,

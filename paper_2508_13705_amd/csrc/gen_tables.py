@@ -212,8 +212,10 @@ def main():
             lines.append("  },")
         lines.append("};")
     lines.append("// Tangential derivative weights [m][l][r*m+q] (Sec. 3.3 Step 3, least squares of degree min(2m+1, 8)), units of xi")
-    for name, idx in (("kT1", 0), ("kT2", 1)):
-        lines.append(f"__constant__ double {name}[5][4][12] = {{")
+    for name, idx, ty in (("kT1", 0, "double"), ("kT2", 1, "double"), ("kT1f", 0, "float"), ("kT2f", 1, "float")):
+        if ty == "float":
+            lines.append(f"// {name}: the same weights rounded to float (the FP32-flux variant)")
+        lines.append(f"__constant__ {ty} {name}[5][4][12] = {{")
         for m in range(5):
             lines.append("  {")
             if m < 2:
