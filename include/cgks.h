@@ -266,10 +266,16 @@ typedef struct {
 
 /* Launch shape of the persistent kernels: grid = (resident blocks per CU) x
  * CUs x grid_mult; xcd_remap != 0 gives consecutive tiles to blocks of one
- * XCD.  ms_per_step: the time measured by cgks_batch_tune (else 0). */
+ * XCD.  Tile shapes of the 2-D kernels: face_tile 0 = 16 faces along the
+ * normal x 8/5/4 lines (orders 5/7/9; the single-grid shape), 1 = 32 x
+ * 4/2/2, 2 = 8 x 16/10/8; line_tile (Step 1) 0 = 32 x 8 cells, 1 = 16 x 16.
+ * Every shape computes the same results.  ms_per_step: the time measured by
+ * cgks_batch_tune (else 0). */
 typedef struct {
   int grid_mult;
   int xcd_remap;
+  int face_tile;
+  int line_tile;
   float ms_per_step;
 } cgks_batch_tuning;
 
@@ -323,17 +329,21 @@ cgks_status cgks_batch_poll(cgks_batch* batch, cgks_job_status* out, void* strea
 cgks_status cgks_batch_info(const cgks_batch* batch, int* njobs, size_t* bytes_used, size_t* table_bytes,
                             int* grid_face);
 
-/* Set / read the launch shape (set drops a captured graph).
- * Errors: CGKS_EINVAL (grid_mult outside 1..16). */
+/* Set / read the launch shape (set drops a captured graph; a change of tile
+ * shape also changes the jobs' tile counts, so the batch must be committed
+ * again before the next step).  Errors: CGKS_EINVAL (grid_mult outside
+ * 1..16, face_tile outside 0..2, line_tile outside 0..1). */
 cgks_status cgks_batch_set_tuning(cgks_batch* batch, const cgks_batch_tuning* tuning);
 cgks_status cgks_batch_get_tuning(const cgks_batch* batch, cgks_batch_tuning* tuning);
 
-/* Autotune the launch shape on the committed jobs: every candidate
- * (grid_mult 1, 2, 4 x xcd_remap 0, 1) runs steps_per_trial real steps, timed
- * with HIP events on `stream`; the fastest is kept and written to *chosen
- * (may be NULL).  All candidates compute the same result, so the trial steps
- * advance the jobs like ordinary steps.  Synchronises `stream`; drops a
- * captured graph. */
+/* Autotune the launch shape on the committed jobs: each candidate runs
+ * steps_per_trial real steps, timed with HIP events on `stream`.  2-D
+ * batches first try every face_tile x line_tile pair (re-committing the table
+ * for each), then grid_mult 1, 2, 4 x xcd_remap 0, 1 with the fastest
+ * shapes; 1-D batches the latter only.  The fastest is kept (the batch stays
+ * committed) and written to *chosen (may be NULL).  All candidates compute
+ * the same result, so the trial steps advance the jobs like ordinary steps.
+ * Synchronises `stream`; drops a captured graph. */
 cgks_status cgks_batch_tune(cgks_batch* batch, int steps_per_trial, void* stream, cgks_batch_tuning* chosen);
 
 #ifdef __cplusplus

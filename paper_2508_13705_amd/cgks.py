@@ -104,7 +104,8 @@ class JobStatus(ctypes.Structure):
 
 
 class BatchTuning(ctypes.Structure):
-    _fields_ = [("grid_mult", ctypes.c_int), ("xcd_remap", ctypes.c_int), ("ms_per_step", ctypes.c_float)]
+    _fields_ = [("grid_mult", ctypes.c_int), ("xcd_remap", ctypes.c_int), ("face_tile", ctypes.c_int),
+                ("line_tile", ctypes.c_int), ("ms_per_step", ctypes.c_float)]
 
 
 _lib = None
@@ -407,18 +408,25 @@ class Batch:
                                     ctypes.byref(gf)))
         return {"njobs": n.value, "bytes_used": used.value, "table_bytes": tb.value, "grid_face": gf.value}
 
+    @staticmethod
+    def _tuning_dict(t):
+        return {"grid_mult": t.grid_mult, "xcd_remap": t.xcd_remap, "face_tile": t.face_tile,
+                "line_tile": t.line_tile, "ms_per_step": t.ms_per_step}
+
     def tuning(self):
         t = BatchTuning()
         check(lib().cgks_batch_get_tuning(self.handle, ctypes.byref(t)))
-        return {"grid_mult": t.grid_mult, "xcd_remap": t.xcd_remap, "ms_per_step": t.ms_per_step}
+        return self._tuning_dict(t)
 
-    def set_tuning(self, grid_mult=1, xcd_remap=1):
-        t = BatchTuning(int(grid_mult), int(xcd_remap), 0.0)
+    def set_tuning(self, grid_mult=1, xcd_remap=1, face_tile=0, line_tile=0):
+        """Set the launch and tile shapes; a change of tile shape needs a commit
+        before the next step."""
+        t = BatchTuning(int(grid_mult), int(xcd_remap), int(face_tile), int(line_tile), 0.0)
         check(lib().cgks_batch_set_tuning(self.handle, ctypes.byref(t)))
 
     def tune(self, steps_per_trial=1):
-        """Autotune the launch shape on the committed jobs (runs 6 x
-        steps_per_trial real steps); returns the chosen shape."""
+        """Autotune tile shapes (2-D) and launch shape on the committed jobs
+        (real steps); returns the chosen tuning."""
         t = BatchTuning()
         check(lib().cgks_batch_tune(self.handle, int(steps_per_trial), _stream_handle(self.stream), ctypes.byref(t)))
-        return {"grid_mult": t.grid_mult, "xcd_remap": t.xcd_remap, "ms_per_step": t.ms_per_step}
+        return self._tuning_dict(t)

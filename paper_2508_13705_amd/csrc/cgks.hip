@@ -78,7 +78,7 @@ __device__ __forceinline__ int xcd_block(int b, int n) {
 template <int M>
 __global__ __launch_bounds__(256) void k_lines(Geo g, Consts C, const double* U, const double* sxo,
                                                const double* syo, double* lvx, double* lvy, Header* hdr) {
-  __shared__ double sm[LinesLds::total];
+  __shared__ double sm[LinesLds<0>::total];
   if (!hdr->active) return;
   const int lb = xcd_block(blockIdx.y * gridDim.x + blockIdx.x, gridDim.x * gridDim.y);
   lines_tile<M>(g, C, U, sxo, syo, lvx, lvy, hdr, lb % gridDim.x, lb / gridDim.x, sm);
@@ -437,10 +437,11 @@ cgks_status cgks_plan_create(const cgks_grid_desc* gd, const cgks_scheme_desc* s
     size_t a = (size_t)((g.nx + 255) / 256) * (g.dim == 2 ? g.ny : 1);
     size_t b1 = (size_t)((g.nx + S1_CELLS - 1) / S1_CELLS);
     size_t c = 0;
-    if (g.dim == 2) {
-      const int NT = g.m == 2 ? 8 : (g.m == 3 ? 5 : 4);
-      c = (size_t)((g.ny + 14) / 15) * ((g.nx + NT - 1) / NT);
-    }
+    if (g.dim == 2)   // y-face tiles of every tile shape (the batched kernels may take any)
+      for (int v = 0; v < kFaceTiles; ++v) {
+        const size_t t = (size_t)face_tiles_n(g.ny, tile_nf(v)) * face_tiles_t(g.nx, tile_nt(v, g.m));
+        if (t > c) c = t;
+      }
     p->max_parts = a > b1 ? (a > c ? a : c) : (b1 > c ? b1 : c);
   }
   p->off_part = o; o += up(2 * p->max_parts);

@@ -132,31 +132,32 @@ __global__ __launch_bounds__(256) void kb_bcs(const BTab* tab, int remap) {
   });
 }
 
-// Step 1 line values of the stage input (2-D), one LT_X x LT_Y tile per item.
+// Step 1 line values of the stage input (2-D), one tile of shape LW per item.
+template <int LW>
 __global__ __launch_bounds__(256) void kb_lines(const BTab* tab, int stage, int remap) {
-  __shared__ double sm[LinesLds::total];
+  __shared__ double sm[LinesLds<LW>::total];
   for_items(tab, PH_LINES, remap, [&](const BJob& J, int k) {
     if (!J.B.hdr->active) return;
     const double* Uin = stage == 1 ? J.B.U : J.B.S;
     const int bx = k % J.ltx, by = k / J.ltx;
     switch (J.M) {
-      case 2: lines_tile<2, true>(J.g, J.C, Uin, J.B.sxo, J.B.syo, J.B.lvx, J.B.lvy, J.B.hdr, bx, by, sm); break;
-      case 3: lines_tile<3, true>(J.g, J.C, Uin, J.B.sxo, J.B.syo, J.B.lvx, J.B.lvy, J.B.hdr, bx, by, sm); break;
-      default: lines_tile<4, true>(J.g, J.C, Uin, J.B.sxo, J.B.syo, J.B.lvx, J.B.lvy, J.B.hdr, bx, by, sm); break;
+      case 2: lines_tile<2, true, LW>(J.g, J.C, Uin, J.B.sxo, J.B.syo, J.B.lvx, J.B.lvy, J.B.hdr, bx, by, sm); break;
+      case 3: lines_tile<3, true, LW>(J.g, J.C, Uin, J.B.sxo, J.B.syo, J.B.lvx, J.B.lvy, J.B.hdr, bx, by, sm); break;
+      default: lines_tile<4, true, LW>(J.g, J.C, Uin, J.B.sxo, J.B.syo, J.B.lvx, J.B.lvy, J.B.hdr, bx, by, sm); break;
     }
   });
 }
 
 // Fused reconstruction + flux + update of one direction and stage over the
-// face tiles of every job of order m = M.
-template <int DIR, int STAGE, typename T, int M>
+// face tiles (shape V) of every job of order m = M.
+template <int DIR, int STAGE, typename T, int M, int V>
 __global__ __launch_bounds__(256, 1) void kb_face(const BTab* tab, int remap) {
   extern __shared__ __align__(16) unsigned char smem[];
   for_items(tab, ph_face(DIR, M), remap, [&](const BJob& J, int k) {
     const int nbx = J.fnb[DIR][0], nby = J.fnb[DIR][1];
     // neighbours along x first (x-faces: normal-first, y-faces: tangential-first)
     const int bx = DIR == 0 ? k % nbx : k / nby, by = DIR == 0 ? k / nbx : k % nby;
-    face2d_tile<DIR, STAGE, M, T, false, 32, false>(J.g, J.C, J.B, smem, bx, by, nbx, nby);
+    face2d_tile<DIR, STAGE, M, T, false, 32, false, V>(J.g, J.C, J.B, smem, bx, by, nbx, nby);
   });
 }
 
@@ -178,7 +179,8 @@ struct cgks_batch {
   int dim = 0, precision = 0, cap = 0;
   size_t budget = 0, used = 0;
   int ncu = 0;
-  int occ[NK] = {};          // resident blocks per CU of each kernel slot
+  int occ[NK] = {};          // resident blocks per CU of each kernel slot (current shapes)
+  int occ_face[kFaceTiles] = {}, occ_lines[kLineTiles] = {};   // per tile shape
   cgks_batch_tuning tune{};  // persistent-grid multiplier and XCD remap in use
   int grid[NK] = {};
   std::vector<BJob> slots;
@@ -204,6 +206,8 @@ struct cgks_batch {
 namespace {
 
 void set_grids(cgks_batch* b) {
+  b->occ[K_FACE] = b->occ_face[b->tune.face_tile];
+  b->occ[K_LINES] = b->occ_lines[b->tune.line_tile];
   for (int k = 0; k < NK; ++k) {
     int g = b->ncu * std::max(1, b->occ[k]) * std::max(1, b->tune.grid_mult);
     b->grid[k] = (g + 7) & ~7;   // a multiple of 8 (one share per XCD)
@@ -213,31 +217,39 @@ void set_grids(cgks_batch* b) {
 
 // Dynamic LDS limit of the batched face kernels and the scratch check of
 // every batched kernel (none may use scratch).
-template <int DIR, int STAGE, typename T, int M>
+template <int DIR, int STAGE, typename T, int M, int V>
 cgks_status prepare_bface() {
-  const void* f = (const void*)kb_face<DIR, STAGE, T, M>;
-  hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)Lds<M, T>::total);
+  const void* f = (const void*)kb_face<DIR, STAGE, T, M, V>;
+  hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)Lds<M, T, V>::total);
   if (e != hipSuccess) return fail(CGKS_EHIP, std::string("hipFuncSetAttribute: ") + hipGetErrorString(e));
   return check_private(f, 0, "batched face kernel");
 }
 
-template <typename T, int M>
+template <typename T, int M, int V>
 cgks_status prepare_bfaces() {
   cgks_status s;
-  if ((s = prepare_bface<0, 1, T, M>()) != CGKS_OK) return s;
-  if ((s = prepare_bface<1, 1, T, M>()) != CGKS_OK) return s;
-  if ((s = prepare_bface<0, 2, T, M>()) != CGKS_OK) return s;
-  return prepare_bface<1, 2, T, M>();
+  if ((s = prepare_bface<0, 1, T, M, V>()) != CGKS_OK) return s;
+  if ((s = prepare_bface<1, 1, T, M, V>()) != CGKS_OK) return s;
+  if ((s = prepare_bface<0, 2, T, M, V>()) != CGKS_OK) return s;
+  return prepare_bface<1, 2, T, M, V>();
+}
+
+template <typename T, int V>
+cgks_status prepare_bshape() {
+  cgks_status s;
+  if ((s = prepare_bfaces<T, 2, V>()) != CGKS_OK) return s;
+  if ((s = prepare_bfaces<T, 3, V>()) != CGKS_OK) return s;
+  return prepare_bfaces<T, 4, V>();
 }
 
 template <typename T>
 cgks_status prepare_batch() {
   cgks_status s;
-  if ((s = prepare_bfaces<T, 2>()) != CGKS_OK) return s;
-  if ((s = prepare_bfaces<T, 3>()) != CGKS_OK) return s;
-  if ((s = prepare_bfaces<T, 4>()) != CGKS_OK) return s;
-  const void* k[] = {(const void*)kb_dt, (const void*)kb_prep, (const void*)kb_bcs, (const void*)kb_lines,
-                     (const void*)kb_stage1d<1, T>, (const void*)kb_stage1d<2, T>};
+  if ((s = prepare_bshape<T, 0>()) != CGKS_OK) return s;
+  if ((s = prepare_bshape<T, 1>()) != CGKS_OK) return s;
+  if ((s = prepare_bshape<T, 2>()) != CGKS_OK) return s;
+  const void* k[] = {(const void*)kb_dt, (const void*)kb_prep, (const void*)kb_bcs, (const void*)kb_lines<0>,
+                     (const void*)kb_lines<1>, (const void*)kb_stage1d<1, T>, (const void*)kb_stage1d<2, T>};
   for (const void* f : k)
     if ((s = check_private(f, 0, "batched kernel")) != CGKS_OK) return s;
   return CGKS_OK;
@@ -249,21 +261,51 @@ hipError_t occupancy(cgks_batch* b) {
   if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&b->occ[K_DT], kb_dt, 256, 0))) return e;
   if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&b->occ[K_PREP], kb_prep, 256, 0))) return e;
   if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&b->occ[K_BCS], kb_bcs, 256, 0))) return e;
-  if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&b->occ[K_LINES], kb_lines, 256, 0))) return e;
-  // the face grid serves every order: size it by the largest tile (m = 4)
-  if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&b->occ[K_FACE], kb_face<1, 2, T, 4>, 256,
-                                                        Lds<4, T>::total)))
+  if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&b->occ_lines[0], kb_lines<0>, 256, 0))) return e;
+  if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&b->occ_lines[1], kb_lines<1>, 256, 0))) return e;
+  // the face grid serves every order: size it by the order that fits the
+  // fewest blocks (the largest LDS tile)
+  auto face_occ = [&](const void* f2, size_t l2, const void* f3, size_t l3, const void* f4, size_t l4, int* out) {
+    int a = 0, c = 0, d = 0;
+    hipError_t r = hipOccupancyMaxActiveBlocksPerMultiprocessor(&a, f2, 256, l2);
+    if (r == hipSuccess) r = hipOccupancyMaxActiveBlocksPerMultiprocessor(&c, f3, 256, l3);
+    if (r == hipSuccess) r = hipOccupancyMaxActiveBlocksPerMultiprocessor(&d, f4, 256, l4);
+    *out = std::min(a, std::min(c, d));
+    return r;
+  };
+  if ((e = face_occ((const void*)kb_face<1, 2, T, 2, 0>, Lds<2, T, 0>::total, (const void*)kb_face<1, 2, T, 3, 0>,
+                    Lds<3, T, 0>::total, (const void*)kb_face<1, 2, T, 4, 0>, Lds<4, T, 0>::total, &b->occ_face[0])))
+    return e;
+  if ((e = face_occ((const void*)kb_face<1, 2, T, 2, 1>, Lds<2, T, 1>::total, (const void*)kb_face<1, 2, T, 3, 1>,
+                    Lds<3, T, 1>::total, (const void*)kb_face<1, 2, T, 4, 1>, Lds<4, T, 1>::total, &b->occ_face[1])))
+    return e;
+  if ((e = face_occ((const void*)kb_face<1, 2, T, 2, 2>, Lds<2, T, 2>::total, (const void*)kb_face<1, 2, T, 3, 2>,
+                    Lds<3, T, 2>::total, (const void*)kb_face<1, 2, T, 4, 2>, Lds<4, T, 2>::total, &b->occ_face[2])))
     return e;
   return hipOccupancyMaxActiveBlocksPerMultiprocessor(&b->occ[K_S1D], kb_stage1d<2, T>, 256, 0);
 }
 
-// The face kernels of one direction and stage, one launch per order.
+// The face kernels of one direction, stage and tile shape, one launch per order.
+template <int DIR, int STAGE, typename T, int V>
+void launch_faces_v(int gf, hipStream_t st, const BTab* t, int r) {
+  constexpr size_t l2 = Lds<2, T, V>::total, l3 = Lds<3, T, V>::total, l4 = Lds<4, T, V>::total;
+  hipLaunchKernelGGL((kb_face<DIR, STAGE, T, 2, V>), dim3(gf), dim3(256), l2, st, t, r);
+  hipLaunchKernelGGL((kb_face<DIR, STAGE, T, 3, V>), dim3(gf), dim3(256), l3, st, t, r);
+  hipLaunchKernelGGL((kb_face<DIR, STAGE, T, 4, V>), dim3(gf), dim3(256), l4, st, t, r);
+}
+
 template <int DIR, int STAGE, typename T>
-void launch_faces(int gf, hipStream_t st, const BTab* t, int r) {
-  constexpr size_t l2 = Lds<2, T>::total, l3 = Lds<3, T>::total, l4 = Lds<4, T>::total;
-  hipLaunchKernelGGL((kb_face<DIR, STAGE, T, 2>), dim3(gf), dim3(256), l2, st, t, r);
-  hipLaunchKernelGGL((kb_face<DIR, STAGE, T, 3>), dim3(gf), dim3(256), l3, st, t, r);
-  hipLaunchKernelGGL((kb_face<DIR, STAGE, T, 4>), dim3(gf), dim3(256), l4, st, t, r);
+void launch_faces(int v, int gf, hipStream_t st, const BTab* t, int r) {
+  switch (v) {
+    case 1: launch_faces_v<DIR, STAGE, T, 1>(gf, st, t, r); break;
+    case 2: launch_faces_v<DIR, STAGE, T, 2>(gf, st, t, r); break;
+    default: launch_faces_v<DIR, STAGE, T, 0>(gf, st, t, r); break;
+  }
+}
+
+void launch_lines(int lw, int gl, hipStream_t st, const BTab* t, int stage, int r) {
+  if (lw == 1) hipLaunchKernelGGL(kb_lines<1>, dim3(gl), dim3(256), 0, st, t, stage, r);
+  else hipLaunchKernelGGL(kb_lines<0>, dim3(gl), dim3(256), 0, st, t, stage, r);
 }
 
 template <typename T>
@@ -278,16 +320,17 @@ hipError_t enqueue_batch_step(const cgks_batch* b, hipStream_t st) {
     hipLaunchKernelGGL((kb_stage1d<2, T>), dim3(b->grid[K_S1D]), dim3(256), 0, st, t, r);
     return hipGetLastError();
   }
-  const int gf = b->grid[K_FACE];
+  const int gf = b->grid[K_FACE], gl = b->grid[K_LINES];
+  const int v = b->tune.face_tile, lw = b->tune.line_tile;
   // every order is launched (a phase without jobs of that order ends at
   // once), so a captured step serves any later mix of orders
-  hipLaunchKernelGGL(kb_lines, dim3(b->grid[K_LINES]), dim3(256), 0, st, t, 1, r);
-  launch_faces<0, 1, T>(gf, st, t, r);
-  launch_faces<1, 1, T>(gf, st, t, r);
+  launch_lines(lw, gl, st, t, 1, r);
+  launch_faces<0, 1, T>(v, gf, st, t, r);
+  launch_faces<1, 1, T>(v, gf, st, t, r);
   hipLaunchKernelGGL(kb_bcs, dim3(b->grid[K_BCS]), dim3(256), 0, st, t, r);
-  hipLaunchKernelGGL(kb_lines, dim3(b->grid[K_LINES]), dim3(256), 0, st, t, 2, r);
-  launch_faces<0, 2, T>(gf, st, t, r);
-  launch_faces<1, 2, T>(gf, st, t, r);
+  launch_lines(lw, gl, st, t, 2, r);
+  launch_faces<0, 2, T>(v, gf, st, t, r);
+  launch_faces<1, 2, T>(v, gf, st, t, r);
   return hipGetLastError();
 }
 
@@ -305,22 +348,22 @@ void drop_graph(cgks_batch* b) {
   b->graph_steps = 0;
 }
 
-// Tile counts of one job for every phase (the single-grid launch shapes).
-void fill_counts(BJob& J) {
+// Tile counts of one job for every phase, for the batch's tile shapes.
+void fill_counts(BJob& J, int face_tile, int line_tile) {
   const Geo& g = J.g;
   J.ax = (g.NX + 1 + 255) / 256;
   J.nsx = J.ax * g.NY;
   J.ay = g.dim == 2 ? (g.NY + 1 + 255) / 256 : 0;
   J.nsy = g.dim == 2 ? J.ay * g.NX : 0;
   J.ns = GhostItems(g).count(g);
-  J.ltx = (g.NX + LT_X - 1) / LT_X;
-  J.lty = (g.NY + LT_Y - 1) / LT_Y;
+  J.ltx = (g.NX + line_tile_x(line_tile) - 1) / line_tile_x(line_tile);
+  J.lty = (g.NY + line_tile_y(line_tile) - 1) / line_tile_y(line_tile);
   if (g.dim == 2) {
-    const int NF = 16, NT = J.M == 2 ? 8 : (J.M == 3 ? 5 : 4);
-    J.fnb[0][0] = (g.nx + NF - 2) / (NF - 1);
-    J.fnb[0][1] = (g.ny + NT - 1) / NT;
-    J.fnb[1][0] = (g.ny + NF - 2) / (NF - 1);
-    J.fnb[1][1] = (g.nx + NT - 1) / NT;
+    const int NF = tile_nf(face_tile), NT = tile_nt(face_tile, J.M);
+    J.fnb[0][0] = face_tiles_n(g.nx, NF);
+    J.fnb[0][1] = face_tiles_t(g.ny, NT);
+    J.fnb[1][0] = face_tiles_n(g.ny, NF);
+    J.fnb[1][1] = face_tiles_t(g.nx, NT);
     J.nseg = 0;
   } else {
     J.fnb[0][0] = J.fnb[0][1] = J.fnb[1][0] = J.fnb[1][1] = 0;
@@ -463,7 +506,7 @@ cgks_status cgks_batch_add(cgks_batch* b, const cgks_plan* p, void* d_state, voi
   J.viscous = p->C.tau_model == CGKS_TAU_VISCOUS ? 1 : 0;
   J.M = p->g.m;
   J.slot = s;
-  fill_counts(J);
+  fill_counts(J, b->tune.face_tile, b->tune.line_tile);
   JobStat& is = b->init_stat[s];
   is.t = hh.t;
   is.dt = hh.dt;
@@ -608,9 +651,20 @@ cgks_status cgks_batch_info(const cgks_batch* b, int* njobs, size_t* bytes_used,
 cgks_status cgks_batch_set_tuning(cgks_batch* b, const cgks_batch_tuning* t) {
   if (!b || !t) return fail(CGKS_EINVAL, "NULL argument");
   if (t->grid_mult < 1 || t->grid_mult > 16) return fail(CGKS_EINVAL, "grid_mult must lie in [1, 16]");
+  if (t->face_tile < 0 || t->face_tile >= kFaceTiles) return fail(CGKS_EINVAL, "face_tile must lie in [0, 2]");
+  if (t->line_tile < 0 || t->line_tile >= kLineTiles) return fail(CGKS_EINVAL, "line_tile must lie in [0, 1]");
+  const bool reshape = t->face_tile != b->tune.face_tile || t->line_tile != b->tune.line_tile;
   b->tune.grid_mult = t->grid_mult;
   b->tune.xcd_remap = t->xcd_remap ? 1 : 0;
+  b->tune.face_tile = t->face_tile;
+  b->tune.line_tile = t->line_tile;
   b->tune.ms_per_step = t->ms_per_step;
+  if (reshape) {
+    // the jobs' tile counts follow the shapes: the table must be uploaded again
+    for (int k = 0; k < b->cap; ++k)
+      if (b->busy[k]) fill_counts(b->slots[k], b->tune.face_tile, b->tune.line_tile);
+    b->committed = false;
+  }
   set_grids(b);
   drop_graph(b);   // launch shapes are baked into a captured graph
   return CGKS_OK;
@@ -623,8 +677,11 @@ cgks_status cgks_batch_get_tuning(const cgks_batch* b, cgks_batch_tuning* t) {
 }
 
 // Times `steps_per_trial` real steps of the committed jobs under each
-// candidate launch shape and keeps the fastest.  Every candidate computes the
-// same result, so the trial steps advance the jobs as ordinary steps do.
+// candidate and keeps the fastest: first the tile shapes of the face and
+// Step 1 kernels (2-D batches; the table is uploaded again for each), with
+// the current grid multiplier and remap, then the grid multiplier and remap
+// with the chosen shapes.  Every candidate computes the same result, so the
+// trial steps advance the jobs as ordinary steps do.
 cgks_status cgks_batch_tune(cgks_batch* b, int steps_per_trial, void* stream, cgks_batch_tuning* chosen) {
   if (!b) return fail(CGKS_EINVAL, "NULL batch");
   if (!b->committed) return fail(CGKS_ESTATE, "batch changed since the last cgks_batch_commit");
@@ -633,33 +690,52 @@ cgks_status cgks_batch_tune(cgks_batch* b, int steps_per_trial, void* stream, cg
   hipEvent_t e0, e1;
   HIP_TRY(hipEventCreate(&e0));
   HIP_TRY(hipEventCreate(&e1));
-  const int mults[] = {1, 2, 4};
   cgks_batch_tuning best = b->tune;
   best.ms_per_step = -1.0f;
   hipError_t e = hipSuccess;
-  for (int remap = 0; remap < 2 && e == hipSuccess; ++remap)
-    for (int mi = 0; mi < 3 && e == hipSuccess; ++mi) {
+  cgks_status cs = CGKS_OK;
+  auto trial = [&](const cgks_batch_tuning& c) {
+    cgks_batch_tuning t = c;
+    if ((cs = cgks_batch_set_tuning(b, &t)) != CGKS_OK) return;
+    if (!b->committed && (cs = cgks_batch_commit(b, stream)) != CGKS_OK) return;
+    if ((e = hipEventRecord(e0, st)) != hipSuccess) return;
+    if ((e = enqueue_steps(b, steps_per_trial, st)) != hipSuccess) return;
+    if ((e = hipEventRecord(e1, st)) != hipSuccess) return;
+    if ((e = hipEventSynchronize(e1)) != hipSuccess) return;
+    float ms = 0.0f;
+    if ((e = hipEventElapsedTime(&ms, e0, e1)) != hipSuccess) return;
+    t.ms_per_step = ms / steps_per_trial;
+    if (best.ms_per_step < 0.0f || t.ms_per_step < best.ms_per_step) best = t;
+  };
+  const cgks_batch_tuning start = b->tune;
+  if (b->dim == 2)
+    for (int v = 0; v < kFaceTiles && e == hipSuccess && cs == CGKS_OK; ++v)
+      for (int lw = 0; lw < kLineTiles && e == hipSuccess && cs == CGKS_OK; ++lw) {
+        cgks_batch_tuning c = start;
+        c.face_tile = v;
+        c.line_tile = lw;
+        trial(c);
+      }
+  const int mults[] = {1, 2, 4};
+  const int fv = b->dim == 2 ? best.face_tile : start.face_tile, flw = b->dim == 2 ? best.line_tile : start.line_tile;
+  for (int remap = 0; remap < 2 && e == hipSuccess && cs == CGKS_OK; ++remap)
+    for (int mi = 0; mi < 3 && e == hipSuccess && cs == CGKS_OK; ++mi) {
       cgks_batch_tuning c{};
       c.grid_mult = mults[mi];
       c.xcd_remap = remap;
-      b->tune = c;
-      set_grids(b);
-      if ((e = hipEventRecord(e0, st)) != hipSuccess) break;
-      if ((e = enqueue_steps(b, steps_per_trial, st)) != hipSuccess) break;
-      if ((e = hipEventRecord(e1, st)) != hipSuccess) break;
-      if ((e = hipEventSynchronize(e1)) != hipSuccess) break;
-      float ms = 0.0f;
-      if ((e = hipEventElapsedTime(&ms, e0, e1)) != hipSuccess) break;
-      c.ms_per_step = ms / steps_per_trial;
-      if (best.ms_per_step < 0.0f || c.ms_per_step < best.ms_per_step) best = c;
+      c.face_tile = fv;
+      c.line_tile = flw;
+      trial(c);
     }
   hipEventDestroy(e0);
   hipEventDestroy(e1);
+  if (cs != CGKS_OK) return cs;
   if (e != hipSuccess) return fail(CGKS_EHIP, std::string("tune: ") + hipGetErrorString(e));
-  b->tune = best;
-  set_grids(b);
-  drop_graph(b);
-  if (chosen) *chosen = best;
+  cgks_batch_tuning keep = best;
+  if ((cs = cgks_batch_set_tuning(b, &keep)) != CGKS_OK) return cs;
+  if (!b->committed && (cs = cgks_batch_commit(b, stream)) != CGKS_OK) return cs;
+  b->tune.ms_per_step = best.ms_per_step;
+  if (chosen) *chosen = b->tune;
   return CGKS_OK;
 }
 

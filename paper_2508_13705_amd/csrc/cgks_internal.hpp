@@ -644,24 +644,32 @@ __device__ __forceinline__ int tile_tid() {
 // loaded once per tile, and the gradient means are formed once per cell
 // rather than once per use (with the same operations in the same order as
 // forming them at each use, so the results do not depend on the tiling).
-constexpr int LT_X = 32, LT_Y = 8;
-struct LinesLds {
-  static constexpr int BX = LT_X + 4, BY = LT_Y + 4;
+// Tile shapes (LW): 0 = 32 x 8 cells (the single-grid shape), 1 = 16 x 16
+// (fewer halo cells along x, shorter rows); the batched path's autotuner
+// picks one.  Results do not depend on the shape.
+constexpr int kLineTiles = 2;
+template <int LW = 0> struct LinesLds {
+  static constexpr int X = LW == 0 ? 32 : 16, Y = LW == 0 ? 8 : 16;
+  static constexpr int BX = X + 4, BY = Y + 4;
   static constexpr int NAVG = 4 * BY * BX;        // averages [v][BY][BX], cells (i0-2+xx, j0-2+yy)
-  static constexpr int NGY = 4 * BY * LT_X;       // y-gradient means [v][BY][LT_X], cells (i0+xx, j0-2+yy)
-  static constexpr int NGX = 4 * LT_Y * BX;       // x-gradient means [v][LT_Y][BX], cells (i0-2+xx, j0+yy)
-  static constexpr int SYN = LT_Y + 5, SXN = LT_X + 5;
-  static constexpr int NSY = LT_X * SYN;          // y-face strengths [xx][gg], face j0-2+gg of column i0+xx
-  static constexpr int NSX = LT_Y * SXN;          // x-face strengths [yy][ff], face i0-2+ff of row j0+yy
+  static constexpr int NGY = 4 * BY * X;          // y-gradient means [v][BY][X], cells (i0+xx, j0-2+yy)
+  static constexpr int NGX = 4 * Y * BX;          // x-gradient means [v][Y][BX], cells (i0-2+xx, j0+yy)
+  static constexpr int SYN = Y + 5, SXN = X + 5;
+  static constexpr int NSY = X * SYN;             // y-face strengths [xx][gg], face j0-2+gg of column i0+xx
+  static constexpr int NSX = Y * SXN;             // x-face strengths [yy][ff], face i0-2+ff of row j0+yy
   static constexpr int total = NAVG + NGY + NGX + NSY + NSX;   // doubles
+  static_assert(X * Y == 256, "one cell per thread");
 };
-static_assert(LT_X * LT_Y == 256, "one cell per thread");
+constexpr int LT_X = LinesLds<0>::X, LT_Y = LinesLds<0>::Y;   // the single-grid shape
+inline int line_tile_x(int lw) { return lw == 0 ? 32 : 16; }
+inline int line_tile_y(int lw) { return lw == 0 ? 8 : 16; }
 
-template <int M, bool PERSIST = false>
+template <int M, bool PERSIST = false, int LW = 0>
 __device__ __forceinline__ void lines_tile(const Geo& g, const Consts& C, const double* U, const double* sxo,
                                            const double* syo, double* lvx, double* lvy, Header* hdr, int bx,
                                            int by, double* sm) {
-  using L = LinesLds;
+  using L = LinesLds<LW>;
+  constexpr int LT_X = L::X, LT_Y = L::Y;
   __shared__ Tally tally;
   const gptr<const double> Ug = glb(U), sxg = glb(sxo), syg = glb(syo);
   const gptr<double> lvxg = glb(lvx), lvyg = glb(lvy);
@@ -829,13 +837,28 @@ __device__ __forceinline__ void lines_tile(const Geo& g, const Consts& C, const 
 // source executed on the CPU is exact.  The heavy phases of the face tile and
 // of the 1-D stage therefore run on all lanes: a lane without an item of its
 // own recomputes a valid one and only its stores are masked.
-template <int M> struct Tile {
-  static constexpr int NF = 16;                               // faces along the normal
-  static constexpr int NT = M == 2 ? 8 : (M == 3 ? 5 : 4);    // lines along the tangential
+// Tile shapes (V): 0 = 16 faces x NT lines (the single-grid shape), 1 = 32 x
+// NT/2 (fewer seam faces computed twice, more halo lines), 2 = 8 x 2 NT
+// (fewer halo lines, more seam faces).  The batched kernels take any of them
+// (chosen by the batch autotuner); the arithmetic of every face and cell is
+// the same in all of them.
+constexpr int kFaceTiles = 3;
+template <int M, int V = 0> struct Tile {
+  static constexpr int NF = V == 1 ? 32 : (V == 2 ? 8 : 16);  // faces along the normal
+  static constexpr int NT = V == 0 ? (M == 2 ? 8 : (M == 3 ? 5 : 4))
+                          : (V == 1 ? (M == 2 ? 4 : 2) : (M == 2 ? 16 : (M == 3 ? 10 : 8)));  // lines
   static constexpr int NC = NF + 1;                           // reconstructed cells
   static constexpr int NR = NT + 2;                           // reconstructed lines
   static constexpr int RK1 = 17, RK2 = 8;                     // results per Gauss point (stage 1 / 2)
+  static_assert(NF * NT * M <= 256, "one Gauss point per thread");
 };
+// tiles of one direction of an nn (normal) x nt (tangential) grid
+__host__ __device__ inline int face_tiles_n(int nn, int nf) { return (nn + nf - 2) / (nf - 1); }
+__host__ __device__ inline int face_tiles_t(int nt, int nlines) { return (nt + nlines - 1) / nlines; }
+inline int tile_nf(int v) { return v == 1 ? 32 : (v == 2 ? 8 : 16); }
+inline int tile_nt(int v, int m) {
+  return v == 0 ? (m == 2 ? 8 : (m == 3 ? 5 : 4)) : (v == 1 ? (m == 2 ? 4 : 2) : (m == 2 ? 16 : (m == 3 ? 10 : 8)));
+}
 
 // LDS of a face tile, laid out by lifetime (barriers B1..B4 of the tile):
 //   staging  Step 2 inputs: line values and h-scaled normal slopes of the
@@ -853,8 +876,11 @@ template <int M> struct Tile {
 //   fin      updated averages of the tile (y-faces), written after B4.
 // recon | staging | atab, with res and then fin over recon and staging,
 // which are dead once B3 has passed.
-template <int M, typename T> struct Lds {
-  using TL = Tile<M>;
+// smallest stride >= n with stride mod 32 = 16 (two lines of 16 lanes on
+// disjoint bank halves), for the shapes whose strides were not enumerated
+constexpr int stride16(int n) { return n + (48 - n % 32) % 32; }
+template <int M, typename T, int V = 0> struct Lds {
+  using TL = Tile<M, V>;
   static constexpr int RS = 8 * M + 1;
   // Step 2 records of (line r, cell c): x-faces row-major, r RW + c RS;
   // y-faces cell-major, c CS + r RS.  A group of lanes that the LDS serves
@@ -863,8 +889,8 @@ template <int M, typename T> struct Lds {
   // strides RW and CS put every lane of such a group on its own bank in
   // Step 3 (found by enumerating strides against the lane layout).  The
   // second-derivative records (NT lines) use RW and cell stride CSD.
-  static constexpr int RW = M == 2 ? 304 : (M == 3 ? 432 : 592);
-  static constexpr int CS = M == 2 ? 200 : (M == 3 ? 189 : 204);
+  static constexpr int RW = V == 0 ? (M == 2 ? 304 : (M == 3 ? 432 : 592)) : stride16(TL::NC * RS);
+  static constexpr int CS = V == 0 ? (M == 2 ? 200 : (M == 3 ? 189 : 204)) : (TL::NR * RS) | 1;
   static constexpr int CSD = TL::NT * RS;
   static_assert(RW >= TL::NC * RS && CS >= TL::NR * RS, "records do not overlap");
   static constexpr int NCS = TL::NC + 4, NSG = TL::NC + 5;
@@ -907,10 +933,11 @@ __device__ __forceinline__ T tanw(int m, int l, int k) {
 // with a barrier so the LDS of the previous tile is free).  SU: staging passes
 // whose loads are issued together (all of them where registers allow; the
 // persistent batched kernels keep more per-job state live and take fewer).
-template <int DIR, int STAGE, int M, typename T, bool PR, int SU = 32, bool PERSIST = false>
+template <int DIR, int STAGE, int M, typename T, bool PR, int SU = 32, bool PERSIST = false, int V = 0>
 __device__ void face2d_tile(const Geo& g, const Consts& C, const Bufs& B, unsigned char* smem, int bx, int by,
                             int nbx, int nby) {
-  using TL = Tile<M>;
+  using TL = Tile<M, V>;
+  using LD = Lds<M, T, V>;
   constexpr int NF = TL::NF, NT = TL::NT, NC = TL::NC, NR = TL::NR;
   const gptr<const Header> hdr = glb((const Header*)B.hdr);
   __shared__ Tally tally;
@@ -921,17 +948,17 @@ __device__ void face2d_tile(const Geo& g, const Consts& C, const Bufs& B, unsign
   tally_zero(tally, tx);
   const double dt = hdr->dt;
   T* s2v = (T*)smem;
-  T* s2d = (T*)(smem + Lds<M, T>::s2v);
-  T* s2dd = (T*)(smem + Lds<M, T>::s2v + Lds<M, T>::s2d);
-  double* res = (double*)(smem + Lds<M, T>::off_res);     // over recon and staging, after B3
-  double* fin = (double*)(smem + Lds<M, T>::off_fin);
-  constexpr int RS = Lds<M, T>::RS;
+  T* s2d = (T*)(smem + LD::s2v);
+  T* s2dd = (T*)(smem + LD::s2v + LD::s2d);
+  double* res = (double*)(smem + LD::off_res);     // over recon and staging, after B3
+  double* fin = (double*)(smem + LD::off_fin);
+  constexpr int RS = LD::RS;
   constexpr int NB = NF * NT * M;   // Gauss points of the tile
   auto I2 = [&](int r, int c, int l, int sd, int v) {     // value and normal-derivative records
-    return (DIR == 0 ? r * Lds<M, T>::RW + c * RS : c * Lds<M, T>::CS + r * RS) + (l * 2 + sd) * 4 + v;
+    return (DIR == 0 ? r * LD::RW + c * RS : c * LD::CS + r * RS) + (l * 2 + sd) * 4 + v;
   };
   auto I2D = [&](int r, int c, int l, int sd, int v) {    // second-derivative records (r < NT)
-    return (DIR == 0 ? r * Lds<M, T>::RW + c * RS : c * Lds<M, T>::CSD + r * RS) + (l * 2 + sd) * 4 + v;
+    return (DIR == 0 ? r * LD::RW + c * RS : c * LD::CSD + r * RS) + (l * 2 + sd) * 4 + v;
   };
   // Gauss point (face f, line r, node l) -> its thread / result column
   auto gp = [&](int f, int r, int l) { return DIR == 0 ? f + NF * (r + NT * l) : r + NT * (f + NF * l); };
@@ -959,11 +986,11 @@ __device__ void face2d_tile(const Geo& g, const Consts& C, const Bufs& B, unsign
   // Entries outside the stored grid (ghosts included) are clamped into it;
   // only items that no thread owns read them.  Every pass runs on all lanes
   // (wave-uniform); only the LDS stores are masked.
-  constexpr int NCS = Lds<M, T>::NCS, NSG = Lds<M, T>::NSG, NSTV = Lds<M, T>::NSTV;
-  T* stv = (T*)(smem + Lds<M, T>::off_staging);                    // [v][l][r][cc]
+  constexpr int NCS = LD::NCS, NSG = LD::NSG, NSTV = LD::NSTV;
+  T* stv = (T*)(smem + LD::off_staging);                    // [v][l][r][cc]
   T* sts = stv + NSTV;                                               // same shape
-  double* stg = (double*)(smem + Lds<M, T>::off_staging + Lds<M, T>::st_sg);   // [r][ff]
-  T* atab = (T*)(smem + Lds<M, T>::off_atab);                       // [c][r], r < NT
+  double* stg = (double*)(smem + LD::off_staging + LD::st_sg);   // [r][ff]
+  T* atab = (T*)(smem + LD::off_atab);                       // [c][r], r < NT
   auto clampi = [](int x, int lo, int hi) { return x < lo ? lo : (x > hi ? hi : x); };
   {
     // a lane keeps one (line, cell) position of a staged plane; the passes

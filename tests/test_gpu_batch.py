@@ -183,11 +183,41 @@ def test_every_launch_shape_gives_the_same_result():
     for s in sol:
         b.add(s, max_steps=8)
     b.commit()
-    t = b.tune(1)                  # 6 candidates x 1 step
+    t = b.tune(1)                  # 6 tile-shape and 6 launch candidates x 1 step
     assert t["grid_mult"] in (1, 2, 4) and t["ms_per_step"] > 0
+    assert t["face_tile"] in (0, 1, 2) and t["line_tile"] in (0, 1)
     b.step(2)
     for s, r in zip(sol, ref):
         _same(s.read(), r, 2)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32_flux"])
+def test_every_tile_shape_gives_the_same_result(precision):
+    """The batched face kernels in each tile shape (16 x NT, 32 x NT/2,
+    8 x 2 NT faces x lines) and the Step 1 kernel in each (32 x 8, 16 x 16)
+    compute every face and cell as the job alone does: bit for bit, for
+    uneven jobs of every order; a change of shape between steps is taken
+    after a commit."""
+    from paper_2508_13705_amd import cgks
+    pbs = _mixed_2d()
+    ref = [_alone(pb, precision, 6) for pb in pbs]
+    for ft in range(3):
+        for lt in range(2):
+            _say(f"tile shapes face {ft} lines {lt}, {precision}")
+            b = cgks.Batch(2, precision, max_jobs=8)
+            b.set_tuning(2, 1, ft, lt)
+            sol = [cgks.Solver(pb, precision=precision) for pb in pbs]
+            for q in sol:
+                b.add(q, max_steps=6)
+            b.commit()
+            b.step(3)
+            # switch shapes half way (the table is uploaded again)
+            b.set_tuning(1, 0, (ft + 1) % 3, 1 - lt)
+            b.commit()
+            b.step(3)
+            assert b.tuning()["face_tile"] == (ft + 1) % 3
+            for q, r in zip(sol, ref):
+                _same(q.read(), r, 2)
 
 
 def test_t_end_and_nonphysical_jobs_stop_alone():
