@@ -151,7 +151,7 @@ __global__ __launch_bounds__(256) void kb_lines(const BTab* tab, int stage, int 
 // Fused reconstruction + flux + update of one direction and stage over the
 // face tiles (shape V) of every job of order m = M.
 template <int DIR, int STAGE, typename T, int M, int V>
-__global__ __launch_bounds__(256, 1) void kb_face(const BTab* tab, int remap) {
+__global__ __launch_bounds__(256, sizeof(T) == 4 ? 2 : 1) void kb_face(const BTab* tab, int remap) {
   extern __shared__ __align__(16) unsigned char smem[];
   for_items(tab, ph_face(DIR, M), remap, [&](const BJob& J, int k) {
     const int nbx = J.fnb[DIR][0], nby = J.fnb[DIR][1];
