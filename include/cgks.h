@@ -114,7 +114,21 @@ typedef struct {
   double c1, c2, mu, prandtl;
   double sigma_thres, gamma_hi, gamma_lo, weno_eps;
   int precision;
+  int reading_flags;        /* 0, or a set of CGKS_READ_* below */
 } cgks_scheme_desc;
+
+/* Alternative readings of points the paper leaves open (reading_flags; 0
+ * gives the defaults):
+ *  - CGKS_READ_A3_GAMMA1_LO: the linear weights of Eq. 3.12, whose printed
+ *    form does not sum to one, read with gamma_1 = (1 - gamma_Hi) gamma_Lo and
+ *    gamma_0 = gamma_2 = (1 - gamma_Hi)(1 - gamma_Lo)/2 (default: the central
+ *    S2 takes the gamma_Lo share and gamma_0 = gamma_1, the mirror-symmetric
+ *    choice);
+ *  - CGKS_READ_A5_UNSCALED_BETA: the smoothness indicators of Eq. 3.13 from the
+ *    members before their DFF scaling of Eq. 3.19 (default: after it);
+ *  - CGKS_READ_A10_SIGMA0_ZERO: the strengths of the step before the first
+ *    set to zero (default: those of the piecewise-constant states, Eq. 3.2). */
+enum { CGKS_READ_A3_GAMMA1_LO = 1, CGKS_READ_A5_UNSCALED_BETA = 2, CGKS_READ_A10_SIGMA0_ZERO = 4 };
 
 typedef struct cgks_plan cgks_plan;
 

@@ -53,6 +53,7 @@ class Params(ctypes.Structure):
         ("cfl", ctypes.c_double),
         ("x0", ctypes.c_double), ("y0", ctypes.c_double),
         ("side", Side * 4),
+        ("reading_flags", ctypes.c_int),
     ]
 
 
@@ -150,6 +151,7 @@ def make_params(grid, scheme):
     p.gamma_lo = scheme.get("gamma_lo", 0.6)
     p.weno_eps = scheme.get("weno_eps", 1e-8)
     p.cfl = scheme.get("cfl", 0.5)
+    p.reading_flags = int(scheme.get("reading_flags", 0))
     return p
 
 

@@ -78,6 +78,8 @@ typedef struct {
   double cfl;
   double x0, y0;      /* grid origin: segment ends are absolute coordinates */
   orc_side side[4];
+  int reading_flags;  /* alternative readings: 1 A3 (gamma_1 takes the gamma_Lo share),
+                         2 A5 (indicators of the unscaled members), 4 A10 (first-step strengths 0) */
 } orc_params;
 
 /* ------------------------------------------------------------------------- */
@@ -740,13 +742,19 @@ static int ase_dff_poly(const orc_params* P, const double* q, const double* hq, 
     for (int k = 0; k < 4; ++k) {
       stencil_fit(which[k], q, hq, pk[k]);
       alpha[k] = (k < 3) ? dff_alpha(which[k], sig, th) : a5;
+      /* A5: indicators of the scaled members (default), or of the unscaled
+       * members (alternative reading) */
+      if (P->reading_flags & 2) beta[k] = orc_beta(pk[k], deg[k]);
       pk[k][0] = Q0 + alpha[k] * (pk[k][0] - Q0);
       for (int j = 1; j < 9; ++j) pk[k][j] *= alpha[k];
-      beta[k] = orc_beta(pk[k], deg[k]);
+      if (!(P->reading_flags & 2)) beta[k] = orc_beta(pk[k], deg[k]);
     }
-    /* linear weights (Eq. 3.12 read as A3) */
+    /* linear weights (Eq. 3.12 read as A3): the central S2 takes the gamma_Lo
+     * share; the alternative reading gives it to S1 (as the printed gamma_1
+     * suggests) and splits the rest between S0 and S2 */
     double gH = P->gamma_hi, gL = P->gamma_lo;
     double g[4] = {(1.0 - gH) * (1.0 - gL) / 2.0, (1.0 - gH) * (1.0 - gL) / 2.0, (1.0 - gH) * gL, gH};
+    if (P->reading_flags & 1) { g[1] = (1.0 - gH) * gL; g[2] = (1.0 - gH) * (1.0 - gL) / 2.0; }
     /* WENO-Z weights (Eq. 3.14-3.16, A4) */
     double tz = (fabs(beta[3] - beta[0]) + fabs(beta[3] - beta[1]) + fabs(beta[3] - beta[2])) / 3.0;
     double w[4], ws = 0.0;
@@ -1355,7 +1363,9 @@ int orc_run(const orc_params* P, double* avg, double* sx, double* sy, double* si
           if (D == 2) GSY(&g, v, l, j, i) = sy[(((size_t)v * m + l) * ny + j) * nx + i];
         }
       }
-  if (init_sig) init_sigma(P, &g, *t_io);
+  /* A10: first-step strengths from the piecewise-constant states (default),
+   * or zero (alternative reading; the calloc'd arrays) */
+  if (init_sig && !(P->reading_flags & 4)) init_sigma(P, &g, *t_io);
   else {
     for (int j = 0; j < ny; ++j)
       for (int F = 0; F <= nx; ++F) GSIGX(&g, j, F) = sigx[(size_t)j * (nx + 1) + F];

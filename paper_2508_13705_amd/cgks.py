@@ -88,7 +88,8 @@ class SchemeDesc(ctypes.Structure):
     _fields_ = [("order", ctypes.c_int), ("gamma", ctypes.c_double), ("tau_model", ctypes.c_int),
                 ("c1", ctypes.c_double), ("c2", ctypes.c_double), ("mu", ctypes.c_double),
                 ("prandtl", ctypes.c_double), ("sigma_thres", ctypes.c_double), ("gamma_hi", ctypes.c_double),
-                ("gamma_lo", ctypes.c_double), ("weno_eps", ctypes.c_double), ("precision", ctypes.c_int)]
+                ("gamma_lo", ctypes.c_double), ("weno_eps", ctypes.c_double), ("precision", ctypes.c_int),
+                ("reading_flags", ctypes.c_int)]
 
 
 class Health(ctypes.Structure):
@@ -194,6 +195,7 @@ def descriptors(problem, precision="fp64"):
     sd.gamma_hi, sd.gamma_lo = s.get("gamma_hi", 0.85), s.get("gamma_lo", 0.6)
     sd.weno_eps = s.get("weno_eps", 1e-8)
     sd.precision = PRECISION[precision]
+    sd.reading_flags = int(s.get("reading_flags", 0))
     return gd, sd
 
 

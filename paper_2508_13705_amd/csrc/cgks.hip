@@ -338,6 +338,8 @@ cgks_status cgks_plan_create(const cgks_grid_desc* gd, const cgks_scheme_desc* s
   if (!(sd->gamma_hi > 0.0 && sd->gamma_hi < 1.0 && sd->gamma_lo > 0.0 && sd->gamma_lo < 1.0))
     return fail(CGKS_EINVAL, "linear weights must lie in (0, 1)");
   if (sd->precision != CGKS_FP64 && sd->precision != CGKS_FP32_FLUX) return fail(CGKS_EINVAL, "unknown precision");
+  if (sd->reading_flags & ~(CGKS_READ_A3_GAMMA1_LO | CGKS_READ_A5_UNSCALED_BETA | CGKS_READ_A10_SIGMA0_ZERO))
+    return fail(CGKS_EINVAL, "unknown reading flag");
   if (gd->nx > (1 << 24) || gd->ny > (1 << 24)) return fail(CGKS_EINVAL, "grid too large");
 
   cgks_plan* p = new (std::nothrow) cgks_plan;
@@ -408,6 +410,15 @@ cgks_status cgks_plan_create(const cgks_grid_desc* gd, const cgks_scheme_desc* s
   C.ghi = sd->gamma_hi;
   C.glo = sd->gamma_lo;
   C.eps = sd->weno_eps;
+  static_assert(RF_A3_GAMMA1_LO == CGKS_READ_A3_GAMMA1_LO && RF_A5_UNSCALED_BETA == CGKS_READ_A5_UNSCALED_BETA &&
+                RF_A10_SIGMA0_ZERO == CGKS_READ_A10_SIGMA0_ZERO, "reading flags");
+  C.rflags = sd->reading_flags;
+  {
+    const double gH = sd->gamma_hi, gL = sd->gamma_lo, share = (1.0 - gH) * (1.0 - gL) / 2.0;
+    C.gw[0] = share;
+    C.gw[1] = (sd->reading_flags & CGKS_READ_A3_GAMMA1_LO) ? (1.0 - gH) * gL : share;
+    C.gw[2] = (sd->reading_flags & CGKS_READ_A3_GAMMA1_LO) ? share : (1.0 - gH) * gL;
+  }
   // near-tie band of the cascade decisions: the strengths entering A carry
   // the rounding of the flux arithmetic (FP64, or FP32 in the FP32-flux
   // variant), summed over up to 12 weighted faces
@@ -526,6 +537,8 @@ cgks_status cgks_init_state(const cgks_plan* p, void* d_state, void* d_work, con
     if (g.dim == 2)
       HIP_TRY(hipMemcpyAsync(b.syn, sy.data(), sy.size() * sizeof(double), hipMemcpyHostToDevice, st));
     HIP_TRY(hipStreamSynchronize(st));
+  } else if (p->C.rflags & CGKS_READ_A10_SIGMA0_ZERO) {
+    // first-step strengths zero: the work buffer was cleared above
   } else {
     dim3 gx((nx + 1 + 255) / 256, g.dim == 2 ? ny : 1);
     hipLaunchKernelGGL(k_init_sigma, gx, dim3(256), 0, st, g, 0, p->C.gamma, b.U, b.sxn, b.syn);

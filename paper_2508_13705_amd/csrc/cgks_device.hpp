@@ -32,10 +32,14 @@ struct Consts {
   double c1, c2, mu, prandtl;
   double prfac;              // 1/prandtl - 1: weight of the heat flux in the Prandtl fix
   double thres, ghi, glo, eps;
+  double gw[3];              // linear weights of the sub-stencils S0, S1, S2 (AO(5,3), Eq. 3.12)
   double tie;                // |A - thres| <= tie: a cascade decision counted as a near tie
   double dx, dy;
   int tau_model, order, m;
+  int rflags;                // alternative readings, a set of RF_* below
 };
+// bits of Consts::rflags, equal to the CGKS_READ_* flags of the C interface
+enum : int { RF_A3_GAMMA1_LO = 1, RF_A5_UNSCALED_BETA = 2, RF_A10_SIGMA0_ZERO = 4 };
 
 template <typename T> CGKS_HD T dev_erfc(T x);
 template <> CGKS_HD __forceinline__ double dev_erfc<double>(double x) { return erfc(x); }
@@ -726,21 +730,24 @@ CGKS_HD __forceinline__ void ao_poly(const T* d, const Cascade& cs, const Consts
                (T(9) * q3 * q3 + T(16) * q2 * q4) * T(1.0 / 80) + T(16) * q4 * q4 * T(1.0 / 448) + T(4) * q2 * q2 +
                (T(36) * q3 * q3 + T(48) * q2 * q4) * T(1.0 / 12) + T(144) * q4 * q4 * T(1.0 / 80) + T(36) * q3 * q3 +
                T(48) * q4 * q4 + T(576) * q4 * q4;
-  // the DFF scaling of a member scales its indicator by alpha^2
+  // the DFF scaling of a member scales its indicator by alpha^2 (the
+  // alternative reading takes the indicators of the unscaled members)
   const T al0 = T(cs.al[0]), al1 = T(cs.al[1]), al2 = T(cs.al[2]), al3 = T(cs.al[3]);
-  const T B0 = al0 * al0 * b0, B1 = al1 * al1 * b1, B2 = al2 * al2 * b2, B3 = al3 * al3 * b3;
-  const T g3 = T(C.ghi), g0 = T((1.0 - C.ghi) * (1.0 - C.glo) / 2.0), g2 = T((1.0 - C.ghi) * C.glo);
+  const bool unscaled = (C.rflags & RF_A5_UNSCALED_BETA) != 0;
+  const T B0 = unscaled ? b0 : al0 * al0 * b0, B1 = unscaled ? b1 : al1 * al1 * b1;
+  const T B2 = unscaled ? b2 : al2 * al2 * b2, B3 = unscaled ? b3 : al3 * al3 * b3;
+  const T g3 = T(C.ghi), g0 = T(C.gw[0]), g1 = T(C.gw[1]), g2 = T(C.gw[2]);
   const T tz = (fabs(B3 - B0) + fabs(B3 - B1) + fabs(B3 - B2)) * T(1.0 / 3);
   const T eps = T(C.eps);
   T r;
   r = tz * dev_rcp<T>(B0 + eps); const T w0 = g0 * (T(1) + r * r);
-  r = tz * dev_rcp<T>(B1 + eps); const T w1 = g0 * (T(1) + r * r);
+  r = tz * dev_rcp<T>(B1 + eps); const T w1 = g1 * (T(1) + r * r);
   r = tz * dev_rcp<T>(B2 + eps); const T w2 = g2 * (T(1) + r * r);
   r = tz * dev_rcp<T>(B3 + eps); const T w3 = g3 * (T(1) + r * r);
   const T ws = dev_rcp<T>(w0 + w1 + w2 + w3);
   const T o0 = w0 * ws, o1 = w1 * ws, o2 = w2 * ws, o3 = w3 * ws;
   const T k3 = o3 * T(1.0 / C.ghi);
-  const T k0 = (o0 - k3 * g0) * al0, k1 = (o1 - k3 * g0) * al1, k2 = (o2 - k3 * g2) * al2, kk3 = k3 * al3;
+  const T k0 = (o0 - k3 * g0) * al0, k1 = (o1 - k3 * g1) * al1, k2 = (o2 - k3 * g2) * al2, kk3 = k3 * al3;
   P[0] = d[2] * (T(1) - k0 - k1 - k2 - kk3) + k0 * c0[0] + k1 * c1[0] + k2 * c2[0] + kk3 * c3[0];
   P[1] = k0 * c0[1] + k1 * c1[1] + k2 * c2[1] + kk3 * c3[1];
   P[2] = k0 * c0[2] + k1 * c1[2] + k2 * c2[2] + kk3 * c3[2];

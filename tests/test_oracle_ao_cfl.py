@@ -40,14 +40,17 @@ def _mirror_poly(c):
 
 
 @pytest.mark.parametrize("seed", range(6))
-def test_ao_reconstruction_is_mirror_symmetric(seed):
+@pytest.mark.parametrize("flags", [0, 2])
+def test_ao_reconstruction_is_mirror_symmetric(seed, flags):
     """Reconstructing mirrored data gives the mirrored polynomial (Eq. 3.11-3.17,
     3.19 with the AO branch taken).  The sub-stencils S0 = {i-1, i} and
     S1 = {i, i+1} are mirror images of each other, so their linear weights
     must be equal; the central S2 and the fifth-order member map to
-    themselves."""
+    themselves.  Indicators of the unscaled members (an alternative reading)
+    keep the symmetry; gamma_1 taking the gamma_Lo share (the other) breaks
+    it, test_gamma1_reading_is_not_mirror_symmetric."""
     rng = np.random.default_rng(100 + seed)
-    sch = W.default_scheme(5)
+    sch = dict(W.default_scheme(5), reading_flags=flags)
     q = rng.normal(size=5)
     hq = rng.normal(size=5)
     sig = rng.uniform(0.0, 0.8, size=6)
@@ -58,6 +61,25 @@ def test_ao_reconstruction_is_mirror_symmetric(seed):
     assert brm == 0
     scale = np.abs(c).max()
     assert np.abs(cm - _mirror_poly(c)).max() <= 1e-13 * scale, (cm, _mirror_poly(c))
+
+
+def test_gamma1_reading_is_not_mirror_symmetric():
+    """With gamma_1 = (1 - gamma_Hi) gamma_Lo (the printed form of Eq. 3.12
+    completed to sum to one) the mirror images S0 and S1 carry different
+    linear weights, so mirrored data no longer give the mirrored polynomial:
+    the reason the default reading gives the gamma_Lo share to S2."""
+    rng = np.random.default_rng(100)
+    sch = dict(W.default_scheme(5), reading_flags=1)
+    worst = 0.0
+    for _ in range(6):
+        q, hq = rng.normal(size=5), rng.normal(size=5)
+        sig = rng.uniform(0.0, 0.8, size=6)
+        sig[2] += 0.6
+        c, br = oracle.recon_poly(sch, q, hq, sig)
+        cm, _ = oracle.recon_poly(sch, *_mirror_data(q, hq, sig))
+        assert br == 0
+        worst = max(worst, np.abs(cm - _mirror_poly(c)).max() / np.abs(c).max())
+    assert worst > 1e-3
 
 
 def _riemann(left, right, n, order, nsteps):
@@ -132,7 +154,8 @@ def test_ao_weights_pick_the_smooth_substencil_at_a_jump(jump_right):
     assert devs[2] < 1e-4
 
 
-def test_weno_z_weights_worked_example():
+@pytest.mark.parametrize("flags", [0, 1, 2, 3])
+def test_weno_z_weights_worked_example(flags):
     """Linear data q_j = j, h Q_x = 1 (the cell's polynomial is xi for every
     member, by polynomial exactness), with the strength 0.6 on the face +3/2
     only.  Then, by Eq. 3.3-3.4 with the face weights of A7:
@@ -144,8 +167,12 @@ def test_weno_z_weights_worked_example():
       gamma = (0.03, 0.03, 0.09, 0.85) for gamma_Hi = 0.85, gamma_Lo = 0.6 (Eq. 3.12, A3);
       omega_k = gamma_k (1 + tau_Z^2 / (beta_k + eps)^2), normalised (Eq. 3.14, 3.16);
     and the AO polynomial (Eq. 3.17) is s xi with
-      s = w3 / g3 (alpha_3 - sum_{k<3} g_k alpha_k) + sum_{k<3} w_k alpha_k."""
-    sch = W.default_scheme(5)
+      s = w3 / g3 (alpha_3 - sum_{k<3} g_k alpha_k) + sum_{k<3} w_k alpha_k.
+    The alternative readings change one input each: gamma_1 taking the
+    gamma_Lo share gives gamma = (0.03, 0.09, 0.03, 0.85); indicators of the
+    unscaled members are all 1, so tau_Z = 0, the weights stay linear and
+    s = alpha_3 = 5/6 whatever the linear weights."""
+    sch = dict(W.default_scheme(5), reading_flags=flags)
     q = np.arange(-2, 3, dtype=np.float64)
     hq = np.ones(5)
     sig = np.zeros(6)
@@ -164,12 +191,15 @@ def test_weno_z_weights_worked_example():
         return w[3] / g[3] * (alpha[3] - sum(g[k] * alpha[k] for k in range(3))) + \
             sum(w[k] * alpha[k] for k in range(3))
 
-    g = [0.03, 0.03, 0.09, 0.85]
-    s = slope(g, tau_z, beta)
+    g = [0.03, 0.09, 0.03, 0.85] if flags & 1 else [0.03, 0.03, 0.09, 0.85]
+    s = 5.0 / 6.0 if flags & 2 else slope(g, tau_z, beta)
     c, br = oracle.recon_poly(sch, q, hq, sig)
     assert br == 0
     assert abs(c[0]) < 1e-15 and np.abs(c[2:]).max() < 1e-14
     assert c[1] == pytest.approx(s, rel=1e-14, abs=0.0)
+    if flags:
+        return
+    g = [0.03, 0.03, 0.09, 0.85]
     # the example tells the reading apart from plausible slips, each of which
     # moves the slope by far more than the tolerance above: tau_Z without its
     # 1/3; S2 taking the (1 - gamma_Lo) share; indicators of the unscaled

@@ -213,3 +213,25 @@ def test_cfl_half_is_stable_2d(order, n, steps):
     assert r["status"] == 0 and r["stats"]["steps"] == steps
     assert np.abs(r["sx"]).max() < 2.0 * np.abs(pb["state"]["sx"]).max()
     assert abs(r["avg"][0].mean() - pb["state"]["avg"][0].mean()) < 1e-13
+
+
+def test_zero_initial_strengths_reading():
+    """Strengths of the step before the first set to zero (an alternative
+    reading of Eq. 3.2 at t = 0): every DFF of the first step is 1 (Eq. 3.3,
+    A = 0), so both stages of that step take the full-order linear stencil
+    everywhere (Algorithm 1), where the default reading (strengths of the
+    initial piecewise-constant data) sends the cells beside the jump to
+    AO(5,3).  From the second step on the strengths come from the first
+    step's fluxes and the run equals one started from explicit zero strengths."""
+    n = 100
+    pb = W.shock_tube("sod", n, 9)
+    r0 = oracle.run(pb, nsteps=1, t_end=0.0)
+    assert r0["stats"]["ao"] > 0
+    pb4 = dict(pb, scheme=dict(pb["scheme"], reading_flags=4))
+    r = oracle.run(pb4, nsteps=1, t_end=0.0)
+    assert r["status"] == 0
+    assert r["stats"]["ao"] == r["stats"]["linear5"] == r["stats"]["linear7"] == 0
+    assert r["stats"]["linear9"] == 2 * (n + 2)
+    a = oracle.run(pb4, nsteps=3, t_end=0.0)
+    b = oracle.run(pb, nsteps=3, t_end=0.0, sigma=(np.zeros(n + 1), np.zeros(1)))
+    assert np.array_equal(a["avg"], b["avg"]) and a["t"] == b["t"]
