@@ -44,15 +44,19 @@ ALGO_FLOP_PER_GP = 3100
 # step) of a design where each stage reads and writes the state once, stage 1
 # writes an accumulator that stage 2 reads, and the strengths are read and
 # written per face: 6 S + 6 words with S = 4 + 8 m state words per cell
-# (1776 B at order 9 in FP64; 984 B when only the averages stay FP64).
-# 1-D: 6 S + 3 words with S = 6 (312 B FP64, 228 B with FP32 slopes).
-ALGO_BYTES_2D = {"fp64": 1776, "fp32_flux": 984}
-ALGO_BYTES_1D = {"fp64": 312, "fp32_flux": 228}
-# Compulsory HBM bytes of one face launch of this design per cell (FP64
-# words, m = 4): stage input (avg 4 + normal slopes 16 + line values 16),
-# partial averages and accumulator (4 + 4 + 4 + 4), normal slopes of the
-# stage state and accumulator (16 + 16): 84 words.
-FACE_BYTES_PER_CELL = 84 * 8
+# (1776 B at order 9 in FP64).  The FP32-flux variant stores the slopes
+# (state, stage state, accumulator) in FP32 and keeps the averages and the
+# strengths in FP64: S = 4 x 8 + 32 x 4 = 160 B, 6 S + 6 x 8 = 1008 B.
+# 1-D: 6 S + 3 words with S = 6 words (312 B FP64; FP32 slopes 3 x 8 + 3 x 4
+# = 36 B, 6 S + 3 x 8 = 240 B).
+ALGO_BYTES_2D = {"fp64": 1776, "fp32_flux": 1008}
+ALGO_BYTES_1D = {"fp64": 312, "fp32_flux": 240}
+# Compulsory HBM bytes of one face launch of this design per cell (m = 4):
+# stage input (avg 4 + normal slopes 16 + line values 16), partial averages
+# and accumulator (4 + 4 + 4 + 4), normal slopes of the stage state and
+# accumulator (16 + 16): 84 words, 672 B in FP64; with the slopes and line
+# values in FP32, 20 FP64 + 64 FP32 words = 416 B.
+FACE_BYTES_PER_CELL = {"fp64": 84 * 8, "fp32_flux": 20 * 8 + 64 * 4}
 
 
 def parse():
@@ -435,8 +439,8 @@ def main():
                # the FP32 peak counts packed FP32 instructions, which this
                # library does not emit; unpacked, FP32 issues at the FP64 rate
                "peak_unpacked": PEAK["fp64_alu"], "frac_unpacked": ach / PEAK["fp64_alu"],
-               "hbm_launch": {"algorithmic_bytes": FACE_BYTES_PER_CELL * cells,
-                              "frac_algorithmic": FACE_BYTES_PER_CELL * cells / (ms * 1e-3) / 1e9 / PEAK["hbm"],
+               "hbm_launch": {"algorithmic_bytes": FACE_BYTES_PER_CELL[prec] * cells,
+                              "frac_algorithmic": FACE_BYTES_PER_CELL[prec] * cells / (ms * 1e-3) / 1e9 / PEAK["hbm"],
                               "frac_measured": (traffic / (ms * 1e-3) / 1e9 / PEAK["hbm"]) if traffic else None},
                "hbm_step": hbm_step}
         if counted:

@@ -106,7 +106,9 @@ typedef struct {
  * linear weights of the AO(5,3) reconstruction; weno_eps: its epsilon.
  * precision: CGKS_FP64, or CGKS_FP32_FLUX (reconstruction and flux moments in
  * FP32; cell-average accumulation, conservation sums and the exponential
- * time coefficients in FP64). */
+ * time coefficients in FP64; the device copies of the slopes, of the stage
+ * state's and accumulator's slopes and of the Step 1 line values are stored
+ * in FP32, the cell averages and interface strengths in FP64). */
 typedef struct {
   int order;
   double gamma;
@@ -159,7 +161,9 @@ typedef struct {
 cgks_status cgks_plan_create(const cgks_grid_desc* grid, const cgks_scheme_desc* scheme, cgks_plan** out);
 
 /* Bytes of the caller-owned device buffers.  d_state holds the conserved
- * cell averages and slopes with a ghost halo; d_work holds the stage state,
+ * cell averages (FP64) and slopes (FP64, or FP32 under CGKS_FP32_FLUX) with a
+ * ghost halo, in a layout private to the library: cgks_init_state and
+ * cgks_read_state convert from and to the FP64 host layouts; d_work holds the stage state,
  * the stage accumulator, the interface strengths (Eq. 3.1), reconstruction
  * intermediates, and a 256-byte header (time, step, dt, counters). */
 cgks_status cgks_plan_sizes(const cgks_plan* plan, size_t* state_bytes, size_t* work_bytes);

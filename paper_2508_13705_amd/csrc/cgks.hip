@@ -48,11 +48,12 @@ __global__ void k_init_sigma(Geo g, int which, double gam, const double* U, doub
   }
 }
 
-// code: the time the ghosts are for (bc_time)
+// code: the time the ghosts are for (bc_time); ST: slope storage type
+template <typename ST>
 __global__ void k_bc_state(Geo g, const BcTable* T, const Header* hdr, int code, double* U) {
   int I, Jr;
   GhostItems(g).at(g, blockIdx.x, I, Jr);
-  bc_state_at(g, T, bc_time(hdr, code), U, I, Jr);
+  bc_state_at<ST>(g, T, bc_time(hdr, code), U, I, Jr);
 }
 
 __global__ void k_bc_sigma(Geo g, const BcTable* T, const Header* hdr, int which, const double* sxn, double* sxo,
@@ -75,13 +76,13 @@ __device__ __forceinline__ int xcd_block(int b, int n) {
   return (x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q) + k;
 }
 
-template <int M>
+template <int M, typename ST>
 __global__ __launch_bounds__(256) void k_lines(Geo g, Consts C, const double* U, const double* sxo,
                                                const double* syo, double* lvx, double* lvy, Header* hdr) {
   __shared__ double sm[LinesLds<0>::total];
   if (!hdr->active) return;
   const int lb = xcd_block(blockIdx.y * gridDim.x + blockIdx.x, gridDim.x * gridDim.y);
-  lines_tile<M>(g, C, U, sxo, syo, lvx, lvy, hdr, lb % gridDim.x, lb / gridDim.x, sm);
+  lines_tile<M, ST>(g, C, U, sxo, syo, lvx, lvy, hdr, lb % gridDim.x, lb / gridDim.x, sm);
 }
 
 // Grid (tiles along the normal, tiles along the tangential).  x-face tiles
@@ -150,7 +151,8 @@ hipError_t launch_bc_state(const cgks_plan* p, const Bufs& b, double* U, int cod
                            Marks* mk = nullptr) {
   const Geo& g = p->g;
   const dim3 grid(GhostItems(g).count(g));   // the segments that hold ghost cells
-  hipLaunchKernelGGL(k_bc_state, grid, dim3(256), 0, st, g, b.bct, b.hdr, code, U);
+  if (p->precision == CGKS_FP64) hipLaunchKernelGGL(k_bc_state<double>, grid, dim3(256), 0, st, g, b.bct, b.hdr, code, U);
+  else hipLaunchKernelGGL(k_bc_state<float>, grid, dim3(256), 0, st, g, b.bct, b.hdr, code, U);
   tick(mk, st);
   return hipGetLastError();
 }
@@ -174,7 +176,7 @@ hipError_t launch_stage2d(const cgks_plan* p, const Bufs& b, int stage, hipStrea
   const double* Uin = stage == 1 ? b.U : b.S;
   {
     dim3 grid((g.NX + LT_X - 1) / LT_X, (g.NY + LT_Y - 1) / LT_Y);
-    hipLaunchKernelGGL(k_lines<M>, grid, dim3(256), 0, st, g, p->C, Uin, b.sxo, b.syo, b.lvx, b.lvy, b.hdr);
+    hipLaunchKernelGGL((k_lines<M, T>), grid, dim3(256), 0, st, g, p->C, Uin, b.sxo, b.syo, b.lvx, b.lvy, b.hdr);
     tick(mk, st);
   }
   const size_t lds = Lds<M, T>::total;
@@ -257,7 +259,7 @@ cgks_status prepare_faces_pr() {
   if ((s = prepare_face<1, 1, M, T, PR>()) != CGKS_OK) return s;
   if ((s = prepare_face<0, 2, M, T, PR>()) != CGKS_OK) return s;
   if ((s = prepare_face<1, 2, M, T, PR>()) != CGKS_OK) return s;
-  return check_private((const void*)k_lines<M>, 0, "line kernel");
+  return check_private((const void*)k_lines<M, T>, 0, "line kernel");
 }
 
 template <int M, typename T>
@@ -430,7 +432,10 @@ cgks_status cgks_plan_create(const cgks_grid_desc* gd, const cgks_scheme_desc* s
   C.m = gd->dim == 2 ? g.m : 1;
   p->precision = sd->precision;
   const size_t nv = g.nv, m = g.m, cells = g.cells;
-  p->state_words = nv * cells * (g.dim == 2 ? 1 + 2 * m : 2);
+  // averages in double, slopes and line values in the working precision
+  const size_t esz = sd->precision == CGKS_FP64 ? sizeof(double) : sizeof(float);
+  auto words = [](size_t bytes) { return (bytes + sizeof(double) - 1) / sizeof(double); };
+  p->state_words = g.avg_words() + words(g.slope_elems() * esz);
   p->sig_x_words = (size_t)g.NY * (g.NX + 1);
   p->sig_y_words = g.dim == 2 ? (size_t)g.NX * (g.NY + 1) : 0;
   auto up = [](size_t w) { return (w + 31) & ~(size_t)31; };  // 256-byte aligned sections
@@ -441,8 +446,8 @@ cgks_status cgks_plan_create(const cgks_grid_desc* gd, const cgks_scheme_desc* s
   p->off_sxn = o; o += up(p->sig_x_words);
   p->off_syo = o; o += up(p->sig_y_words);
   p->off_syn = o; o += up(p->sig_y_words);
-  p->off_lvx = o; o += g.dim == 2 ? up(nv * m * cells) : 0;
-  p->off_lvy = o; o += g.dim == 2 ? up(nv * m * cells) : 0;
+  p->off_lvx = o; o += g.dim == 2 ? up(words(nv * m * cells * esz)) : 0;
+  p->off_lvy = o; o += g.dim == 2 ? up(words(nv * m * cells * esz)) : 0;
   {
     // partials: the initial reduction grid, the 1-D stage grid, the 2-D y-face grid
     size_t a = (size_t)((g.nx + 255) / 256) * (g.dim == 2 ? g.ny : 1);
@@ -505,13 +510,19 @@ cgks_status cgks_init_state(const cgks_plan* p, void* d_state, void* d_work, con
   } catch (...) {
     return fail(CGKS_ENOMEM, "staging buffer");
   }
+  // slopes in the storage type of the plan (rounded to float in the FP32-flux variant)
+  const bool f64 = p->precision == CGKS_FP64;
+  auto put_slope = [&](size_t k, double val) {
+    if (f64) slopes<double>(hs.data(), g)[k] = val;
+    else slopes<float>(hs.data(), g)[k] = (float)val;
+  };
   for (int v = 0; v < nv; ++v)
     for (int j = 0; j < ny; ++j)
       for (int i = 0; i < nx; ++i) {
         hs[g.avg(v, i, j)] = h_avg[((size_t)v * ny + j) * nx + i];
         for (int l = 0; l < m; ++l) {
-          hs[g.sx(v, l, i, j)] = h_slope_x[(((size_t)v * m + l) * ny + j) * nx + i];
-          if (g.dim == 2) hs[g.sy(v, l, i, j)] = h_slope_y[(((size_t)v * m + l) * ny + j) * nx + i];
+          put_slope(g.sx(v, l, i, j), h_slope_x[(((size_t)v * m + l) * ny + j) * nx + i]);
+          if (g.dim == 2) put_slope(g.sy(v, l, i, j), h_slope_y[(((size_t)v * m + l) * ny + j) * nx + i]);
         }
       }
   Bufs b = bufs(p, d_state, d_work);
@@ -611,21 +622,25 @@ cgks_status cgks_read_state(const cgks_plan* p, const void* d_state, const void*
   HIP_TRY(hipStreamSynchronize(st));
   if (hh.magic != kMagic) return fail(CGKS_ESTATE, "work buffer was not initialised by cgks_init_state");
   const int nx = g.nx, ny = g.ny, m = g.m, nv = g.nv;
+  const bool f64 = p->precision == CGKS_FP64;
+  auto slope = [&](size_t k) -> double {
+    return f64 ? slopes<double>(hs.data(), g)[k] : (double)slopes<float>(hs.data(), g)[k];
+  };
   for (int v = 0; v < nv; ++v)
     for (int j = 0; j < ny; ++j)
       for (int i = 0; i < nx; ++i) {
         if (h_avg) h_avg[((size_t)v * ny + j) * nx + i] = hs[g.avg(v, i, j)];
         for (int l = 0; l < m; ++l) {
-          if (h_slope_x) h_slope_x[(((size_t)v * m + l) * ny + j) * nx + i] = hs[g.sx(v, l, i, j)];
-          if (g.dim == 2 && h_slope_y) h_slope_y[(((size_t)v * m + l) * ny + j) * nx + i] = hs[g.sy(v, l, i, j)];
+          if (h_slope_x) h_slope_x[(((size_t)v * m + l) * ny + j) * nx + i] = slope(g.sx(v, l, i, j));
+          if (g.dim == 2 && h_slope_y) h_slope_y[(((size_t)v * m + l) * ny + j) * nx + i] = slope(g.sy(v, l, i, j));
         }
         // cell-averaged gradients: Gauss-weighted means of the line slopes
         // (1-D: the stored slope itself)
         double gxs = 0.0, gys = 0.0;
         for (int l = 0; l < m; ++l) {
           const double w = g.dim == 2 ? kGw[m][l] : 1.0;
-          gxs += w * hs[g.sx(v, l, i, j)];
-          if (g.dim == 2) gys += w * hs[g.sy(v, l, i, j)];
+          gxs += w * slope(g.sx(v, l, i, j));
+          if (g.dim == 2) gys += w * slope(g.sy(v, l, i, j));
         }
         if (h_grad_x) h_grad_x[((size_t)v * ny + j) * nx + i] = gxs;
         if (h_grad_y && g.dim == 2) h_grad_y[((size_t)v * ny + j) * nx + i] = gys;

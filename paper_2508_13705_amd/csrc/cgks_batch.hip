@@ -65,7 +65,10 @@ __device__ __forceinline__ int find_job(P pre, int n, int item) {
 // Persistent loop over the items of a phase.  With remap, blocks that the
 // dispatcher places on one XCD (block b runs on XCD b mod 8) take
 // consecutive items, so neighbouring tiles of a grid share that XCD's L2.
-template <class F>
+// CREF: read the job descriptor in place through a constant pointer (the
+// default), or copy it (the FP64 face kernels, whose registers are full:
+// there the in-place reads cost scratch).
+template <bool CREF = true, class F>
 __device__ __forceinline__ void for_items(const BTab* tab, int ph, int remap, F&& f) {
   const int total = tab->total[ph];
   const int G = gridDim.x;
@@ -80,14 +83,24 @@ __device__ __forceinline__ void for_items(const BTab* tab, int ph, int remap, F&
     const int j = __builtin_amdgcn_readfirstlane(find_job(pre, n, item));
     const int k = __builtin_amdgcn_readfirstlane(item - pre[j]);
 #if defined(__HIP_DEVICE_COMPILE__)
-    // read through a pointer of global type: scalar loads (through the generic
-    // table pointer they would be FLAT loads, which count against the LDS
-    // counter)
-    const BJob J = glb((const BJob*)tab->jobs)[j];
+    // read through a pointer of constant type: the table does not change
+    // while a kernel runs, so its fields are scalar loads that the compiler
+    // may repeat where they are used, as it does with kernel arguments,
+    // instead of holding the whole descriptor in registers across the tile
+    // (through the generic table pointer they would be FLAT loads, which
+    // count against the LDS counter)
+    using cjob = const __attribute__((address_space(4))) BJob*;
+    if (CREF) {
+      f(*(const BJob*)((cjob)tab->jobs + j), k);
+    } else {
+      // through a pointer of global type: scalar loads
+      const BJob J = glb((const BJob*)tab->jobs)[j];
+      f(J, k);
+    }
 #else
     const BJob& J = tab->jobs[j];
-#endif
     f(J, k);
+#endif
   }
 }
 
@@ -100,7 +113,9 @@ __global__ __launch_bounds__(256) void kb_dt(const BTab* tab) {
   }
 }
 
-// Strength commit and ghost faces (both directions), then ghost cells of W^n.
+// Strength commit and ghost faces (both directions), then ghost cells of W^n
+// (ST: slope storage type of the batch's precision).
+template <typename ST>
 __global__ __launch_bounds__(256) void kb_prep(const BTab* tab, int remap) {
   for_items(tab, PH_PREP, remap, [&](const BJob& J, int k) {
     if (!J.B.hdr->active) return;
@@ -118,22 +133,23 @@ __global__ __launch_bounds__(256) void kb_prep(const BTab* tab, int remap) {
     k -= J.nsy;
     int I, Jr;
     GhostItems(J.g).at(J.g, k, I, Jr);
-    bc_state_at(J.g, J.B.bct, bc_time(J.B.hdr, 1), J.B.U, I, Jr);
+    bc_state_at<ST>(J.g, J.B.bct, bc_time(J.B.hdr, 1), J.B.U, I, Jr);
   });
 }
 
 // Ghost cells of the stage state W*.
+template <typename ST>
 __global__ __launch_bounds__(256) void kb_bcs(const BTab* tab, int remap) {
   for_items(tab, PH_BCS, remap, [&](const BJob& J, int k) {
     if (!J.B.hdr->active) return;
     int I, Jr;
     GhostItems(J.g).at(J.g, k, I, Jr);
-    bc_state_at(J.g, J.B.bct, bc_time(J.B.hdr, 2), J.B.S, I, Jr);
+    bc_state_at<ST>(J.g, J.B.bct, bc_time(J.B.hdr, 2), J.B.S, I, Jr);
   });
 }
 
 // Step 1 line values of the stage input (2-D), one tile of shape LW per item.
-template <int LW>
+template <int LW, typename ST>
 __global__ __launch_bounds__(256) void kb_lines(const BTab* tab, int stage, int remap) {
   __shared__ double sm[LinesLds<LW>::total];
   for_items(tab, PH_LINES, remap, [&](const BJob& J, int k) {
@@ -141,9 +157,9 @@ __global__ __launch_bounds__(256) void kb_lines(const BTab* tab, int stage, int 
     const double* Uin = stage == 1 ? J.B.U : J.B.S;
     const int bx = k % J.ltx, by = k / J.ltx;
     switch (J.M) {
-      case 2: lines_tile<2, true, LW>(J.g, J.C, Uin, J.B.sxo, J.B.syo, J.B.lvx, J.B.lvy, J.B.hdr, bx, by, sm); break;
-      case 3: lines_tile<3, true, LW>(J.g, J.C, Uin, J.B.sxo, J.B.syo, J.B.lvx, J.B.lvy, J.B.hdr, bx, by, sm); break;
-      default: lines_tile<4, true, LW>(J.g, J.C, Uin, J.B.sxo, J.B.syo, J.B.lvx, J.B.lvy, J.B.hdr, bx, by, sm); break;
+      case 2: lines_tile<2, ST, true, LW>(J.g, J.C, Uin, J.B.sxo, J.B.syo, J.B.lvx, J.B.lvy, J.B.hdr, bx, by, sm); break;
+      case 3: lines_tile<3, ST, true, LW>(J.g, J.C, Uin, J.B.sxo, J.B.syo, J.B.lvx, J.B.lvy, J.B.hdr, bx, by, sm); break;
+      default: lines_tile<4, ST, true, LW>(J.g, J.C, Uin, J.B.sxo, J.B.syo, J.B.lvx, J.B.lvy, J.B.hdr, bx, by, sm); break;
     }
   });
 }
@@ -153,7 +169,7 @@ __global__ __launch_bounds__(256) void kb_lines(const BTab* tab, int stage, int 
 template <int DIR, int STAGE, typename T, int M, int V>
 __global__ __launch_bounds__(256, sizeof(T) == 4 ? 2 : 1) void kb_face(const BTab* tab, int remap) {
   extern __shared__ __align__(16) unsigned char smem[];
-  for_items(tab, ph_face(DIR, M), remap, [&](const BJob& J, int k) {
+  for_items<sizeof(T) == 4>(tab, ph_face(DIR, M), remap, [&](const BJob& J, int k) {
     const int nbx = J.fnb[DIR][0], nby = J.fnb[DIR][1];
     // neighbours along x first (x-faces: normal-first, y-faces: tangential-first)
     const int bx = DIR == 0 ? k % nbx : k / nby, by = DIR == 0 ? k / nbx : k % nby;
@@ -248,8 +264,8 @@ cgks_status prepare_batch() {
   if ((s = prepare_bshape<T, 0>()) != CGKS_OK) return s;
   if ((s = prepare_bshape<T, 1>()) != CGKS_OK) return s;
   if ((s = prepare_bshape<T, 2>()) != CGKS_OK) return s;
-  const void* k[] = {(const void*)kb_dt, (const void*)kb_prep, (const void*)kb_bcs, (const void*)kb_lines<0>,
-                     (const void*)kb_lines<1>, (const void*)kb_stage1d<1, T>, (const void*)kb_stage1d<2, T>};
+  const void* k[] = {(const void*)kb_dt, (const void*)kb_prep<T>, (const void*)kb_bcs<T>, (const void*)kb_lines<0, T>,
+                     (const void*)kb_lines<1, T>, (const void*)kb_stage1d<1, T>, (const void*)kb_stage1d<2, T>};
   for (const void* f : k)
     if ((s = check_private(f, 0, "batched kernel")) != CGKS_OK) return s;
   return CGKS_OK;
@@ -259,10 +275,10 @@ template <typename T>
 hipError_t occupancy(cgks_batch* b) {
   hipError_t e;
   if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&b->occ[K_DT], kb_dt, 256, 0))) return e;
-  if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&b->occ[K_PREP], kb_prep, 256, 0))) return e;
-  if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&b->occ[K_BCS], kb_bcs, 256, 0))) return e;
-  if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&b->occ_lines[0], kb_lines<0>, 256, 0))) return e;
-  if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&b->occ_lines[1], kb_lines<1>, 256, 0))) return e;
+  if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&b->occ[K_PREP], kb_prep<T>, 256, 0))) return e;
+  if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&b->occ[K_BCS], kb_bcs<T>, 256, 0))) return e;
+  if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&b->occ_lines[0], kb_lines<0, T>, 256, 0))) return e;
+  if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&b->occ_lines[1], kb_lines<1, T>, 256, 0))) return e;
   // the face grid serves every order: size it by the order that fits the
   // fewest blocks (the largest LDS tile)
   auto face_occ = [&](const void* f2, size_t l2, const void* f3, size_t l3, const void* f4, size_t l4, int* out) {
@@ -303,9 +319,10 @@ void launch_faces(int v, int gf, hipStream_t st, const BTab* t, int r) {
   }
 }
 
+template <typename T>
 void launch_lines(int lw, int gl, hipStream_t st, const BTab* t, int stage, int r) {
-  if (lw == 1) hipLaunchKernelGGL(kb_lines<1>, dim3(gl), dim3(256), 0, st, t, stage, r);
-  else hipLaunchKernelGGL(kb_lines<0>, dim3(gl), dim3(256), 0, st, t, stage, r);
+  if (lw == 1) hipLaunchKernelGGL((kb_lines<1, T>), dim3(gl), dim3(256), 0, st, t, stage, r);
+  else hipLaunchKernelGGL((kb_lines<0, T>), dim3(gl), dim3(256), 0, st, t, stage, r);
 }
 
 template <typename T>
@@ -313,10 +330,10 @@ hipError_t enqueue_batch_step(const cgks_batch* b, hipStream_t st) {
   const BTab* t = b->dtab;
   const int r = b->tune.xcd_remap ? 1 : 0;
   hipLaunchKernelGGL(kb_dt, dim3(b->grid[K_DT]), dim3(256), 0, st, t);
-  hipLaunchKernelGGL(kb_prep, dim3(b->grid[K_PREP]), dim3(256), 0, st, t, r);
+  hipLaunchKernelGGL(kb_prep<T>, dim3(b->grid[K_PREP]), dim3(256), 0, st, t, r);
   if (b->dim == 1) {
     hipLaunchKernelGGL((kb_stage1d<1, T>), dim3(b->grid[K_S1D]), dim3(256), 0, st, t, r);
-    hipLaunchKernelGGL(kb_bcs, dim3(b->grid[K_BCS]), dim3(256), 0, st, t, r);
+    hipLaunchKernelGGL(kb_bcs<T>, dim3(b->grid[K_BCS]), dim3(256), 0, st, t, r);
     hipLaunchKernelGGL((kb_stage1d<2, T>), dim3(b->grid[K_S1D]), dim3(256), 0, st, t, r);
     return hipGetLastError();
   }
@@ -324,11 +341,11 @@ hipError_t enqueue_batch_step(const cgks_batch* b, hipStream_t st) {
   const int v = b->tune.face_tile, lw = b->tune.line_tile;
   // every order is launched (a phase without jobs of that order ends at
   // once), so a captured step serves any later mix of orders
-  launch_lines(lw, gl, st, t, 1, r);
+  launch_lines<T>(lw, gl, st, t, 1, r);
   launch_faces<0, 1, T>(v, gf, st, t, r);
   launch_faces<1, 1, T>(v, gf, st, t, r);
-  hipLaunchKernelGGL(kb_bcs, dim3(b->grid[K_BCS]), dim3(256), 0, st, t, r);
-  launch_lines(lw, gl, st, t, 2, r);
+  hipLaunchKernelGGL(kb_bcs<T>, dim3(b->grid[K_BCS]), dim3(256), 0, st, t, r);
+  launch_lines<T>(lw, gl, st, t, 2, r);
   launch_faces<0, 2, T>(v, gf, st, t, r);
   launch_faces<1, 2, T>(v, gf, st, t, r);
   return hipGetLastError();

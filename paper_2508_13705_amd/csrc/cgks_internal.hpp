@@ -121,12 +121,19 @@ struct Geo {
     return (size_t)(dim == 2 ? j + H : 0) * NX + (i + H);
   }
   __host__ __device__ size_t avg(int v, int i, int j) const { return (size_t)v * cells + cell(i, j); }
+  // A state is nv planes of cell averages (double) followed by its slope
+  // planes: x-slopes [v][l], then (2-D) y-slopes [v][l].  The slopes are
+  // stored in the working precision of the plan (double, or float in the
+  // FP32-flux variant); sx and sy index them from the slope base
+  // (slopes<ST>(U, g)), not from the start of the state.
   __host__ __device__ size_t sx(int v, int l, int i, int j) const {
-    return (size_t)nv * cells + ((size_t)v * m + l) * cells + cell(i, j);
+    return ((size_t)v * m + l) * cells + cell(i, j);
   }
   __host__ __device__ size_t sy(int v, int l, int i, int j) const {
-    return (size_t)nv * cells + (size_t)nv * m * cells + ((size_t)v * m + l) * cells + cell(i, j);
+    return (size_t)nv * m * cells + ((size_t)v * m + l) * cells + cell(i, j);
   }
+  __host__ __device__ size_t avg_words() const { return (size_t)nv * cells; }
+  __host__ __device__ size_t slope_elems() const { return (size_t)nv * m * cells * (dim == 2 ? 2 : 1); }
   __host__ __device__ size_t lv(int v, int l, int i, int j) const { return ((size_t)v * m + l) * cells + cell(i, j); }
   __host__ __device__ size_t sgx(int j, int F) const { return (size_t)(dim == 2 ? j + H : 0) * (NX + 1) + F + H; }
   __host__ __device__ size_t sgy(int i, int G) const { return (size_t)(i + H) * (NY + 1) + G + H; }
@@ -140,7 +147,7 @@ struct Bufs {
   double* sxn;    // strengths computed in this step
   double* syo;
   double* syn;
-  double* lvx;
+  double* lvx;    // Step 1 line values (element type: the plan's working precision)
   double* lvy;
   double* part;   // per-block [max(|U|+c), min(rho)] of the last reduction
   Header* hdr;
@@ -157,6 +164,16 @@ using gptr = __attribute__((address_space(1))) T*;
 template <typename T>
 __device__ __forceinline__ gptr<T> glb(T* p) {
   return (gptr<T>)p;
+}
+
+// The slope planes of a state whose averages start at U (element type ST).
+template <typename ST>
+__host__ __device__ __forceinline__ ST* slopes(double* U, const Geo& g) {
+  return (ST*)(U + g.avg_words());
+}
+template <typename ST>
+__host__ __device__ __forceinline__ const ST* slopes(const double* U, const Geo& g) {
+  return (const ST*)(U + g.avg_words());
 }
 
 }  // namespace
@@ -284,6 +301,7 @@ struct GhostItems {
 // normal slope and reverse the order of the tangential line slopes; walls
 // add their momentum signs.  A prescribed state gives that state and zero
 // slopes.
+template <typename ST>
 __device__ __forceinline__ void bc_state_at(const Geo& g, const BcTable* T, double tb, double* U, int I, int J) {
   if (I >= g.NX) return;
   const int i = I - H, j = (g.dim == 2) ? J - H : 0;
@@ -301,23 +319,25 @@ __device__ __forceinline__ void bc_state_at(const Geo& g, const BcTable* T, doub
     if (kx != CGKS_BC_INFLOW) si = src_cell(i, g.nx, g.bc[0], g.bc[1], mx);
   }
   const bool fixed = ky == CGKS_BC_INFLOW || kx == CGKS_BC_INFLOW;
+  ST* S = slopes<ST>(U, g);
   for (int v = 0; v < g.nv; ++v) {
     const double odd = (mx ? wall_sign(kx, v, 1, g.dim) : 1.0) * (my ? wall_sign(ky, v, 2, g.dim) : 1.0);
     if (fixed) {   // a prescribed state, seen through a y-mirror when the x-side prescribes it
       U[g.avg(v, i, j)] = odd * cons[v];
       for (int l = 0; l < g.m; ++l) {
-        U[g.sx(v, l, i, j)] = 0.0;
-        if (g.dim == 2) U[g.sy(v, l, i, j)] = 0.0;
+        S[g.sx(v, l, i, j)] = ST(0);
+        if (g.dim == 2) S[g.sy(v, l, i, j)] = ST(0);
       }
       continue;
     }
     U[g.avg(v, i, j)] = odd * U[g.avg(v, si, sj)];
+    // the signs are +-1: the products are exact in either storage type
     for (int l = 0; l < g.m; ++l) {
       const int lx = my ? g.m - 1 - l : l;   // x-slope lines are horizontal: mirrored by a y-mirror
-      U[g.sx(v, l, i, j)] = (mx ? -odd : odd) * U[g.sx(v, lx, si, sj)];
+      S[g.sx(v, l, i, j)] = ST(mx ? -odd : odd) * S[g.sx(v, lx, si, sj)];
       if (g.dim == 2) {
         const int ly = mx ? g.m - 1 - l : l;
-        U[g.sy(v, l, i, j)] = (my ? -odd : odd) * U[g.sy(v, ly, si, sj)];
+        S[g.sy(v, l, i, j)] = ST(my ? -odd : odd) * S[g.sy(v, ly, si, sj)];
       }
     }
   }
@@ -664,7 +684,9 @@ constexpr int LT_X = LinesLds<0>::X, LT_Y = LinesLds<0>::Y;   // the single-grid
 inline int line_tile_x(int lw) { return lw == 0 ? 32 : 16; }
 inline int line_tile_y(int lw) { return lw == 0 ? 8 : 16; }
 
-template <int M, bool PERSIST = false, int LW = 0>
+// ST: storage type of the slopes and line values (the plan's working
+// precision); the arithmetic is double in both variants.
+template <int M, typename ST, bool PERSIST = false, int LW = 0>
 __device__ __forceinline__ void lines_tile(const Geo& g, const Consts& C, const double* U, const double* sxo,
                                            const double* syo, double* lvx, double* lvy, Header* hdr, int bx,
                                            int by, double* sm) {
@@ -672,7 +694,8 @@ __device__ __forceinline__ void lines_tile(const Geo& g, const Consts& C, const 
   constexpr int LT_X = L::X, LT_Y = L::Y;
   __shared__ Tally tally;
   const gptr<const double> Ug = glb(U), sxg = glb(sxo), syg = glb(syo);
-  const gptr<double> lvxg = glb(lvx), lvyg = glb(lvy);
+  const gptr<const ST> Sl = glb(slopes<ST>(U, g));
+  const gptr<ST> lvxg = glb((ST*)lvx), lvyg = glb((ST*)lvy);
   double* avg = sm;
   double* gy = avg + L::NAVG;
   double* gx = gy + L::NGY;
@@ -713,7 +736,7 @@ __device__ __forceinline__ void lines_tile(const Geo& g, const Consts& C, const 
       const int v = k / (L::BY * LT_X), xx = k % LT_X, yy = (k / LT_X) % L::BY;
       const int i = ci(i0 + xx), j = cj(j0 - 2 + yy);
 #pragma unroll
-      for (int l = 0; l < M; ++l) ra[p][l] = Ug[g.sy(v, l, i, j)];
+      for (int l = 0; l < M; ++l) ra[p][l] = double(Sl[g.sy(v, l, i, j)]);
     }
 #pragma unroll
     for (int p = 0; p < PGY; ++p) {
@@ -732,7 +755,7 @@ __device__ __forceinline__ void lines_tile(const Geo& g, const Consts& C, const 
       const int v = k / (LT_Y * L::BX), xx = k % L::BX, yy = (k / L::BX) % LT_Y;
       const int i = ci(i0 - 2 + xx), j = cj(j0 + yy);
 #pragma unroll
-      for (int l = 0; l < M; ++l) ra[p][l] = Ug[g.sx(v, l, i, j)];
+      for (int l = 0; l < M; ++l) ra[p][l] = double(Sl[g.sx(v, l, i, j)]);
     }
 #pragma unroll
     for (int p = 0; p < PSY; ++p) {   // faces contiguous in memory along gg
@@ -792,7 +815,7 @@ __device__ __forceinline__ void lines_tile(const Geo& g, const Consts& C, const 
 #pragma unroll
     for (int l = 0; l < M; ++l)
 #pragma unroll
-      for (int v = 0; v < 4; ++v) lvxg[g.lv(v, l, i, j)] = out[l][v];
+      for (int v = 0; v < 4; ++v) lvxg[g.lv(v, l, i, j)] = ST(out[l][v]);
   }
   // y-face line values: row j, columns i-2..i+2, needed for i in [-1, nx]
   if (i >= -1 && i <= g.nx && j <= g.ny + 2) {
@@ -817,7 +840,7 @@ __device__ __forceinline__ void lines_tile(const Geo& g, const Consts& C, const 
 #pragma unroll
     for (int l = 0; l < M; ++l)
 #pragma unroll
-      for (int v = 0; v < 4; ++v) lvyg[g.lv(v, l, i, j)] = out[l][v];
+      for (int v = 0; v < 4; ++v) lvyg[g.lv(v, l, i, j)] = ST(out[l][v]);
   }
   tally_add(tally, interior, brx, tiex, C.order, tid);
   tally_add(tally, interior, bry, tiey, C.order, tid);
@@ -969,16 +992,15 @@ __device__ void face2d_tile(const Geo& g, const Consts& C, const Bufs& B, unsign
   const int T0 = by * NT;
   const double hn = DIR == 0 ? C.dx : C.dy, ht = DIR == 0 ? C.dy : C.dx;
   const gptr<const double> Uin = glb((const double*)(STAGE == 1 ? B.U : B.S));
-  const gptr<const double> LV = glb((const double*)(DIR == 0 ? B.lvx : B.lvy));
+  const gptr<const T> LV = glb((const T*)(DIR == 0 ? B.lvx : B.lvy));
   const gptr<const double> sgN = glb((const double*)(DIR == 0 ? B.sxo : B.syo));   // normal-face strengths
   const gptr<const double> sgT = glb((const double*)(DIR == 0 ? B.syo : B.sxo));   // tangential-face strengths
   const gptr<double> Ug = glb(B.U), Sg = glb(B.S), Ag = glb(B.A);
+  // slope planes of the state, stage state and accumulator (element type T)
+  const gptr<T> UgS = glb(slopes<T>(B.U, g)), SgS = glb(slopes<T>(B.S, g)), AgS = glb(slopes<T>(B.A, g));
   const int gcomp[4] = {0, DIR == 0 ? 1 : 2, DIR == 0 ? 2 : 1, 3};
   auto gi = [&](int n, int t) { return DIR == 0 ? n : t; };
   auto gj = [&](int n, int t) { return DIR == 0 ? t : n; };
-  auto sN = [&](int v, int l, int n, int t) {  // normal slope on line l
-    return DIR == 0 ? g.sx(v, l, gi(n, t), gj(n, t)) : g.sy(v, l, gi(n, t), gj(n, t));
-  };
   auto sgn_idx = [&](int t, int face) { return DIR == 0 ? g.sgx(t, face) : g.sgy(t, face); };
   auto sgt_idx = [&](int n, int face) { return DIR == 0 ? g.sgy(n, face) : g.sgx(n, face); };
 
@@ -1004,13 +1026,15 @@ __device__ void face2d_tile(const Geo& g, const Consts& C, const Bufs& B, unsign
     const bool slot = tid < PPP * PL;
     const int n = clampi(F0 - 3 + cc, -H, nmax + H - 1), t = clampi(T0 - 1 + r, -H, tmax + H - 1);
     const size_t cell = g.cell(gi(n, t), gj(n, t));
-    const gptr<const double> slope = Uin + (size_t)g.nv * g.cells + (DIR == 0 ? 0 : (size_t)g.nv * g.m * g.cells);
+    const T hnT = T(hn);   // the slopes are staged h-scaled
+    const gptr<const T> slope = glb(slopes<T>((const double*)(STAGE == 1 ? B.U : B.S), g)) +
+                                (DIR == 0 ? 0 : (size_t)g.nv * g.m * g.cells);
 #pragma unroll SU
     for (int p0 = 0; p0 < NPL; p0 += PPP) {
       const int pl = p0 + lp < NPL ? p0 + lp : NPL - 1;
       const int arr = pl / (4 * M), vl = pl % (4 * M), v = vl / M, l = vl % M;
       const size_t off = ((size_t)gcomp[v] * M + l) * g.cells + cell;
-      const T val = arr == 0 ? T(LV[off]) : T(hn * slope[off]);
+      const T val = arr == 0 ? LV[off] : hnT * slope[off];
       if (slot && p0 + lp < NPL) stv[arr * NSTV + (vl * NR + r) * NCS + cc] = val;
     }
   }
@@ -1207,15 +1231,15 @@ __device__ void face2d_tile(const Geo& g, const Consts& C, const Bufs& B, unsign
       if (DIR == 1) fin[v * NFT + ci * NT + r] = snew;
       for (int l = 0; l < M; ++l) {
         const size_t is = DIR == 0 ? g.sx(v, l, i, j) : g.sy(v, l, i, j);
-        Sg[is] = (rb(8 + v, l) - ra(8 + v, l)) * ihn;
-        Ag[is] = (rb(12 + v, l) - ra(12 + v, l)) * ihn;
+        SgS[is] = T((rb(8 + v, l) - ra(8 + v, l)) * ihn);
+        AgS[is] = T((rb(12 + v, l) - ra(12 + v, l)) * ihn);
       }
     } else {
       // every load before the first store: U and A are distinct arrays, but
       // the compiler cannot know it and would otherwise wait for each load
       double aslope[M];
 #pragma unroll
-      for (int l = 0; l < M; ++l) aslope[l] = Ag[DIR == 0 ? g.sx(v, l, i, j) : g.sy(v, l, i, j)];
+      for (int l = 0; l < M; ++l) aslope[l] = double(AgS[DIR == 0 ? g.sx(v, l, i, j) : g.sy(v, l, i, j)]);
       const double base = DIR == 0 ? Ag[ia] : Ug[ia];
       double dA = 0.0;
       for (int l = 0; l < M; ++l) dA += kGw[M][l] * (rb(v, l) - ra(v, l));
@@ -1225,7 +1249,7 @@ __device__ void face2d_tile(const Geo& g, const Consts& C, const Bufs& B, unsign
 #pragma unroll
       for (int l = 0; l < M; ++l) {
         const size_t is = DIR == 0 ? g.sx(v, l, i, j) : g.sy(v, l, i, j);
-        Ug[is] = aslope[l] + (rb(4 + v, l) - ra(4 + v, l)) * ihn;
+        UgS[is] = T(aslope[l] + (rb(4 + v, l) - ra(4 + v, l)) * ihn);
       }
     }
   }
@@ -1283,6 +1307,9 @@ __device__ void stage1d_seg(const Geo& g, const Consts& C, const Bufs& B, double
   const int t = threadIdx.x;
   const gptr<const double> Uin = glb((const double*)(STAGE == 1 ? B.U : B.S));
   const gptr<double> Ug = glb(B.U), Sg = glb(B.S), Ag = glb(B.A);
+  // slope planes (element type T)
+  const gptr<const T> UinS = glb(slopes<T>((const double*)(STAGE == 1 ? B.U : B.S), g));
+  const gptr<T> UgS = glb(slopes<T>(B.U, g)), SgS = glb(slopes<T>(B.S, g)), AgS = glb(slopes<T>(B.A, g));
   const double h = C.dx;
   T* sa = (T*)(sm + Lds1D<T>::avg);
   T* ss = (T*)(sm + Lds1D<T>::slo);
@@ -1299,7 +1326,7 @@ __device__ void stage1d_seg(const Geo& g, const Consts& C, const Bufs& B, double
     const int v = k / S1_NS, c = k % S1_NS;
     const int cell = clampc(F0 - 3 + c);
     const T a = T(Uin[g.avg(v, cell, 0)]);
-    const T sl = T(h * Uin[g.sx(v, 0, cell, 0)]);
+    const T sl = T(h * double(UinS[g.sx(v, 0, cell, 0)]));
     if (base + t < 3 * S1_NS) { sa[v * S1_NS + c] = a; ss[v * S1_NS + c] = sl; }
   }
 #pragma unroll
@@ -1408,7 +1435,7 @@ __device__ void stage1d_seg(const Geo& g, const Consts& C, const Bufs& B, double
 #pragma unroll
     for (int v = 0; v < 3; ++v) {
       in0[v] = STAGE == 1 ? Ug[g.avg(v, i, 0)] : Ag[g.avg(v, i, 0)];
-      in1[v] = STAGE == 1 ? 0.0 : Ag[g.sx(v, 0, i, 0)];
+      in1[v] = STAGE == 1 ? 0.0 : double(AgS[g.sx(v, 0, i, 0)]);
     }
 #pragma unroll
     for (int v = 0; v < 3; ++v) {
@@ -1418,12 +1445,12 @@ __device__ void stage1d_seg(const Geo& g, const Consts& C, const Bufs& B, double
         W[v] = u0 - (res[f + 1][v] - res[f][v]) * ih;
         Sg[ia] = W[v];
         Ag[ia] = u0 - (res[f + 1][3 + v] - res[f][3 + v]) * ih;
-        Sg[is] = (res[f + 1][6 + v] - res[f][6 + v]) * ih;
-        Ag[is] = (res[f + 1][9 + v] - res[f][9 + v]) * ih;
+        SgS[is] = T((res[f + 1][6 + v] - res[f][6 + v]) * ih);
+        AgS[is] = T((res[f + 1][9 + v] - res[f][9 + v]) * ih);
       } else {
         W[v] = in0[v] - (res[f + 1][v] - res[f][v]) * ih;
         Ug[ia] = W[v];
-        Ug[is] = in1[v] + (res[f + 1][3 + v] - res[f][3 + v]) * ih;
+        UgS[is] = T(in1[v] + (res[f + 1][3 + v] - res[f][3 + v]) * ih);
       }
     }
     rr = W[0];
