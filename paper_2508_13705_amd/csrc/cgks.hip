@@ -96,7 +96,7 @@ __global__ __launch_bounds__(256, FaceWaves<T>::value) void k_face2d(Geo g, Cons
   const int lb = xcd_block(blockIdx.y * gridDim.x + blockIdx.x, gridDim.x * gridDim.y);
   const int bx = DIR == 0 ? lb % gridDim.x : lb / gridDim.y;
   const int by = DIR == 0 ? lb / gridDim.x : lb % gridDim.y;
-  face2d_tile<DIR, STAGE, M, T, PR>(g, C, B, smem, bx, by, gridDim.x, gridDim.y);
+  face2d_tile<DIR, STAGE, M, T, PR, 32, false, 0, true>(g, C, B, smem, bx, by, gridDim.x, gridDim.y);
 }
 
 template <int STAGE, typename T, bool PR>

@@ -956,7 +956,8 @@ __device__ __forceinline__ T tanw(int m, int l, int k) {
 // with a barrier so the LDS of the previous tile is free).  SU: staging passes
 // whose loads are issued together (all of them where registers allow; the
 // persistent batched kernels keep more per-job state live and take fewer).
-template <int DIR, int STAGE, int M, typename T, bool PR, int SU = 32, bool PERSIST = false, int V = 0>
+template <int DIR, int STAGE, int M, typename T, bool PR, int SU = 32, bool PERSIST = false, int V = 0,
+          bool UNROLL = false>
 __device__ void face2d_tile(const Geo& g, const Consts& C, const Bufs& B, unsigned char* smem, int bx, int by,
                             int nbx, int nby) {
   using TL = Tile<M, V>;
@@ -1067,6 +1068,11 @@ __device__ void face2d_tile(const Geo& g, const Consts& C, const Bufs& B, unsign
   // Every pass runs on all 256 lanes: a lane without an item of its own
   // recomputes a valid item of the tile (c = r = 1, l = 0) and stores nothing.
   constexpr int NA = NC * NR * M;
+  // UNROLL (single-grid kernels): in a loop the compiler keeps the
+  // stencils' FP64 constants in scalar registers across the passes and
+  // spills them into vector lanes; unrolled, the FP64 step is 7% shorter.
+  // The arithmetic is the same either way.
+#pragma unroll(UNROLL ? (NA + 255) / 256 : 1)
   for (int base = 0; base < NA; base += 256) {
     const int it = base + tx;
     int c, r, l;
