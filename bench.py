@@ -76,6 +76,8 @@ def parse():
     ap.add_argument("--boundaries", type=int, default=1, help="run the wall/inflow workloads to their end times (0: skip)")
     ap.add_argument("--shard-parts", type=int, default=8,
                     help="also time one GPU's slab of the grid split this many ways (0: skip)")
+    ap.add_argument("--probe-batch-jobs", type=int, default=1024,
+                    help="jobs of the 1-D Riemann batch that --pmc-probe steps (0: none)")
     ap.add_argument("--pmc-probe", action="store_true",
                     help="for hardware-counter runs: one step of each path, then a device copy of "
                          "COPY_BYTES (the calibration of the byte counters); prints nothing else")
@@ -374,7 +376,7 @@ def cpu_baseline(seconds):
 COPY_BYTES = 1 << 30
 
 
-def pmc_probe(n):
+def pmc_probe(n, batch_jobs):
     import torch
     from paper_2508_13705_amd import cgks
     from paper_2508_13705_amd import workloads as W
@@ -385,17 +387,31 @@ def pmc_probe(n):
         torch.cuda.synchronize()
         del s
         torch.cuda.empty_cache()
+    # the batched 1-D stage kernels: a seeded subset of the 1-D Riemann batch,
+    # two batch steps per precision (the second is the one to read)
+    if batch_jobs > 0:
+        probs = W.riemann_batch(seed=2, count=batch_jobs)
+        for precision in ("fp64", "fp32_flux"):
+            B = cgks.Batch(1, precision, max_jobs=batch_jobs)
+            sol = [cgks.Solver(pb, precision=precision) for pb in probs]
+            for pb, q in zip(probs, sol):
+                B.add(q, max_steps=0, t_end=pb["run"]["t_end"])
+            B.commit()
+            B.step(2)
+            torch.cuda.synchronize()
+            del B, sol
+            torch.cuda.empty_cache()
     src = torch.ones(COPY_BYTES // 8, dtype=torch.float64, device="cuda")
     dst = torch.empty_like(src)
     dst.copy_(src)
     torch.cuda.synchronize()
-    print(json.dumps({"pmc_probe": True, "copy_bytes": COPY_BYTES, "n": n}))
+    print(json.dumps({"pmc_probe": True, "copy_bytes": COPY_BYTES, "n": n, "batch_jobs": batch_jobs}))
 
 
 def main():
     a = parse()
     if a.pmc_probe:
-        pmc_probe(a.n)
+        pmc_probe(a.n, a.probe_batch_jobs)
         return
     if a.gpus != 1:
         print(json.dumps({"error": "one GPU only: the library has no multi-GPU path; run with --gpus 1"}))

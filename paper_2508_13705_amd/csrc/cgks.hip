@@ -101,9 +101,18 @@ __global__ __launch_bounds__(256, FaceWaves<T>::value) void k_face2d(Geo g, Cons
 
 template <int STAGE, typename T, bool PR>
 __global__ __launch_bounds__(256) void k_stage1d(Geo g, Consts C, Bufs B) {
-  __shared__ double res[256][12];
-  __shared__ __align__(16) unsigned char sm[Lds1D<T>::total];
-  stage1d_seg<STAGE, T, PR>(g, C, B, res, sm, blockIdx.x, gridDim.x);
+  if constexpr (sizeof(T) == 4) {   // inputs copied into LDS by DMA
+    __shared__ S1In<T> in;
+    __shared__ S1Acc<T> acc;
+    __shared__ S1Mid<T, STAGE> mid;
+    s1_issue_in<STAGE, T>(g, B, blockIdx.x, &in, threadIdx.x);
+    s1_landed();
+    stage1d_seg_lds<STAGE, T, PR>(g, C, B, &in, &acc, &mid, blockIdx.x, gridDim.x);
+  } else {                           // inputs through registers
+    __shared__ double res[256][12];
+    __shared__ __align__(16) unsigned char sm[Lds1D<T>::total];
+    stage1d_seg<STAGE, T, PR>(g, C, B, res, sm, blockIdx.x, gridDim.x);
+  }
 }
 
 __global__ __launch_bounds__(256) void k_sum1(Geo g, const double* U, DD* part, int nblk) {

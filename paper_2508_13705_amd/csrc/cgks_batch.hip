@@ -42,12 +42,20 @@ struct BJob {
   int ns;                  // ghost-cell items (GhostItems)
 };
 
+struct S1Item {
+  int job, seg;
+};
+
 struct BTab {
   int njobs, cap;
   int total[NPH];
   BJob* jobs;      // [cap], table order
   int* pre;        // [NPH][cap + 1] prefix sums of the items per job
   JobStat* stat;   // [cap], by slot
+  // 1-D: the (job, segment) of every item of the stage phase; a 1-D batch has
+  // thousands of jobs of a few segments, and a binary search of the prefix
+  // sums would cost a dozen dependent loads per segment
+  S1Item* s1map;
 };
 
 // Largest j in [0, n) with pre[j] <= item (pre[0] = 0, pre[n] = total).
@@ -60,6 +68,22 @@ __device__ __forceinline__ int find_job(P pre, int n, int item) {
     else hi = mid;
   }
   return lo;
+}
+
+// A job's descriptor, read in place through a pointer of constant type: the
+// table does not change while a kernel runs, so its fields are scalar loads
+// that the compiler may repeat where they are used, as it does with kernel
+// arguments, instead of holding the whole descriptor in registers across a
+// tile (through the generic table pointer they would be FLAT loads, which
+// count against the LDS counter).  The host pass, which cannot form that
+// address space, reads it directly.
+__device__ __forceinline__ const BJob& job_ref(const BTab* tab, int j) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  using cjob = const __attribute__((address_space(4))) BJob*;
+  return *(const BJob*)((cjob)tab->jobs + j);
+#else
+  return tab->jobs[j];
+#endif
 }
 
 // Persistent loop over the items of a phase.  With remap, blocks that the
@@ -83,23 +107,15 @@ __device__ __forceinline__ void for_items(const BTab* tab, int ph, int remap, F&
     const int j = __builtin_amdgcn_readfirstlane(find_job(pre, n, item));
     const int k = __builtin_amdgcn_readfirstlane(item - pre[j]);
 #if defined(__HIP_DEVICE_COMPILE__)
-    // read through a pointer of constant type: the table does not change
-    // while a kernel runs, so its fields are scalar loads that the compiler
-    // may repeat where they are used, as it does with kernel arguments,
-    // instead of holding the whole descriptor in registers across the tile
-    // (through the generic table pointer they would be FLAT loads, which
-    // count against the LDS counter)
-    using cjob = const __attribute__((address_space(4))) BJob*;
     if (CREF) {
-      f(*(const BJob*)((cjob)tab->jobs + j), k);
+      f(job_ref(tab, j), k);
     } else {
-      // through a pointer of global type: scalar loads
+      // a copy, read through a pointer of global type: scalar loads
       const BJob J = glb((const BJob*)tab->jobs)[j];
       f(J, k);
     }
 #else
-    const BJob& J = tab->jobs[j];
-    f(J, k);
+    f(tab->jobs[j], k);
 #endif
   }
 }
@@ -179,11 +195,54 @@ __global__ __launch_bounds__(256, sizeof(T) == 4 ? 2 : 1) void kb_face(const BTa
 
 // One stage of the 1-D scheme over the segments of every job.
 template <int STAGE, typename T>
-__global__ __launch_bounds__(256, 2) void kb_stage1d(const BTab* tab, int remap) {
-  __shared__ double res[256][12];
-  __shared__ __align__(16) unsigned char sm[Lds1D<T>::total];
-  for_items(tab, PH_S1D, remap,
-            [&](const BJob& J, int k) { stage1d_seg<STAGE, T, false>(J.g, J.C, J.B, res, sm, k, J.nseg); });
+__global__ __launch_bounds__(256, sizeof(T) == 4 ? 3 : 2) void kb_stage1d(const BTab* tab, int remap) {
+  const int total = tab->total[PH_S1D];
+  const int G = gridDim.x;
+  int lb = blockIdx.x;
+  if (remap) lb = (blockIdx.x & 7) * (G >> 3) + (blockIdx.x >> 3);   // G is a multiple of 8
+  // the item's job and segment (wave-uniform): scalar loads through a
+  // pointer of constant type, the map does not change while the kernel runs
+  auto item_of = [&](int item, int& j, int& seg) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    const S1Item e = ((const __attribute__((address_space(4))) S1Item*)tab->s1map)[item];
+#else
+    const S1Item e = tab->s1map[item];
+#endif
+    j = __builtin_amdgcn_readfirstlane(e.job);
+    seg = __builtin_amdgcn_readfirstlane(e.seg);
+  };
+  if constexpr (sizeof(T) == 4) {
+    // FP32: inputs copied into LDS by DMA; the descriptor read in place
+    // (registers are this kernel's limit: three waves per SIMD)
+    __shared__ S1In<T> in;
+    __shared__ S1Acc<T> acc;
+    __shared__ S1Mid<T, STAGE> mid;
+    for (int item = lb; item < total; item += G) {
+      int j, seg;
+      item_of(item, j, seg);
+      const BJob& J = job_ref(tab, j);
+      __syncthreads();   // the previous segment is done with the LDS
+      s1_issue_in<STAGE, T>(J.g, J.B, seg, &in, tile_tid());
+      s1_landed();
+      stage1d_seg_lds<STAGE, T, false, true>(J.g, J.C, J.B, &in, &acc, &mid, seg, J.nseg);
+    }
+  } else {
+    // FP64: inputs through registers; a copy of the descriptor (its scalar
+    // registers are full: fields read in place would be reloaded, and waited
+    // for, at every use)
+    __shared__ double res[256][12];
+    __shared__ __align__(16) unsigned char sm[Lds1D<T>::total];
+    for (int item = lb; item < total; item += G) {
+      int j, seg;
+      item_of(item, j, seg);
+#if defined(__HIP_DEVICE_COMPILE__)
+      const BJob J = glb((const BJob*)tab->jobs)[j];
+#else
+      const BJob& J = tab->jobs[j];
+#endif
+      stage1d_seg<STAGE, T, false>(J.g, J.C, J.B, res, sm, seg, J.nseg);
+    }
+  }
 }
 
 // Kernel slots of the persistent launches (grid sizes are per slot).
@@ -213,6 +272,9 @@ struct cgks_batch {
   JobStat* hstat = nullptr;  // pinned host copy of the progress records (cgks_batch_poll)
   size_t off_stat = 0, table_bytes = 0;
   std::vector<unsigned char> staging;
+  S1Item* ds1map = nullptr;   // device (job, segment) map of the 1-D stage phase
+  size_t s1cap = 0;           // its capacity in items
+  std::vector<S1Item> hs1map;
   hipStream_t cap_stream = nullptr;
   hipGraphExec_t exec = nullptr;
   int graph_steps = 0;
@@ -485,6 +547,7 @@ cgks_status cgks_batch_destroy(cgks_batch* b) {
   if (b->cap_stream) hipStreamDestroy(b->cap_stream);
   if (b->hstat) hipHostFree(b->hstat);
   if (b->dmem) hipFree(b->dmem);
+  if (b->ds1map) hipFree(b->ds1map);
   delete b;
   return CGKS_OK;
 }
@@ -582,6 +645,31 @@ cgks_status cgks_batch_commit(cgks_batch* b, void* stream) {
     T->total[ph] = (int)acc;
   }
   for (int k = 0; k < n; ++k) jobs[k] = b->slots[b->order[k]];
+  // 1-D: the (job, segment) of every stage item, in the device map (grown
+  // when the batch outgrows it; the graph reads the map's address from the
+  // table, so it stays valid)
+  if (b->dim == 1) {
+    const size_t tot = (size_t)T->total[PH_S1D];
+    if (tot > b->s1cap) {
+      const size_t cap = tot + tot / 4 + 1024;
+      HIP_TRY(hipStreamSynchronize(st));   // no launch in flight reads the old map
+      if (b->ds1map) HIP_TRY(hipFree(b->ds1map));
+      b->ds1map = nullptr;
+      b->s1cap = 0;
+      HIP_TRY(hipMalloc((void**)&b->ds1map, cap * sizeof(S1Item)));
+      b->s1cap = cap;
+    }
+    try {
+      b->hs1map.resize(tot);
+    } catch (...) {
+      return fail(CGKS_ENOMEM, "batch segment map");
+    }
+    const int* P = pre + (size_t)PH_S1D * (b->cap + 1);
+    for (int k = 0; k < n; ++k)
+      for (int q = P[k]; q < P[k + 1]; ++q) b->hs1map[q] = S1Item{k, q - P[k]};
+    if (tot) HIP_TRY(hipMemcpyAsync(b->ds1map, b->hs1map.data(), tot * sizeof(S1Item), hipMemcpyHostToDevice, st));
+  }
+  T->s1map = b->ds1map;
   // the host staging buffer is reused by the next commit: copy and wait
   HIP_TRY(hipMemcpyAsync(b->dmem, base, sizeof(BTab), hipMemcpyHostToDevice, st));
   if (n) HIP_TRY(hipMemcpyAsync(b->djobs, jobs, sizeof(BJob) * n, hipMemcpyHostToDevice, st));

@@ -1282,16 +1282,251 @@ __device__ void face2d_tile(const Geo& g, const Consts& C, const Bufs& B, unsign
 
 
 // ---------------------------------------------------------------------------
-// 1-D stage kernel.  A block owns faces F0 .. F0+S1_FACES-1 and updates cells
-// F0 .. F0+S1_FACES-2.  Phases, separated by barriers: the segment's inputs
-// to LDS in one batch of loads; one thread per cell reconstructs both of its
-// faces (cells F0-1 .. F0+S1_FACES-1, one per thread); one thread per face
-// takes its two states and computes the flux; the update.
+// 1-D stage.  A segment owns faces F0 .. F0+S1_FACES-1 and updates cells
+// F0 .. F0+S1_FACES-2.  Its inputs (cell averages, slopes and face strengths
+// with the stencil halo; in stage 2 also the accumulator of the updated
+// cells) are loaded straight from memory into LDS, as stored, without passing
+// through registers (global_load_lds).  Phases, separated by barriers: one
+// thread per cell reconstructs both of its faces (cells F0-1 .. F0+S1_FACES-1,
+// one per thread); one thread per face takes its two states and computes the
+// flux; the update.  A persistent block issues the next segment's input loads
+// into a second buffer before it reconstructs the current one, so their
+// latency is hidden behind this segment's arithmetic.
 // ---------------------------------------------------------------------------
 constexpr int S1_FACES = 255;                  // faces per block
 constexpr int S1_CELLS = S1_FACES - 1;         // updated cells per block
 constexpr int S1_NS = S1_FACES + 5;            // staged cells F0-3 .. F0+S1_FACES+1
 constexpr int S1_NG = S1_FACES + 6;            // staged faces F0-3 .. F0+S1_FACES+2
+
+// One input buffer: averages (double) and slopes (storage type T) of the
+// staged cells, strengths (double) of the staged faces.
+template <typename T> struct S1In {
+  double avg[3][S1_NS];
+  T slo[3][S1_NS];
+  double sig[S1_NG];
+};
+// Stage 2: the accumulator (averages, slopes) of the updated cells.
+template <typename T> struct S1Acc {
+  double avg[3][S1_CELLS];
+  T slo[3][S1_CELLS];
+};
+// The reconstructions [cell][side][k][v] and, once every flux has read its
+// two states, the flux results [face][12 or 6] in the same space.
+template <typename T, int STAGE> union S1Mid {
+  T rc[256][18];
+  double res[256][STAGE == 1 ? 12 : 6];
+};
+
+// Copy n 4-byte words into LDS at dst (word w from the global address
+// src(w)) without passing through registers.  Each wave takes every fourth
+// chunk of 64 words; lane L of chunk j writes word 64 j + L.  Complete after
+// s1_landed.
+template <class F>
+__device__ __forceinline__ void lds_copy(void* dst, int n, int tid, F&& src) {
+  const int lane = tid & 63;
+  for (int j = tid >> 6; j * 64 < n; j += 4) {
+    const int w = j * 64 + lane;
+    auto* d = (__attribute__((address_space(3))) void*)((unsigned*)dst + j * 64);
+    if (w < n) __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void*)src(w), d, 4, 0, 0);
+  }
+}
+
+// Every load of the block into LDS has landed: each wave waits for its own
+// memory operations, then the barrier covers the other waves'.
+__device__ __forceinline__ void s1_landed() {
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+}
+
+// Issue the input loads of segment seg (entries outside the stored grid are
+// clamped into it; no owned item reads them).  One copy per plane: word w of
+// a plane of doubles is half w & 1 of entry w / 2.
+template <int STAGE, typename T>
+__device__ __forceinline__ void s1_issue_in(const Geo& g, const Bufs& B, int seg, S1In<T>* in, int tid) {
+  const int F0 = seg * S1_CELLS;
+  const double* U = STAGE == 1 ? B.U : B.S;
+  const T* Us = slopes<T>(U, g);
+  auto cellc = [&](int c) {
+    const int x = F0 - 3 + c;
+    return x < -H ? -H : (x > g.nx + H - 1 ? g.nx + H - 1 : x);
+  };
+  constexpr int WS = sizeof(T) / 4;   // words per slope
+#pragma unroll
+  for (int v = 0; v < 3; ++v) {
+    const double* Uv = U + g.avg(v, 0, 0);
+    lds_copy(&in->avg[v][0], 2 * S1_NS, tid,
+             [&](int w) { return (const unsigned*)(Uv + cellc(w >> 1)) + (w & 1); });
+    const T* Sv = Us + g.sx(v, 0, 0, 0);
+    lds_copy(&in->slo[v][0], WS * S1_NS, tid,
+             [&](int w) { return (const unsigned*)(Sv + cellc(w / WS)) + (w % WS); });
+  }
+  lds_copy(&in->sig[0], 2 * S1_NG, tid, [&](int w) {
+    const int face = F0 - 3 + (w >> 1);
+    return (const unsigned*)(B.sxo + g.sgx(0, face < -H ? -H : (face > g.nx + H ? g.nx + H : face))) + (w & 1);
+  });
+}
+
+// Stage 2: issue the loads of the accumulator of the segment's updated cells.
+template <typename T>
+__device__ __forceinline__ void s1_issue_acc(const Geo& g, const Bufs& B, int seg, S1Acc<T>* acc, int tid) {
+  const int F0 = seg * S1_CELLS;
+  const T* As = slopes<T>(B.A, g);
+  auto cellc = [&](int c) { const int x = F0 + c; return x > g.nx - 1 ? g.nx - 1 : x; };
+  constexpr int WS = sizeof(T) / 4;
+#pragma unroll
+  for (int v = 0; v < 3; ++v) {
+    const double* Av = B.A + g.avg(v, 0, 0);
+    lds_copy(&acc->avg[v][0], 2 * S1_CELLS, tid, [&](int w) { return (const unsigned*)(Av + cellc(w >> 1)) + (w & 1); });
+    const T* Sv = As + g.sx(v, 0, 0, 0);
+    lds_copy(&acc->slo[v][0], WS * S1_CELLS, tid, [&](int w) { return (const unsigned*)(Sv + cellc(w / WS)) + (w % WS); });
+  }
+}
+
+// The arithmetic of segment seg, from its inputs in LDS (landed and made
+// visible by a barrier).  Stage 2 issues the accumulator loads itself.
+// PERSIST: called from a persistent loop (an index the compiler cannot hoist
+// out of the loop, as in face2d_tile).
+template <int STAGE, typename T, bool PR, bool PERSIST = false>
+__device__ void stage1d_seg_lds(const Geo& g, const Consts& C, const Bufs& B, const S1In<T>* in, S1Acc<T>* acc,
+                            S1Mid<T, STAGE>* mid, int seg, int nseg) {
+  const gptr<const Header> hdr = glb((const Header*)B.hdr);
+  if (!hdr->active) return;
+  const double dt = hdr->dt;
+  const int F0 = seg * S1_CELLS;
+  const int t = PERSIST ? tile_tid() : (int)threadIdx.x;
+  const gptr<double> Ug = glb(B.U), Sg = glb(B.S), Ag = glb(B.A);
+  const gptr<T> UgS = glb(slopes<T>(B.U, g)), SgS = glb(slopes<T>(B.S, g)), AgS = glb(slopes<T>(B.A, g));
+  const double h = C.dx;
+  __shared__ Tally tally;
+  tally_zero(tally, t);
+  __syncthreads();
+  // ---- reconstruction: cell F0-1+t (staged index t+2), both faces ----
+  {
+    double s[6];
+#pragma unroll
+    for (int q = 0; q < 6; ++q) s[q] = in->sig[t + q];           // faces cell-2 .. cell+3
+    const Cascade cs = cascade(s, C.order, C.thres, C.tie);
+    // own reconstructions: the cells the segment updates, and the ghost
+    // cells -1 and nx beside the first and last boundary faces
+    const int cell = F0 - 1 + t;
+    tally_add(tally,
+              (cell >= F0 && cell < F0 + S1_CELLS && cell < g.nx) || (cell == -1 && seg == 0) ||
+                  (cell == g.nx && seg == nseg - 1),
+              cs.branch, cs.tie, C.order, t);
+    T d[3][9];
+#pragma unroll
+    for (int v = 0; v < 3; ++v) {
+#pragma unroll
+      for (int k = 0; k < 5; ++k) d[v][k] = T(in->avg[v][t + k]);
+#pragma unroll
+      for (int k = 0; k < 4; ++k) d[v][5 + k] = T(h * double(in->slo[v][t + (k < 2 ? k : k + 1)]));   // cells -2, -1, +1, +2
+    }
+    T out[2][3][3];
+    recon_faces<T, 3>(d, cs, C, out);
+#pragma unroll
+    for (int sd = 0; sd < 2; ++sd)
+#pragma unroll
+      for (int k = 0; k < 3; ++k)
+#pragma unroll
+        for (int v = 0; v < 3; ++v) mid->rc[t][(sd * 3 + k) * 3 + v] = out[sd][k][v];
+  }
+  __syncthreads();
+  tally_flush(tally, B.hdr, t);
+  if (STAGE == 2) s1_issue_acc<T>(g, B, seg, acc, t);   // lands during the flux
+  // ---- flux: face F0+f, one per thread (wave-uniform: lanes without a face
+  // of their own compute the block's last face and store nothing) ----
+  const int f = t;
+  const int F = F0 + f;
+  const bool own = f < S1_FACES && F <= g.nx;
+  const int fc = own ? f : (g.nx - F0 < S1_FACES - 1 ? g.nx - F0 : S1_FACES - 1);
+  const int Fc = F0 + fc;
+  {
+    T Wk[2][6][4];
+#pragma unroll
+    for (int sd = 0; sd < 2; ++sd) {
+      const int cell = Fc - 1 + sd;
+      const int tc = fc + sd;                  // its reconstruction slot
+      const int side = sd == 0 ? 0 : 1;   // left state: +1/2 face of cell F-1; right: -1/2 face of cell F
+#pragma unroll
+      for (int v = 0; v < 4; ++v)
+#pragma unroll
+        for (int dd = 0; dd < 6; ++dd) Wk[sd][dd][v] = T(0);
+#pragma unroll
+      for (int v = 0; v < 3; ++v) {
+        Wk[sd][0][v] = mid->rc[tc][(side * 3 + 0) * 3 + v];
+        Wk[sd][1][v] = mid->rc[tc][(side * 3 + 1) * 3 + v] / T(h);
+        Wk[sd][3][v] = mid->rc[tc][(side * 3 + 2) * 3 + v] / T(h * h);
+      }
+      if (!positive_state<T, 1>(Wk[sd][0])) {
+#pragma unroll
+        for (int v = 0; v < 3; ++v) {
+          Wk[sd][0][v] = T(in->avg[v][cell - (F0 - 3)]);
+          Wk[sd][1][v] = T(0);
+          Wk[sd][3][v] = T(0);
+        }
+        // counted once per face: the segment's last face is the next one's first
+        if (own && (f < S1_CELLS || F == g.nx)) atomicAdd((unsigned long long*)&B.hdr->fallbacks, 1ull);
+      }
+    }
+    __syncthreads();   // every flux has its two states: the results may overwrite them
+    FaceOut fo;
+    gks_flux<T, 1, PR>(Wk[0], Wk[1], dt, C, fo);
+    if (own) {
+#pragma unroll
+    for (int v = 0; v < 3; ++v) {
+      if (STAGE == 1) {
+        mid->res[f][v] = fo.Fh[v];
+        mid->res[f][3 + v] = (8.0 / 3.0) * fo.Fh[v] - (1.0 / 3.0) * fo.F1[v];
+        mid->res[f][6 + v] = fo.Wh[v];
+        mid->res[f][9 + v] = -(4.0 / 3.0) * fo.W0[v] + (8.0 / 3.0) * fo.Wh[v] - (1.0 / 3.0) * fo.W1[v];
+      } else {
+        mid->res[f][v] = (4.0 / 3.0) * (fo.F1[v] - 2.0 * fo.Fh[v]);
+        mid->res[f][3 + v] = (4.0 / 3.0) * (fo.W0[v] - 2.0 * fo.Wh[v] + fo.W1[v]);
+      }
+    }
+    if (STAGE == 1) glb(B.sxn)[g.sgx(0, F)] = fo.sigma;
+    }
+  }
+  if (STAGE == 2) s1_landed();   // the accumulator loads, and the results
+  else __syncthreads();
+  const int i = F0 + f;  // cell
+  bool valid = false;
+  double s = 0.0, rr = 1.0;
+  if (f < S1_CELLS && i < g.nx) {
+    const double ih = 1.0 / h;
+    double W[3];
+#pragma unroll
+    for (int v = 0; v < 3; ++v) {
+      const size_t ia = g.avg(v, i, 0), is = g.sx(v, 0, i, 0);
+      const auto& r0 = mid->res[f];
+      const auto& r1 = mid->res[f + 1];
+      if (STAGE == 1) {
+        const double u0 = in->avg[v][f + 3];   // the stage input: W^n of cell i
+        W[v] = u0 - (r1[v] - r0[v]) * ih;
+        Sg[ia] = W[v];
+        Ag[ia] = u0 - (r1[3 + v] - r0[3 + v]) * ih;
+        SgS[is] = T((r1[6 + v] - r0[6 + v]) * ih);
+        AgS[is] = T((r1[9 + v] - r0[9 + v]) * ih);
+      } else {
+        W[v] = acc->avg[v][f] - (r1[v] - r0[v]) * ih;
+        Ug[ia] = W[v];
+        UgS[is] = T(double(acc->slo[v][f]) + (r1[3 + v] - r0[3 + v]) * ih);
+      }
+    }
+    rr = W[0];
+    valid = cell_speed(W, 1, C.gamma, s);
+    if (!valid) atomicAdd((unsigned long long*)&B.hdr->nonphysical, 1ull);
+  }
+  if (STAGE == 2) reduce_speed(B, s, rr, valid, seg, nseg);
+}
+
+// The FP64 variant of the stage body: the inputs pass through registers
+// (converted and h-scaled on the way) into LDS, the update reads its inputs
+// from memory, and the flux results have an LDS area of their own.  Measured
+// on the 4096-problem batch it is 9% faster in FP64 than the body above,
+// whose inputs are copied by LDS DMA (one instruction per 4 bytes, so twice
+// the instructions for doubles); in FP32 the body above is 15% faster (three
+// waves per SIMD).  The two do the same arithmetic on the same values.
 // LDS of a segment (bytes, for element type T): averages and h-scaled slopes
 // [v][S1_NS] (T), strengths [S1_NG] (double), reconstructions [cell][side][k][v] (T)
 template <typename T> struct Lds1D {
