@@ -43,7 +43,7 @@ struct BJob {
 };
 
 struct S1Item {
-  int job, seg;
+  int job, seg;   // job (table order), item index within the job
 };
 
 struct BTab {
@@ -52,10 +52,12 @@ struct BTab {
   BJob* jobs;      // [cap], table order
   int* pre;        // [NPH][cap + 1] prefix sums of the items per job
   JobStat* stat;   // [cap], by slot
-  // 1-D: the (job, segment) of every item of the stage phase; a 1-D batch has
-  // thousands of jobs of a few segments, and a binary search of the prefix
-  // sums would cost a dozen dependent loads per segment
-  S1Item* s1map;
+  // 1-D: the (job, index in the job) of every item of each phase, at
+  // imap + ioff[phase] (null in 2-D, whose batches hold few jobs); a 1-D
+  // batch has thousands of jobs of a few items each, and a binary search of
+  // the prefix sums would cost a dozen dependent loads per item
+  S1Item* imap;
+  int ioff[NPH];
 };
 
 // Largest j in [0, n) with pre[j] <= item (pre[0] = 0, pre[n] = total).
@@ -92,7 +94,10 @@ __device__ __forceinline__ const BJob& job_ref(const BTab* tab, int j) {
 // CREF: read the job descriptor in place through a constant pointer (the
 // default), or copy it (the FP64 face kernels, whose registers are full:
 // there the in-place reads cost scratch).
-template <bool CREF = true, class F>
+// MAP: the phase may run in a 1-D batch, whose items come from the item map
+// when it is present (the 2-D-only kernels leave the branch out: their
+// scalar registers are full).
+template <bool CREF = true, bool MAP = false, class F>
 __device__ __forceinline__ void for_items(const BTab* tab, int ph, int remap, F&& f) {
   const int total = tab->total[ph];
   const int G = gridDim.x;
@@ -100,12 +105,24 @@ __device__ __forceinline__ void for_items(const BTab* tab, int ph, int remap, F&
   if (remap) lb = (blockIdx.x & 7) * (G >> 3) + (blockIdx.x >> 3);   // G is a multiple of 8
   const int n = tab->njobs;
   const gptr<const int> pre = glb((const int*)tab->pre) + (size_t)ph * (tab->cap + 1);
+  const S1Item* imap = MAP ? tab->imap : nullptr;
   for (int item = lb; item < total; item += G) {
     // the job and tile are the same for the whole block: made wave-uniform,
     // the job descriptor comes through scalar loads instead of occupying
-    // vector registers
-    const int j = __builtin_amdgcn_readfirstlane(find_job(pre, n, item));
-    const int k = __builtin_amdgcn_readfirstlane(item - pre[j]);
+    // vector registers.  1-D batches read them from the item map.
+    int j, k;
+    if (MAP && imap) {
+#if defined(__HIP_DEVICE_COMPILE__)
+      const S1Item e = glb(imap)[tab->ioff[ph] + item];
+#else
+      const S1Item e = imap[tab->ioff[ph] + item];
+#endif
+      j = __builtin_amdgcn_readfirstlane(e.job);
+      k = __builtin_amdgcn_readfirstlane(e.seg);
+    } else {
+      j = __builtin_amdgcn_readfirstlane(find_job(pre, n, item));
+      k = __builtin_amdgcn_readfirstlane(item - pre[j]);
+    }
 #if defined(__HIP_DEVICE_COMPILE__)
     if (CREF) {
       f(job_ref(tab, j), k);
@@ -133,7 +150,7 @@ __global__ __launch_bounds__(256) void kb_dt(const BTab* tab) {
 // (ST: slope storage type of the batch's precision).
 template <typename ST>
 __global__ __launch_bounds__(256) void kb_prep(const BTab* tab, int remap) {
-  for_items(tab, PH_PREP, remap, [&](const BJob& J, int k) {
+  for_items<true, true>(tab, PH_PREP, remap, [&](const BJob& J, int k) {
     if (!J.B.hdr->active) return;
     if (k < J.nsx) {
       bc_sigma_at(J.g, J.B.bct, bc_time(J.B.hdr, 1), 0, J.B.sxn, J.B.sxo, J.B.syn, J.B.syo,
@@ -156,7 +173,7 @@ __global__ __launch_bounds__(256) void kb_prep(const BTab* tab, int remap) {
 // Ghost cells of the stage state W*.
 template <typename ST>
 __global__ __launch_bounds__(256) void kb_bcs(const BTab* tab, int remap) {
-  for_items(tab, PH_BCS, remap, [&](const BJob& J, int k) {
+  for_items<true, true>(tab, PH_BCS, remap, [&](const BJob& J, int k) {
     if (!J.B.hdr->active) return;
     int I, Jr;
     GhostItems(J.g).at(J.g, k, I, Jr);
@@ -204,9 +221,9 @@ __global__ __launch_bounds__(256, sizeof(T) == 4 ? 3 : 2) void kb_stage1d(const 
   // pointer of constant type, the map does not change while the kernel runs
   auto item_of = [&](int item, int& j, int& seg) {
 #if defined(__HIP_DEVICE_COMPILE__)
-    const S1Item e = ((const __attribute__((address_space(4))) S1Item*)tab->s1map)[item];
+    const S1Item e = ((const __attribute__((address_space(4))) S1Item*)tab->imap)[tab->ioff[PH_S1D] + item];
 #else
-    const S1Item e = tab->s1map[item];
+    const S1Item e = tab->imap[tab->ioff[PH_S1D] + item];
 #endif
     j = __builtin_amdgcn_readfirstlane(e.job);
     seg = __builtin_amdgcn_readfirstlane(e.seg);
@@ -272,9 +289,9 @@ struct cgks_batch {
   JobStat* hstat = nullptr;  // pinned host copy of the progress records (cgks_batch_poll)
   size_t off_stat = 0, table_bytes = 0;
   std::vector<unsigned char> staging;
-  S1Item* ds1map = nullptr;   // device (job, segment) map of the 1-D stage phase
-  size_t s1cap = 0;           // its capacity in items
-  std::vector<S1Item> hs1map;
+  S1Item* dimap = nullptr;    // device item map of a 1-D batch (BTab::imap)
+  size_t icap = 0;            // its capacity in items
+  std::vector<S1Item> himap;
   hipStream_t cap_stream = nullptr;
   hipGraphExec_t exec = nullptr;
   int graph_steps = 0;
@@ -547,7 +564,7 @@ cgks_status cgks_batch_destroy(cgks_batch* b) {
   if (b->cap_stream) hipStreamDestroy(b->cap_stream);
   if (b->hstat) hipHostFree(b->hstat);
   if (b->dmem) hipFree(b->dmem);
-  if (b->ds1map) hipFree(b->ds1map);
+  if (b->dimap) hipFree(b->dimap);
   delete b;
   return CGKS_OK;
 }
@@ -645,31 +662,41 @@ cgks_status cgks_batch_commit(cgks_batch* b, void* stream) {
     T->total[ph] = (int)acc;
   }
   for (int k = 0; k < n; ++k) jobs[k] = b->slots[b->order[k]];
-  // 1-D: the (job, segment) of every stage item, in the device map (grown
-  // when the batch outgrows it; the graph reads the map's address from the
-  // table, so it stays valid)
+  // 1-D: the (job, index) of every item of the item phases, in the device
+  // map (grown when the batch outgrows it; the graph reads the map's address
+  // from the table, so it stays valid)
+  T->imap = nullptr;
   if (b->dim == 1) {
-    const size_t tot = (size_t)T->total[PH_S1D];
-    if (tot > b->s1cap) {
+    const int phs[] = {PH_PREP, PH_BCS, PH_S1D};
+    size_t tot = 0;
+    for (int ph : phs) {
+      T->ioff[ph] = (int)tot;
+      tot += (size_t)T->total[ph];
+    }
+    if (tot >= (1ull << 31)) return fail(CGKS_EINVAL, "batch too large for 32-bit item indices");
+    if (tot > b->icap) {
       const size_t cap = tot + tot / 4 + 1024;
       HIP_TRY(hipStreamSynchronize(st));   // no launch in flight reads the old map
-      if (b->ds1map) HIP_TRY(hipFree(b->ds1map));
-      b->ds1map = nullptr;
-      b->s1cap = 0;
-      HIP_TRY(hipMalloc((void**)&b->ds1map, cap * sizeof(S1Item)));
-      b->s1cap = cap;
+      if (b->dimap) HIP_TRY(hipFree(b->dimap));
+      b->dimap = nullptr;
+      b->icap = 0;
+      HIP_TRY(hipMalloc((void**)&b->dimap, cap * sizeof(S1Item)));
+      b->icap = cap;
     }
     try {
-      b->hs1map.resize(tot);
+      b->himap.resize(tot);
     } catch (...) {
-      return fail(CGKS_ENOMEM, "batch segment map");
+      return fail(CGKS_ENOMEM, "batch item map");
     }
-    const int* P = pre + (size_t)PH_S1D * (b->cap + 1);
-    for (int k = 0; k < n; ++k)
-      for (int q = P[k]; q < P[k + 1]; ++q) b->hs1map[q] = S1Item{k, q - P[k]};
-    if (tot) HIP_TRY(hipMemcpyAsync(b->ds1map, b->hs1map.data(), tot * sizeof(S1Item), hipMemcpyHostToDevice, st));
+    for (int ph : phs) {
+      const int* P = pre + (size_t)ph * (b->cap + 1);
+      S1Item* M = b->himap.data() + T->ioff[ph];
+      for (int k = 0; k < n; ++k)
+        for (int q = P[k]; q < P[k + 1]; ++q) M[q] = S1Item{k, q - P[k]};
+    }
+    if (tot) HIP_TRY(hipMemcpyAsync(b->dimap, b->himap.data(), tot * sizeof(S1Item), hipMemcpyHostToDevice, st));
+    T->imap = b->dimap;
   }
-  T->s1map = b->ds1map;
   // the host staging buffer is reused by the next commit: copy and wait
   HIP_TRY(hipMemcpyAsync(b->dmem, base, sizeof(BTab), hipMemcpyHostToDevice, st));
   if (n) HIP_TRY(hipMemcpyAsync(b->djobs, jobs, sizeof(BJob) * n, hipMemcpyHostToDevice, st));
