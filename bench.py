@@ -11,8 +11,10 @@ moments in FP32, FP64 accumulation); the FP64 path is timed beside it.
 Beside the headline, the same run measures (a) the batched path on the
 4096-problem 1-D Riemann batch (200-4000 cells each, 9th order, CFL 0.5),
 one persistent launch per phase for the whole batch in a captured hipGraph,
-against the same jobs stepped one at a time by the single-grid path, and
-(b) the serving loop on a Poisson trace of 2-D jobs (side 128-2048, orders
+against the same jobs stepped one at a time by the single-grid path, (a')
+one 1024^2 order-9 job stepped alone and as the only job of a batch (the
+batched kernels' cost over the single-grid ones, with the autotuned tile
+shapes), (b) the serving loop on a Poisson trace of 2-D jobs (side 128-2048, orders
 5/7/9, smooth or four-quadrant data, 50-500 steps) under an HBM budget:
 p50/p99 latency and throughput, (c) the wall and inflow workloads at the
 paper's meshes to their end times, and (d) one GPU's share of the 2048^2 grid
@@ -20,7 +22,8 @@ cut into 8 slabs (2048 x 256, the shape a multi-GPU run would give each GPU).
 
 Prints one JSON line.  Usage:
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--n 2048] [--cpu-seconds 20]
-                    [--batch-steps 40] [--serve-jobs 200] [--boundaries 1] [--shard-parts 8]
+                    [--batch-steps 40] [--batch2d-n 1024] [--serve-jobs 200] [--boundaries 1]
+                    [--shard-parts 8]
 """
 import argparse
 import hashlib
@@ -50,6 +53,10 @@ ALGO_FLOP_PER_GP = 3100
 # 1-D: 6 S + 3 words with S = 6 words (312 B FP64; FP32 slopes 3 x 8 + 3 x 4
 # = 36 B, 6 S + 3 x 8 = 240 B).
 ALGO_BYTES_2D = {"fp64": 1776, "fp32_flux": 1008}
+# Algorithmic FLOPs of the 1-D path per cell-update: per cell and stage one
+# reconstruction of both faces (3 components) and one flux, 1630 FLOP by
+# source count (paper_2508_13705_amd/csrc/flop_count.cpp), two stages.
+ALGO_FLOP_1D = 2 * 1630
 ALGO_BYTES_1D = {"fp64": 312, "fp32_flux": 240}
 # Compulsory HBM bytes of one face launch of this design per cell (m = 4):
 # stage input (avg 4 + normal slopes 16 + line values 16), partial averages
@@ -69,6 +76,8 @@ def parse():
     ap.add_argument("--fp64-steps", type=int, default=None, help="timed steps of the FP64 path (default: --steps)")
     ap.add_argument("--batch-jobs", type=int, default=4096)
     ap.add_argument("--batch-steps", type=int, default=40, help="timed batch steps of the 1-D batch (0: skip)")
+    ap.add_argument("--batch2d-n", type=int, default=1024,
+                    help="side of the 2-D job timed alone and batched (0: skip)")
     ap.add_argument("--serve-jobs", type=int, default=200, help="jobs in the serving trace (0: skip)")
     ap.add_argument("--serve-load", type=float, default=0.8, help="offered load of the serving trace")
     ap.add_argument("--serve-ref-jobs", type=int, default=48,
@@ -102,6 +111,12 @@ def _profile_entry(field, kernel):
     if d.get("source_hash") != kernel_source_hash():
         return None
     return d.get(field, {}).get(kernel)
+
+
+def profile_1d(precision):
+    """Counted bytes and FLOPs per cell-stage of the batched 1-D stage kernels
+    (mean of the two stages), if the profile matches the current sources."""
+    return _profile_entry("batch_1d_per_cell_stage", precision)
 
 
 def measured_traffic(kernel):
@@ -199,11 +214,7 @@ def bench_batch_1d(jobs, steps, precision, graph_steps=10):
         el1 = time.perf_counter() - t0
         h1 = [s.health()["steps"] for s in sample]
     upd1 = sum(s.plan.gd.nx * (b - a) for s, a, b in zip(sample, h0, h1))
-    # HBM roof of the whole batched step: the algorithmic bytes per cell-update
-    # over the measured step time (the stage kernels are ~90% of it)
-    gbs = upd / el * ALGO_BYTES_1D[precision] / 1e9
-    roof = {"bound": "hbm", "achieved": gbs, "peak": PEAK["hbm"], "unit": "GB/s", "frac": gbs / PEAK["hbm"],
-            "algorithmic_bytes_per_cell_update": ALGO_BYTES_1D[precision], "scope": "whole batch step"}
+    roof = roofline_1d(precision, upd / el)
     return {"workload": f"{jobs} 1-D Riemann problems, 200-4000 cells, order 9, CFL 0.5, t_end 0.15, seed 2",
             "precision": precision, "value": upd / el, "unit": "cell-updates/s", "roofline": roof,
             "batch_steps": reps * graph_steps,
@@ -212,6 +223,71 @@ def bench_batch_1d(jobs, steps, precision, graph_steps=10):
             "single_grid_sequential": {"value": upd1 / el1 if el1 > 0 else None, "jobs": len(sample),
                                        "steps_each": graph_steps},
             "speedup_vs_single_grid": (upd / el) / (upd1 / el1) if upd1 > 0 else None}
+
+
+def roofline_1d(precision, rate):
+    """Roofline of the batched 1-D step at `rate` cell-updates/s: the HBM roof
+    (algorithmic bytes per cell-update) and the VALU roof (the source count of
+    the FLOPs per cell-update), t_roof = max of the two; frac = t_roof / t."""
+    t = 1.0 / rate
+    b = ALGO_BYTES_1D[precision]
+    f = ALGO_FLOP_1D
+    t_hbm = b / (PEAK["hbm"] * 1e9)
+    peak_alu = PEAK["fp64_alu"]          # FP64, and FP32 without packed instructions
+    t_alu = f / (peak_alu * 1e12)
+    alu = t_alu >= t_hbm
+    out = {"bound": "alu" if alu else "hbm",
+           "achieved": f * rate / 1e12 if alu else b * rate / 1e9,
+           "peak": peak_alu if alu else PEAK["hbm"], "unit": "TFLOP/s" if alu else "GB/s",
+           "frac": (t_alu if alu else t_hbm) / t,
+           "algorithmic_bytes_per_cell_update": b, "algorithmic_flops_per_cell_update": f,
+           "hbm_frac": t_hbm / t, "alu_frac": t_alu / t, "scope": "whole batch step",
+           "traffic": None}
+    c = profile_1d(precision)
+    if c:
+        out["counted"] = c
+        if c.get("bytes_per_cell_stage"):
+            out["traffic"] = 2 * c["bytes_per_cell_stage"]   # bytes per cell-update, measured
+    return out
+
+
+def bench_batch_2d(n, steps, precision, order=9):
+    """One 2-D job (turbulence n x n, order 9) stepped alone on the
+    single-grid path and as the only job of a batch (persistent kernels,
+    captured graph, autotuned launch and tile shapes): ms per step of each."""
+    import torch
+    from paper_2508_13705_amd import cgks
+    from paper_2508_13705_amd import workloads as W
+    pb = W.turbulence_2d(seed=4, n=n, order=order, nsteps=steps, prandtl=1.0, quad=4)
+    s = cgks.Solver(pb, precision=precision)
+    s.step(2)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.step(steps)
+    torch.cuda.synchronize()
+    single = 1e3 * (time.perf_counter() - t0) / steps
+    del s
+    stream = torch.cuda.Stream()
+    B = cgks.Batch(2, precision, max_jobs=1, stream=stream)
+    q = cgks.Solver(pb, precision=precision, stream=stream)
+    B.add(q, max_steps=10 ** 6)
+    B.commit()
+    tuning = B.tune(1)
+    gs = 5
+    B.capture(gs)
+    B.launch()
+    stream.synchronize()
+    reps = max(1, steps // gs)
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        B.launch()
+    stream.synchronize()
+    batched = 1e3 * (time.perf_counter() - t0) / (reps * gs)
+    del B, q
+    torch.cuda.empty_cache()
+    return {"workload": f"turbulence {n}x{n}, order {order}, Pr 1, one job", "precision": precision,
+            "single_grid_ms_per_step": single, "batched_ms_per_step": batched, "batched_over_single": batched / single,
+            "tuning": tuning}
 
 
 def bench_shard(problem, parts, steps, warmup, full):
@@ -513,6 +589,8 @@ def main():
 
     if a.batch_steps > 0:
         section("batch_1d", batch_1d)
+    if a.batch2d_n > 0:
+        section("batch_2d", lambda: {p: bench_batch_2d(a.batch2d_n, 10, p) for p in ("fp32_flux", "fp64")})
     if a.serve_jobs > 0:
         section("serving", lambda: bench_serving(a.serve_jobs, a.serve_load, value, ref_jobs=a.serve_ref_jobs))
     if a.boundaries:
