@@ -435,6 +435,10 @@ cgks_status cgks_plan_create(const cgks_grid_desc* gd, const cgks_scheme_desc* s
   // variant), summed over up to 12 weighted faces
   C.tie = sd->sigma_thres * (sd->precision == CGKS_FP64 ? 1e-12 : 1e-5);
   C.dx = p->dx;
+  C.idx = 1.0 / p->dx;
+  C.idx2 = 1.0 / (p->dx * p->dx);
+  C.idy = 1.0 / p->dy;
+  C.idy2 = 1.0 / (p->dy * p->dy);
   C.dy = p->dy;
   C.tau_model = sd->tau_model;
   C.order = sd->order;

@@ -35,6 +35,7 @@ struct Consts {
   double gw[3];              // linear weights of the sub-stencils S0, S1, S2 (AO(5,3), Eq. 3.12)
   double tie;                // |A - thres| <= tie: a cascade decision counted as a near tie
   double dx, dy;
+  double idx, idy, idx2, idy2;   // 1/dx, 1/dy, 1/dx^2, 1/dy^2 (no divisions in the kernels)
   int tau_model, order, m;
   int rflags;                // alternative readings, a set of RF_* below
 };

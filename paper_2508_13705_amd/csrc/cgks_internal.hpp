@@ -991,7 +991,9 @@ __device__ void face2d_tile(const Geo& g, const Consts& C, const Bufs& B, unsign
   const int tmax = DIR == 0 ? g.ny : g.nx;   // cells along the tangential
   const int F0 = bx * (NF - 1);
   const int T0 = by * NT;
-  const double hn = DIR == 0 ? C.dx : C.dy, ht = DIR == 0 ? C.dy : C.dx;
+  const double hn = DIR == 0 ? C.dx : C.dy;
+  const double ihn = DIR == 0 ? C.idx : C.idy, ihn2 = DIR == 0 ? C.idx2 : C.idy2;   // normal 1/h, 1/h^2
+  const double iht = DIR == 0 ? C.idy : C.idx, iht2 = DIR == 0 ? C.idy2 : C.idx2;   // tangential
   const gptr<const double> Uin = glb((const double*)(STAGE == 1 ? B.U : B.S));
   const gptr<const T> LV = glb((const T*)(DIR == 0 ? B.lvx : B.lvy));
   const gptr<const double> sgN = glb((const double*)(DIR == 0 ? B.sxo : B.syo));   // normal-face strengths
@@ -1100,7 +1102,7 @@ __device__ void face2d_tile(const Geo& g, const Consts& C, const Bufs& B, unsign
     }
     T out[2][3][4];
     recon_faces<T, 4>(d, cs, C, out);
-    const T ih = T(1.0 / hn), ih2 = T(1.0 / (hn * hn));
+    const T ih = T(ihn), ih2 = T(ihn2);
     if (own) {
 #pragma unroll
       for (int sd = 0; sd < 2; ++sd)
@@ -1139,7 +1141,7 @@ __device__ void face2d_tile(const Geo& g, const Consts& C, const Bufs& B, unsign
       const int c = sd == 0 ? f : f + 1;      // left state: cell nf-1 (its +1/2 face); right: cell nf
       const int ncell = nf - 1 + sd;
       const T at = atab[(f + sd) * NT + r];    // cell ncell = F0-1+(f+sd), line t
-      const T it1 = at * T(1.0 / ht), it2 = at * T(1.0 / (ht * ht));
+      const T it1 = at * T(iht), it2 = at * T(iht2);
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         Wk[sd][0][v] = s2v[I2(r + 1, c, l, sd, v)];
@@ -1209,7 +1211,6 @@ __device__ void face2d_tile(const Geo& g, const Consts& C, const Bufs& B, unsign
   }
 
   // ---- cell update of this direction ----
-  const double ihn = 1.0 / hn;
   constexpr int NFT = (NF - 1) * NT;   // updated cells of the tile
   for (int it = tx; it < (NF - 1) * NT * 4; it += blockDim.x) {
     int ci, r, v;
@@ -1454,8 +1455,8 @@ __device__ void stage1d_seg_lds(const Geo& g, const Consts& C, const Bufs& B, co
 #pragma unroll
       for (int v = 0; v < 3; ++v) {
         Wk[sd][0][v] = mid->rc[tc][(side * 3 + 0) * 3 + v];
-        Wk[sd][1][v] = mid->rc[tc][(side * 3 + 1) * 3 + v] / T(h);
-        Wk[sd][3][v] = mid->rc[tc][(side * 3 + 2) * 3 + v] / T(h * h);
+        Wk[sd][1][v] = mid->rc[tc][(side * 3 + 1) * 3 + v] * T(C.idx);
+        Wk[sd][3][v] = mid->rc[tc][(side * 3 + 2) * 3 + v] * T(C.idx2);
       }
       if (!positive_state<T, 1>(Wk[sd][0])) {
 #pragma unroll
@@ -1493,7 +1494,7 @@ __device__ void stage1d_seg_lds(const Geo& g, const Consts& C, const Bufs& B, co
   bool valid = false;
   double s = 0.0, rr = 1.0;
   if (f < S1_CELLS && i < g.nx) {
-    const double ih = 1.0 / h;
+    const double ih = C.idx;
     double W[3];
 #pragma unroll
     for (int v = 0; v < 3; ++v) {
@@ -1631,8 +1632,8 @@ __device__ void stage1d_seg(const Geo& g, const Consts& C, const Bufs& B, double
 #pragma unroll
       for (int v = 0; v < 3; ++v) {
         Wk[sd][0][v] = rc[((tc * 2 + side) * 3 + 0) * 3 + v];
-        Wk[sd][1][v] = rc[((tc * 2 + side) * 3 + 1) * 3 + v] / T(h);
-        Wk[sd][3][v] = rc[((tc * 2 + side) * 3 + 2) * 3 + v] / T(h * h);
+        Wk[sd][1][v] = rc[((tc * 2 + side) * 3 + 1) * 3 + v] * T(C.idx);
+        Wk[sd][3][v] = rc[((tc * 2 + side) * 3 + 2) * 3 + v] * T(C.idx2);
       }
       if (!positive_state<T, 1>(Wk[sd][0])) {
 #pragma unroll
@@ -1668,7 +1669,7 @@ __device__ void stage1d_seg(const Geo& g, const Consts& C, const Bufs& B, double
   bool valid = false;
   double s = 0.0, rr = 1.0;
   if (f < S1_CELLS && i < g.nx) {
-    const double ih = 1.0 / h;
+    const double ih = C.idx;
     double W[3];
     // every load before the first store (the arrays are distinct, which the
     // compiler cannot know)

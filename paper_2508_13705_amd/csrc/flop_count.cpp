@@ -52,6 +52,7 @@ int main() {
   Consts C;
   C.gamma = 1.4; C.Kd = 5.0; C.iKd = 0.2; C.c1 = 0.05; C.c2 = 1.0; C.mu = 1e-4; C.thres = 1.0; C.ghi = 0.85; C.glo = 0.6;
   C.eps = 1e-8; C.dx = C.dy = 1.0 / 2048; C.tau_model = 2; C.order = 9; C.m = 4;
+  C.idx = C.idy = 2048; C.idx2 = C.idy2 = 2048.0 * 2048.0;
   C.gw[0] = C.gw[1] = (1.0 - C.ghi) * (1.0 - C.glo) / 2.0; C.gw[2] = (1.0 - C.ghi) * C.glo; C.rflags = 0;
   // flux at one Gauss point (2-D and 1-D), smooth viscous state
   Fl Wl[6][4], Wr[6][4];
