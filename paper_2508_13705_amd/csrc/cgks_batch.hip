@@ -185,7 +185,7 @@ __global__ __launch_bounds__(256) void kb_bcs(const BTab* tab, int remap) {
 template <int LW, typename ST>
 __global__ __launch_bounds__(256) void kb_lines(const BTab* tab, int stage, int remap) {
   __shared__ double sm[LinesLds<LW>::total];
-  for_items(tab, PH_LINES, remap, [&](const BJob& J, int k) {
+  for_items<false>(tab, PH_LINES, remap, [&](const BJob& J, int k) {
     if (!J.B.hdr->active) return;
     const double* Uin = stage == 1 ? J.B.U : J.B.S;
     const int bx = k % J.ltx, by = k / J.ltx;

@@ -674,27 +674,29 @@ CGKS_HD __forceinline__ double dff_of(double A, double thres) { return (A < thre
 // counts as a near tie (rounding of the strengths can move A across it).
 // Only the decisions the cascade takes are judged; the DFF values
 // themselves are continuous in A.
+// A decision "DFF below 1" is taken as A > thres: for a positive threshold
+// and a finite A it is the same test (thres / A rounds below 1 exactly when
+// A > thres), without a division where the stencil is kept.
 CGKS_HD __forceinline__ Cascade cascade(const double* s, int order, double thres, double tie) {
   Cascade c;
   const double A5 = 2.0 * s[1] + 2.0 * s[2] + 2.0 * s[3] + 2.0 * s[4];
-  const double a5 = dff_of(A5, thres);
   c.tie = fabs(A5 - thres) <= tie;
-  if (a5 < 1.0) {
+  if (A5 > thres) {
     c.branch = 0;
     c.al[0] = dff_of(2.0 * s[1] + 2.0 * s[2] + s[3], thres);
     c.al[1] = dff_of(s[2] + 2.0 * s[3] + 2.0 * s[4], thres);
     c.al[2] = dff_of(s[1] + s[2] + s[3] + s[4], thres);
-    c.al[3] = a5;
+    c.al[3] = thres / A5;
     return c;
   }
   if (order == 5) { c.branch = 5; return c; }
   const double A7 = s[0] + 2.0 * s[1] + 2.0 * s[2] + 2.0 * s[3] + 2.0 * s[4] + s[5];
   c.tie = c.tie || fabs(A7 - thres) <= tie;
-  if (dff_of(A7, thres) < 1.0) { c.branch = 5; return c; }
+  if (A7 > thres) { c.branch = 5; return c; }
   if (order == 7) { c.branch = 7; return c; }
   const double A9 = 2.0 * s[0] + 2.0 * s[1] + 2.0 * s[2] + 2.0 * s[3] + 2.0 * s[4] + 2.0 * s[5];
   c.tie = c.tie || fabs(A9 - thres) <= tie;
-  c.branch = (dff_of(A9, thres) < 1.0) ? 7 : 9;
+  c.branch = A9 > thres ? 7 : 9;
   return c;
 }
 
