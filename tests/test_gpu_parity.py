@@ -255,3 +255,44 @@ def test_ghost_segments_batched_equal_alone():
         assert g["steps"] == a["steps"] == 12
         for k in ("avg", "sx", "sigx"):
             assert np.array_equal(g[k], a[k]), (pb["grid"]["nx"], k)
+
+
+# 1-D sides around the stage segments of 254 updated cells (255 faces): the
+# FP32-flux stage copies each segment's inputs into LDS by DMA, clamping the
+# stencil halo into the stored grid at the last segment.
+SEG1D = [253, 254, 255, 508, 509]
+
+
+@pytest.mark.parametrize("n", SEG1D)
+def test_fp32_flux_stage_segments_1d(n):
+    pb = W.fourier_1d(n=n, order=9, nsteps=10)
+    got, ref, _ = run_both(pb, precision="fp32_flux")
+    e = errors(got, ref, 1, cell(pb))
+    print("[parity fp32]", e, flush=True)
+    assert got["steps"] == ref["stats"]["steps"] and e["avg"] <= 1e-5 and e["sx"] <= 1e-5, e
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32_flux"])
+def test_stage_segments_shock_tube_batched_equal_alone(precision):
+    """Transmissive shock tubes of those sides (the halo clamped at both ends),
+    as jobs of one batch: bit-identical to each alone, and FP64 at parity with
+    the oracle."""
+    from paper_2508_13705_amd import cgks
+    pbs = [W.shock_tube("sod", n, 9) for n in SEG1D]
+    b = cgks.Batch(1, precision, max_jobs=len(pbs))
+    sol = [cgks.Solver(pb, precision=precision) for pb in pbs]
+    for s in sol:
+        b.add(s, max_steps=8)
+    b.commit()
+    b.step(8)
+    b.poll()
+    for pb, s in zip(pbs, sol):
+        alone = cgks.Solver(pb, precision=precision)
+        alone.step(8)
+        a, g = alone.read(), s.read()
+        assert g["steps"] == a["steps"] == 8
+        for k in ("avg", "sx", "sigx"):
+            assert np.array_equal(g[k], a[k]), (pb["grid"]["nx"], k)
+        if precision == "fp64":
+            ref = oracle.run(pb, nsteps=8)
+            assert_parity(a, ref, 1, h=cell(pb))
