@@ -206,7 +206,7 @@ __global__ __launch_bounds__(256, sizeof(T) == 4 ? 2 : 1) void kb_face(const BTa
     const int nbx = J.fnb[DIR][0], nby = J.fnb[DIR][1];
     // neighbours along x first (x-faces: normal-first, y-faces: tangential-first)
     const int bx = DIR == 0 ? k % nbx : k / nby, by = DIR == 0 ? k / nbx : k % nby;
-    face2d_tile<DIR, STAGE, M, T, false, 32, false, V>(J.g, J.C, J.B, smem, bx, by, nbx, nby);
+    face2d_tile<DIR, STAGE, M, T, false, 32, false, V, sizeof(T) == 4>(J.g, J.C, J.B, smem, bx, by, nbx, nby);
   });
 }
 
