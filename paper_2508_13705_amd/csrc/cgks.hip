@@ -91,12 +91,12 @@ __global__ __launch_bounds__(256) void k_lines(Geo g, Consts C, const double* U,
 // and share their cache lines in L2 (a y-face tile spans only NT + 2 cells
 // along x).
 template <int DIR, int STAGE, int M, typename T, bool PR>
-__global__ __launch_bounds__(256, FaceWaves<T>::value) void k_face2d(Geo g, Consts C, Bufs B) {
+__global__ __launch_bounds__(256, (FaceWaves<T, DIR, STAGE>::value)) void k_face2d(Geo g, Consts C, Bufs B) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int lb = xcd_block(blockIdx.y * gridDim.x + blockIdx.x, gridDim.x * gridDim.y);
   const int bx = DIR == 0 ? lb % gridDim.x : lb / gridDim.y;
   const int by = DIR == 0 ? lb / gridDim.x : lb % gridDim.y;
-  face2d_tile<DIR, STAGE, M, T, PR, 32, false, 0, true>(g, C, B, smem, bx, by, gridDim.x, gridDim.y);
+  face2d_tile<DIR, STAGE, M, T, PR, 32, false, 0, true, sizeof(T) == 4>(g, C, B, smem, bx, by, gridDim.x, gridDim.y);
 }
 
 template <int STAGE, typename T, bool PR>
@@ -188,18 +188,18 @@ hipError_t launch_stage2d(const cgks_plan* p, const Bufs& b, int stage, hipStrea
     hipLaunchKernelGGL((k_lines<M, T>), grid, dim3(256), 0, st, g, p->C, Uin, b.sxo, b.syo, b.lvx, b.lvy, b.hdr);
     tick(mk, st);
   }
-  const size_t lds = Lds<M, T>::total;
+  const size_t ldsx = Lds<M, T, 0, sizeof(T) == 4 ? 0 : -1>::total, ldsy = Lds<M, T, 0, sizeof(T) == 4 ? 1 : -1>::total;
   dim3 gx((g.nx + TL::NF - 2) / (TL::NF - 1), (g.ny + TL::NT - 1) / TL::NT);
   dim3 gy((g.ny + TL::NF - 2) / (TL::NF - 1), (g.nx + TL::NT - 1) / TL::NT);
   if (stage == 1) {
-    hipLaunchKernelGGL((k_face2d<0, 1, M, T, PR>), gx, dim3(256), lds, st, g, p->C, b);
+    hipLaunchKernelGGL((k_face2d<0, 1, M, T, PR>), gx, dim3(256), ldsx, st, g, p->C, b);
     tick(mk, st);
-    hipLaunchKernelGGL((k_face2d<1, 1, M, T, PR>), gy, dim3(256), lds, st, g, p->C, b);
+    hipLaunchKernelGGL((k_face2d<1, 1, M, T, PR>), gy, dim3(256), ldsy, st, g, p->C, b);
     tick(mk, st);
   } else {
-    hipLaunchKernelGGL((k_face2d<0, 2, M, T, PR>), gx, dim3(256), lds, st, g, p->C, b);
+    hipLaunchKernelGGL((k_face2d<0, 2, M, T, PR>), gx, dim3(256), ldsx, st, g, p->C, b);
     tick(mk, st);
-    hipLaunchKernelGGL((k_face2d<1, 2, M, T, PR>), gy, dim3(256), lds, st, g, p->C, b);
+    hipLaunchKernelGGL((k_face2d<1, 2, M, T, PR>), gy, dim3(256), ldsy, st, g, p->C, b);
     tick(mk, st);
   }
   return hipGetLastError();
@@ -256,7 +256,7 @@ const char* kKernels2d[] = {"dt", "bc_sigma", "bc_state", "lines", "face_x_stage
 template <int DIR, int STAGE, int M, typename T, bool PR>
 cgks_status prepare_face() {
   const void* f = (const void*)k_face2d<DIR, STAGE, M, T, PR>;
-  hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)Lds<M, T>::total);
+  hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)Lds<M, T, 0, sizeof(T) == 4 ? DIR : -1>::total);
   if (e != hipSuccess) return fail(CGKS_EHIP, std::string("hipFuncSetAttribute: ") + hipGetErrorString(e));
   return check_private(f, 0, "face kernel");
 }

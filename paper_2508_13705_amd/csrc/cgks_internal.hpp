@@ -902,7 +902,7 @@ inline int tile_nt(int v, int m) {
 // smallest stride >= n with stride mod 32 = 16 (two lines of 16 lanes on
 // disjoint bank halves), for the shapes whose strides were not enumerated
 constexpr int stride16(int n) { return n + (48 - n % 32) % 32; }
-template <int M, typename T, int V = 0> struct Lds {
+template <int M, typename T, int V = 0, int D = -1> struct Lds {
   using TL = Tile<M, V>;
   static constexpr int RS = 8 * M + 1;
   // Step 2 records of (line r, cell c): x-faces row-major, r RW + c RS;
@@ -912,7 +912,14 @@ template <int M, typename T, int V = 0> struct Lds {
   // strides RW and CS put every lane of such a group on its own bank in
   // Step 3 (found by enumerating strides against the lane layout).  The
   // second-derivative records (NT lines) use RW and cell stride CSD.
-  static constexpr int RW = V == 0 ? (M == 2 ? 304 : (M == 3 ? 432 : 592)) : stride16(TL::NC * RS);
+  // D: the records of one direction only (0 x-faces, 1 y-faces; -1 both,
+  // for kernels that serve both from one LDS size).  FP32 x-face tiles of
+  // their own (D = 0) run three blocks per CU: at M = 4 their records stay
+  // unpadded, since the padded stride would push the tile past a third of
+  // the LDS, and the third block is worth more than the conflicts the
+  // padding removes.
+  static constexpr bool PADX = V == 0 && !(D == 0 && sizeof(T) == 4 && M == 4);
+  static constexpr int RW = PADX ? (M == 2 ? 304 : (M == 3 ? 432 : 592)) : (V == 0 ? TL::NC * RS : stride16(TL::NC * RS));
   static constexpr int CS = V == 0 ? (M == 2 ? 200 : (M == 3 ? 189 : 204)) : (TL::NR * RS) | 1;
   static constexpr int CSD = TL::NT * RS;
   static_assert(RW >= TL::NC * RS && CS >= TL::NR * RS, "records do not overlap");
@@ -920,9 +927,11 @@ template <int M, typename T, int V = 0> struct Lds {
   static constexpr int NSTV = 4 * M * TL::NR * NCS;   // per staged array
   static constexpr size_t a8(size_t x) { return (x + 7) / 8 * 8; }
   static constexpr size_t mx(size_t a, size_t b) { return a > b ? a : b; }
-  static constexpr size_t s2v = mx((size_t)TL::NR * RW, (size_t)TL::NC * CS) * sizeof(T);   // both layouts
+  static constexpr size_t XW = D == 1 ? 0 : (size_t)TL::NR * RW, YW = D == 0 ? 0 : (size_t)TL::NC * CS;
+  static constexpr size_t XD = D == 1 ? 0 : (size_t)TL::NT * RW, YD = D == 0 ? 0 : (size_t)TL::NC * CSD;
+  static constexpr size_t s2v = mx(XW, YW) * sizeof(T);
   static constexpr size_t s2d = s2v;
-  static constexpr size_t s2dd = mx((size_t)TL::NT * RW, (size_t)TL::NC * CSD) * sizeof(T);
+  static constexpr size_t s2dd = mx(XD, YD) * sizeof(T);
   static constexpr size_t recon = a8(s2v + s2d + s2dd);
   static constexpr size_t st_sg = a8(2 * NSTV * sizeof(T));          // offset of the strengths in staging
   static constexpr size_t staging = st_sg + (size_t)TL::NR * NSG * sizeof(double);
@@ -936,13 +945,24 @@ template <int M, typename T, int V = 0> struct Lds {
   static constexpr size_t total = off_atab + (size_t)TL::NC * TL::NT * sizeof(T);
 };
 
-// Waves per SIMD the face kernels are compiled for.  Both variants fit their
-// registers without spilling to scratch (FP64 with the whole register file of
-// one wave per SIMD, FP32 with half of it); the library checks at start-up
-// that no face kernel uses private memory.
-template <typename T> struct FaceWaves {
-  static constexpr int value = sizeof(T) == 8 ? 1 : 2;
+// Waves per SIMD the single-grid face kernels are compiled for, each without
+// spilling to scratch: FP64 with the whole register file of one wave per
+// SIMD; FP32 with a third of it, and with the LDS of an x-face tile three
+// blocks share a CU, except the y-face stage-1 kernel, which needs about 200
+// registers and runs two waves.  (The batched face kernels, whose persistent
+// loop and job descriptors add registers, run two FP32 waves.)  The library
+// checks at start-up that no face kernel uses private memory.
+template <typename T, int DIR = 0, int STAGE = 2> struct FaceWaves {
+  static constexpr int value = sizeof(T) == 8 ? 1 : (DIR == 1 && STAGE == 1 ? 2 : 3);
 };
+// three FP32 x-face tiles, with their static LDS (the tally) and the
+// allocation rounded up to 1280 bytes, fit one CU (a tile of 53.5 KB runs
+// three blocks per CU, one of 54.2 KB two)
+constexpr size_t lds_alloc(size_t b) { return (b + 1279) / 1280 * 1280; }
+static_assert(lds_alloc(Lds<2, float, 0, 0>::total + sizeof(Tally)) <= 160 * 1024 / 3 &&
+                  lds_alloc(Lds<3, float, 0, 0>::total + sizeof(Tally)) <= 160 * 1024 / 3 &&
+                  lds_alloc(Lds<4, float, 0, 0>::total + sizeof(Tally)) <= 160 * 1024 / 3,
+              "FP32 x-face tiles fit three blocks per CU");
 
 // Step 3 tangential-fit weights in the working precision (float copies of
 // the tables for the FP32-flux variant: no conversion per use)
@@ -957,11 +977,11 @@ __device__ __forceinline__ T tanw(int m, int l, int k) {
 // whose loads are issued together (all of them where registers allow; the
 // persistent batched kernels keep more per-job state live and take fewer).
 template <int DIR, int STAGE, int M, typename T, bool PR, int SU = 32, bool PERSIST = false, int V = 0,
-          bool UNROLL = false>
+          bool UNROLL = false, bool OWN = false>
 __device__ void face2d_tile(const Geo& g, const Consts& C, const Bufs& B, unsigned char* smem, int bx, int by,
                             int nbx, int nby) {
   using TL = Tile<M, V>;
-  using LD = Lds<M, T, V>;
+  using LD = Lds<M, T, V, OWN ? DIR : -1>;
   constexpr int NF = TL::NF, NT = TL::NT, NC = TL::NC, NR = TL::NR;
   const gptr<const Header> hdr = glb((const Header*)B.hdr);
   __shared__ Tally tally;
