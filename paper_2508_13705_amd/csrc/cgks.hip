@@ -123,7 +123,7 @@ __global__ __launch_bounds__(256) void k_sum2(int nv, const DD* part, int nblk, 
   sums_pass2(nv, part, nblk, out);
 }
 
-__global__ void k_reduce(Geo g, double gam, const double* U, Bufs B) {
+__global__ __launch_bounds__(256) void k_reduce(Geo g, double gam, const double* U, Bufs B) {
   Header* hdr = B.hdr;
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   const int j = blockIdx.y;
@@ -188,18 +188,20 @@ hipError_t launch_stage2d(const cgks_plan* p, const Bufs& b, int stage, hipStrea
     hipLaunchKernelGGL((k_lines<M, T>), grid, dim3(256), 0, st, g, p->C, Uin, b.sxo, b.syo, b.lvx, b.lvy, b.hdr);
     tick(mk, st);
   }
-  const size_t ldsx = Lds<M, T, 0, sizeof(T) == 4 ? 0 : -1>::total, ldsy = Lds<M, T, 0, sizeof(T) == 4 ? 1 : -1>::total;
+  constexpr bool own = sizeof(T) == 4;
+  constexpr size_t lx1 = FaceLds<0, 1, M, T, 0, own>::total, ly1 = FaceLds<1, 1, M, T, 0, own>::total;
+  constexpr size_t lx2 = FaceLds<0, 2, M, T, 0, own>::total, ly2 = FaceLds<1, 2, M, T, 0, own>::total;
   dim3 gx((g.nx + TL::NF - 2) / (TL::NF - 1), (g.ny + TL::NT - 1) / TL::NT);
   dim3 gy((g.ny + TL::NF - 2) / (TL::NF - 1), (g.nx + TL::NT - 1) / TL::NT);
   if (stage == 1) {
-    hipLaunchKernelGGL((k_face2d<0, 1, M, T, PR>), gx, dim3(256), ldsx, st, g, p->C, b);
+    hipLaunchKernelGGL((k_face2d<0, 1, M, T, PR>), gx, dim3(256), lx1, st, g, p->C, b);
     tick(mk, st);
-    hipLaunchKernelGGL((k_face2d<1, 1, M, T, PR>), gy, dim3(256), ldsy, st, g, p->C, b);
+    hipLaunchKernelGGL((k_face2d<1, 1, M, T, PR>), gy, dim3(256), ly1, st, g, p->C, b);
     tick(mk, st);
   } else {
-    hipLaunchKernelGGL((k_face2d<0, 2, M, T, PR>), gx, dim3(256), ldsx, st, g, p->C, b);
+    hipLaunchKernelGGL((k_face2d<0, 2, M, T, PR>), gx, dim3(256), lx2, st, g, p->C, b);
     tick(mk, st);
-    hipLaunchKernelGGL((k_face2d<1, 2, M, T, PR>), gy, dim3(256), ldsy, st, g, p->C, b);
+    hipLaunchKernelGGL((k_face2d<1, 2, M, T, PR>), gy, dim3(256), ly2, st, g, p->C, b);
     tick(mk, st);
   }
   return hipGetLastError();
@@ -256,7 +258,7 @@ const char* kKernels2d[] = {"dt", "bc_sigma", "bc_state", "lines", "face_x_stage
 template <int DIR, int STAGE, int M, typename T, bool PR>
 cgks_status prepare_face() {
   const void* f = (const void*)k_face2d<DIR, STAGE, M, T, PR>;
-  hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)Lds<M, T, 0, sizeof(T) == 4 ? DIR : -1>::total);
+  hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)FaceLds<DIR, STAGE, M, T, 0, sizeof(T) == 4>::total);
   if (e != hipSuccess) return fail(CGKS_EHIP, std::string("hipFuncSetAttribute: ") + hipGetErrorString(e));
   return check_private(f, 0, "face kernel");
 }

@@ -464,8 +464,11 @@ __device__ __forceinline__ void tally_flush(const Tally& t, Header* hdr, int tid
 // ---------------------------------------------------------------------------
 // Block-level max(|U| + c) and min(rho); thread 0 writes the block's partial
 // (reduced by k_dt before the next step).  Called by every thread of the block.
+struct SpeedRed {
+  double v[2][4];   // per wave of a block of at most 256 threads
+};
 __device__ __forceinline__ void reduce_speed(const Bufs& B, double s, double r, bool valid, int bid, int nparts) {
-  __shared__ double red[2][16];
+  __shared__ SpeedRed red;
   double sm = valid ? s : 0.0;
   double rm = valid ? r : INFINITY;
   for (int off = 32; off > 0; off >>= 1) {
@@ -473,10 +476,10 @@ __device__ __forceinline__ void reduce_speed(const Bufs& B, double s, double r, 
     rm = fmin(rm, __shfl_xor(rm, off, 64));
   }
   const int w = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
-  if ((threadIdx.x & 63) == 0) { red[0][w] = sm; red[1][w] = rm; }
+  if ((threadIdx.x & 63) == 0) { red.v[0][w] = sm; red.v[1][w] = rm; }
   __syncthreads();
   if (threadIdx.x == 0) {
-    for (int k = 1; k < nw; ++k) { sm = fmax(sm, red[0][k]); rm = fmin(rm, red[1][k]); }
+    for (int k = 1; k < nw; ++k) { sm = fmax(sm, red.v[0][k]); rm = fmin(rm, red.v[1][k]); }
     const gptr<double> part = glb(B.part);
     part[2 * bid] = sm;
     part[2 * bid + 1] = rm;
@@ -902,7 +905,7 @@ inline int tile_nt(int v, int m) {
 // smallest stride >= n with stride mod 32 = 16 (two lines of 16 lanes on
 // disjoint bank halves), for the shapes whose strides were not enumerated
 constexpr int stride16(int n) { return n + (48 - n % 32) % 32; }
-template <int M, typename T, int V = 0, int D = -1> struct Lds {
+template <int M, typename T, int V = 0, int D = -1, bool OCC3 = false> struct Lds {
   using TL = Tile<M, V>;
   static constexpr int RS = 8 * M + 1;
   // Step 2 records of (line r, cell c): x-faces row-major, r RW + c RS;
@@ -913,14 +916,13 @@ template <int M, typename T, int V = 0, int D = -1> struct Lds {
   // Step 3 (found by enumerating strides against the lane layout).  The
   // second-derivative records (NT lines) use RW and cell stride CSD.
   // D: the records of one direction only (0 x-faces, 1 y-faces; -1 both,
-  // for kernels that serve both from one LDS size).  FP32 x-face tiles of
-  // their own (D = 0) run three blocks per CU: at M = 4 their records stay
-  // unpadded, since the padded stride would push the tile past a third of
-  // the LDS, and the third block is worth more than the conflicts the
-  // padding removes.
-  static constexpr bool PADX = V == 0 && !(D == 0 && sizeof(T) == 4 && M == 4);
-  static constexpr int RW = PADX ? (M == 2 ? 304 : (M == 3 ? 432 : 592)) : (V == 0 ? TL::NC * RS : stride16(TL::NC * RS));
-  static constexpr int CS = V == 0 ? (M == 2 ? 200 : (M == 3 ? 189 : 204)) : (TL::NR * RS) | 1;
+  // for kernels that serve both from one LDS size).  OCC3: the tile runs
+  // three blocks per CU; at M = 4 its records then stay unpadded, since the
+  // padded stride would push the tile past a third of the LDS, and the
+  // third block is worth more than the conflicts the padding removes.
+  static constexpr bool PAD = V == 0 && !(OCC3 && M == 4);
+  static constexpr int RW = PAD ? (M == 2 ? 304 : (M == 3 ? 432 : 592)) : (V == 0 ? TL::NC * RS : stride16(TL::NC * RS));
+  static constexpr int CS = PAD ? (M == 2 ? 200 : (M == 3 ? 189 : 204)) : (TL::NR * RS) | 1;
   static constexpr int CSD = TL::NT * RS;
   static_assert(RW >= TL::NC * RS && CS >= TL::NR * RS, "records do not overlap");
   static constexpr int NCS = TL::NC + 4, NSG = TL::NC + 5;
@@ -955,14 +957,21 @@ template <int M, typename T, int V = 0, int D = -1> struct Lds {
 template <typename T, int DIR = 0, int STAGE = 2> struct FaceWaves {
   static constexpr int value = sizeof(T) == 8 ? 1 : (DIR == 1 && STAGE == 1 ? 2 : 3);
 };
-// three FP32 x-face tiles, with their static LDS (the tally) and the
-// allocation rounded up to 1280 bytes, fit one CU (a tile of 53.5 KB runs
-// three blocks per CU, one of 54.2 KB two)
+// LDS layout of a face tile; OWN: a single-grid kernel, sized for its own
+// direction and wave count
+template <int DIR, int STAGE, int M, typename T, int V, bool OWN>
+using FaceLds = Lds<M, T, V, OWN ? DIR : -1, OWN && FaceWaves<T, DIR, STAGE>::value == 3>;
+// three FP32 tiles of the three-wave kernels, with their static LDS (the
+// tally, and the speed reduction at stage 2) and the allocation rounded up
+// to 1280 bytes, fit one CU (a tile of 53.5 KB runs three blocks per CU, one
+// of 54.2 KB two)
 constexpr size_t lds_alloc(size_t b) { return (b + 1279) / 1280 * 1280; }
-static_assert(lds_alloc(Lds<2, float, 0, 0>::total + sizeof(Tally)) <= 160 * 1024 / 3 &&
-                  lds_alloc(Lds<3, float, 0, 0>::total + sizeof(Tally)) <= 160 * 1024 / 3 &&
-                  lds_alloc(Lds<4, float, 0, 0>::total + sizeof(Tally)) <= 160 * 1024 / 3,
-              "FP32 x-face tiles fit three blocks per CU");
+template <int M> constexpr bool fits3() {
+  return lds_alloc(FaceLds<0, 2, M, float, 0, true>::total + sizeof(Tally) + sizeof(SpeedRed)) <= 160 * 1024 / 3 &&
+         lds_alloc(FaceLds<1, 2, M, float, 0, true>::total + sizeof(Tally) + sizeof(SpeedRed)) <= 160 * 1024 / 3 &&
+         lds_alloc(FaceLds<0, 1, M, float, 0, true>::total + sizeof(Tally)) <= 160 * 1024 / 3;
+}
+static_assert(fits3<2>() && fits3<3>() && fits3<4>(), "FP32 three-wave face tiles fit three blocks per CU");
 
 // Step 3 tangential-fit weights in the working precision (float copies of
 // the tables for the FP32-flux variant: no conversion per use)
@@ -981,7 +990,7 @@ template <int DIR, int STAGE, int M, typename T, bool PR, int SU = 32, bool PERS
 __device__ void face2d_tile(const Geo& g, const Consts& C, const Bufs& B, unsigned char* smem, int bx, int by,
                             int nbx, int nby) {
   using TL = Tile<M, V>;
-  using LD = Lds<M, T, V, OWN ? DIR : -1>;
+  using LD = FaceLds<DIR, STAGE, M, T, V, OWN>;
   constexpr int NF = TL::NF, NT = TL::NT, NC = TL::NC, NR = TL::NR;
   const gptr<const Header> hdr = glb((const Header*)B.hdr);
   __shared__ Tally tally;
