@@ -658,6 +658,12 @@ __device__ __forceinline__ int tile_tid() {
   asm volatile("" : "+v"(t));
   return t;
 }
+// a value the compiler must take as new at this point, so that it does not
+// keep what it derived from the value earlier live until here
+__device__ __forceinline__ double fresh(double x) {
+  asm volatile("" : "+v"(x));
+  return x;
+}
 
 // Step 1 over a tile of LT_X x LT_Y cells (x fastest; block of 256 threads,
 // one cell each) with its inputs staged in LDS: the cell averages on the
@@ -949,13 +955,12 @@ template <int M, typename T, int V = 0, int D = -1, bool OCC3 = false> struct Ld
 
 // Waves per SIMD the single-grid face kernels are compiled for, each without
 // spilling to scratch: FP64 with the whole register file of one wave per
-// SIMD; FP32 with a third of it, and with the LDS of an x-face tile three
-// blocks share a CU, except the y-face stage-1 kernel, which needs about 200
-// registers and runs two waves.  (The batched face kernels, whose persistent
-// loop and job descriptors add registers, run two FP32 waves.)  The library
-// checks at start-up that no face kernel uses private memory.
+// SIMD; FP32 with a third of it (168 registers), three blocks sharing a CU.
+// (The batched face kernels, whose persistent loop and job descriptors add
+// registers, run two FP32 waves.)  The library checks at start-up that no
+// face kernel uses private memory.
 template <typename T, int DIR = 0, int STAGE = 2> struct FaceWaves {
-  static constexpr int value = sizeof(T) == 8 ? 1 : (DIR == 1 && STAGE == 1 ? 2 : 3);
+  static constexpr int value = sizeof(T) == 8 ? 1 : 3;
 };
 // LDS layout of a face tile; OWN: a single-grid kernel, sized for its own
 // direction and wave count
@@ -969,7 +974,8 @@ constexpr size_t lds_alloc(size_t b) { return (b + 1279) / 1280 * 1280; }
 template <int M> constexpr bool fits3() {
   return lds_alloc(FaceLds<0, 2, M, float, 0, true>::total + sizeof(Tally) + sizeof(SpeedRed)) <= 160 * 1024 / 3 &&
          lds_alloc(FaceLds<1, 2, M, float, 0, true>::total + sizeof(Tally) + sizeof(SpeedRed)) <= 160 * 1024 / 3 &&
-         lds_alloc(FaceLds<0, 1, M, float, 0, true>::total + sizeof(Tally)) <= 160 * 1024 / 3;
+         lds_alloc(FaceLds<0, 1, M, float, 0, true>::total + sizeof(Tally)) <= 160 * 1024 / 3 &&
+         lds_alloc(FaceLds<1, 1, M, float, 0, true>::total + sizeof(Tally)) <= 160 * 1024 / 3;
 }
 static_assert(fits3<2>() && fits3<3>() && fits3<4>(), "FP32 three-wave face tiles fit three blocks per CU");
 
@@ -1149,9 +1155,11 @@ __device__ void face2d_tile(const Geo& g, const Consts& C, const Bufs& B, unsign
 
   // ---- Steps 3-4 at every face Gauss point: one Gauss point per thread ----
   static_assert(NB <= 256, "one Gauss point per thread of a 256-thread block");
-  // as in Step 2, lanes without a Gauss point of their own compute one of the
-  // tile's (f = r = 0 at their wave's node l, always inside the grid) and
-  // store nothing
+  // as in Step 2, lanes without a Gauss point of their own compute at face
+  // f = 0 of line r = 0 (always inside the grid) and store nothing.  They
+  // keep their wave's node index l; at M = 3 the lanes past the tile's last
+  // Gauss point (NB < 256) have l = M, a node whose tangential-fit weights are
+  // zero in the tables, and read only LDS of the tile
   const int it = tx;
   int f, r, l;
   if (DIR == 0) { f = it % NF; r = (it / NF) % NT; l = it / (NF * NT); }
@@ -1161,7 +1169,7 @@ __device__ void face2d_tile(const Geo& g, const Consts& C, const Bufs& B, unsign
   // scalar loads
   if ((NF * NT) % 64 == 0) l = __builtin_amdgcn_readfirstlane(l);
   const bool own = it < NB && F0 + f <= nmax && T0 + r < tmax;
-  if (!own) { f = 0; r = 0; }   // keeps l: Gauss point (0, 0, l) lies in the tile
+  if (!own) { f = 0; r = 0; }
   {
     const int nf = F0 + f, t = T0 + r;
     T Wk[2][6][4];
@@ -1291,8 +1299,11 @@ __device__ void face2d_tile(const Geo& g, const Consts& C, const Bufs& B, unsign
   }
   if (DIR == 1) {
     __syncthreads();
-    // health and (stage 2) the speed reduction for the next time step
-    const int it = tx;
+    // health and (stage 2) the speed reduction for the next time step.  In
+    // the single-grid kernels the lane's cell indices and gamma are taken
+    // afresh (tile_tid, fresh): shared with Step 3, what is derived from them
+    // would stay live in registers through the flux
+    const int it = OWN ? tile_tid() : tx;
     bool valid = false;
     double s = 0.0, rr = 1.0;
     if (it < (NF - 1) * NT) {
@@ -1302,7 +1313,7 @@ __device__ void face2d_tile(const Geo& g, const Consts& C, const Bufs& B, unsign
         double W[4];
         for (int v = 0; v < 4; ++v) W[v] = fin[v * NFT + ci * NT + r];
         rr = W[0];
-        valid = cell_speed(W, 2, C.gamma, s);
+        valid = cell_speed(W, 2, OWN ? fresh(C.gamma) : C.gamma, s);
         if (!valid) atomicAdd((unsigned long long*)&B.hdr->nonphysical, 1ull);
       }
     }
