@@ -272,7 +272,7 @@ def bench_batch_2d(n, steps, precision, order=9):
     q = cgks.Solver(pb, precision=precision, stream=stream)
     B.add(q, max_steps=10 ** 6)
     B.commit()
-    tuning = B.tune(1)
+    tuning = B.tune(3)
     gs = 5
     B.capture(gs)
     B.launch()

@@ -8,7 +8,11 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libcgks.so")
 OBJ = os.path.join(HERE, "_build")
-SOURCES = ["cgks.hip", "cgks_batch.hip"]
+SOURCES = ["cgks.hip", "cgks_batch.hip", "cgks_batch_f32.hip"]
+# per-source flags: the batched FP32 face kernels without machine
+# loop-invariant code motion (it would hold the flux's FP64 constants in
+# vector registers across their persistent loop)
+EXTRA_FLAGS = {"cgks_batch_f32.hip": ["-mllvm", "-disable-machine-licm"]}
 
 HIPCC_FLAGS = ["-O3", "--offload-arch=gfx950", "-std=c++17", "-fPIC",
                # multiply-adds fused only within a source expression: every
@@ -34,7 +38,8 @@ def build(verbose=False):
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
     os.makedirs(OBJ, exist_ok=True)
     objs = [os.path.join(OBJ, os.path.splitext(s)[0] + ".o") for s in SOURCES]
-    cmds = [[hipcc] + HIPCC_FLAGS + ["-c", "-o", o, os.path.join(CSRC, s)] for s, o in zip(SOURCES, objs)]
+    cmds = [[hipcc] + HIPCC_FLAGS + EXTRA_FLAGS.get(s, []) + ["-c", "-o", o, os.path.join(CSRC, s)]
+            for s, o in zip(SOURCES, objs)]
     with ThreadPoolExecutor(len(cmds)) as ex:
         list(ex.map(_run, cmds))
     tmp = LIB + ".tmp"

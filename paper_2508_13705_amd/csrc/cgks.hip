@@ -90,13 +90,18 @@ __global__ __launch_bounds__(256) void k_lines(Geo g, Consts C, const double* U,
 // tiles that run together are neighbours along x, the contiguous direction,
 // and share their cache lines in L2 (a y-face tile spans only NT + 2 cells
 // along x).
+// FP32 kernels: the LDS layout of their own direction, for their wave count
+// (FP64 keeps the shared layout)
+template <typename T, int DIR, int STAGE>
+constexpr int kOwnW = sizeof(T) == 4 ? FaceWaves<T, DIR, STAGE>::value : 0;
+
 template <int DIR, int STAGE, int M, typename T, bool PR>
 __global__ __launch_bounds__(256, (FaceWaves<T, DIR, STAGE>::value)) void k_face2d(Geo g, Consts C, Bufs B) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int lb = xcd_block(blockIdx.y * gridDim.x + blockIdx.x, gridDim.x * gridDim.y);
   const int bx = DIR == 0 ? lb % gridDim.x : lb / gridDim.y;
   const int by = DIR == 0 ? lb / gridDim.x : lb % gridDim.y;
-  face2d_tile<DIR, STAGE, M, T, PR, 32, false, 0, true, sizeof(T) == 4>(g, C, B, smem, bx, by, gridDim.x, gridDim.y);
+  face2d_tile<DIR, STAGE, M, T, PR, 32, false, 0, true, kOwnW<T, DIR, STAGE>>(g, C, B, smem, bx, by, gridDim.x, gridDim.y);
 }
 
 template <int STAGE, typename T, bool PR>
@@ -188,9 +193,8 @@ hipError_t launch_stage2d(const cgks_plan* p, const Bufs& b, int stage, hipStrea
     hipLaunchKernelGGL((k_lines<M, T>), grid, dim3(256), 0, st, g, p->C, Uin, b.sxo, b.syo, b.lvx, b.lvy, b.hdr);
     tick(mk, st);
   }
-  constexpr bool own = sizeof(T) == 4;
-  constexpr size_t lx1 = FaceLds<0, 1, M, T, 0, own>::total, ly1 = FaceLds<1, 1, M, T, 0, own>::total;
-  constexpr size_t lx2 = FaceLds<0, 2, M, T, 0, own>::total, ly2 = FaceLds<1, 2, M, T, 0, own>::total;
+  constexpr size_t lx1 = FaceLds<0, M, T, 0, kOwnW<T, 0, 1>>::total, ly1 = FaceLds<1, M, T, 0, kOwnW<T, 1, 1>>::total;
+  constexpr size_t lx2 = FaceLds<0, M, T, 0, kOwnW<T, 0, 2>>::total, ly2 = FaceLds<1, M, T, 0, kOwnW<T, 1, 2>>::total;
   dim3 gx((g.nx + TL::NF - 2) / (TL::NF - 1), (g.ny + TL::NT - 1) / TL::NT);
   dim3 gy((g.ny + TL::NF - 2) / (TL::NF - 1), (g.nx + TL::NT - 1) / TL::NT);
   if (stage == 1) {
@@ -258,7 +262,7 @@ const char* kKernels2d[] = {"dt", "bc_sigma", "bc_state", "lines", "face_x_stage
 template <int DIR, int STAGE, int M, typename T, bool PR>
 cgks_status prepare_face() {
   const void* f = (const void*)k_face2d<DIR, STAGE, M, T, PR>;
-  hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)FaceLds<DIR, STAGE, M, T, 0, sizeof(T) == 4>::total);
+  hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)FaceLds<DIR, M, T, 0, kOwnW<T, DIR, STAGE>>::total);
   if (e != hipSuccess) return fail(CGKS_EHIP, std::string("hipFuncSetAttribute: ") + hipGetErrorString(e));
   return check_private(f, 0, "face kernel");
 }

@@ -18,124 +18,9 @@
 #include <algorithm>
 #include <chrono>
 
+#include "cgks_batch.hpp"
+
 namespace {
-
-// Phases of a step, in launch order (2-D; 1-D uses DT, PREP, S1D1, BCS, S1D2).
-// The face phases are per order m: each has a kernel compiled for that m
-// alone, which keeps its registers within the register file.
-enum Phase { PH_DT = 0, PH_PREP, PH_LINES, PH_FX2, PH_FX3, PH_FX4, PH_FY2, PH_FY3, PH_FY4, PH_BCS, PH_S1D, NPH };
-constexpr int ph_face(int dir, int m) { return (dir == 0 ? PH_FX2 : PH_FY2) + (m - 2); }
-
-struct BJob {
-  Geo g;
-  Consts C;
-  Bufs B;
-  double dt_fixed, cfl, t_end, h;
-  double sbc;              // largest |U| + c of the job's prescribed boundary states
-  long long max_steps;
-  int viscous, M, slot, pad;
-  int ax, ay;              // 256-wide segments per row: sigma x-faces, sigma y-faces
-  int nsx, nsy;            // PREP items of the sigma x / y parts
-  int fnb[2][2];           // face tiles (along normal, along tangential) of x- and y-faces
-  int ltx, lty;            // Step 1 tiles along x and y
-  int nseg;                // 1-D stage segments
-  int ns;                  // ghost-cell items (GhostItems)
-};
-
-struct S1Item {
-  int job, seg;   // job (table order), item index within the job
-};
-
-struct BTab {
-  int njobs, cap;
-  int total[NPH];
-  BJob* jobs;      // [cap], table order
-  int* pre;        // [NPH][cap + 1] prefix sums of the items per job
-  JobStat* stat;   // [cap], by slot
-  // 1-D: the (job, index in the job) of every item of each phase, at
-  // imap + ioff[phase] (null in 2-D, whose batches hold few jobs); a 1-D
-  // batch has thousands of jobs of a few items each, and a binary search of
-  // the prefix sums would cost a dozen dependent loads per item
-  S1Item* imap;
-  int ioff[NPH];
-};
-
-// Largest j in [0, n) with pre[j] <= item (pre[0] = 0, pre[n] = total).
-template <class P>
-__device__ __forceinline__ int find_job(P pre, int n, int item) {
-  int lo = 0, hi = n;
-  while (hi - lo > 1) {
-    const int mid = (lo + hi) >> 1;
-    if (pre[mid] <= item) lo = mid;
-    else hi = mid;
-  }
-  return lo;
-}
-
-// A job's descriptor, read in place through a pointer of constant type: the
-// table does not change while a kernel runs, so its fields are scalar loads
-// that the compiler may repeat where they are used, as it does with kernel
-// arguments, instead of holding the whole descriptor in registers across a
-// tile (through the generic table pointer they would be FLAT loads, which
-// count against the LDS counter).  The host pass, which cannot form that
-// address space, reads it directly.
-__device__ __forceinline__ const BJob& job_ref(const BTab* tab, int j) {
-#if defined(__HIP_DEVICE_COMPILE__)
-  using cjob = const __attribute__((address_space(4))) BJob*;
-  return *(const BJob*)((cjob)tab->jobs + j);
-#else
-  return tab->jobs[j];
-#endif
-}
-
-// Persistent loop over the items of a phase.  With remap, blocks that the
-// dispatcher places on one XCD (block b runs on XCD b mod 8) take
-// consecutive items, so neighbouring tiles of a grid share that XCD's L2.
-// CREF: read the job descriptor in place through a constant pointer (the
-// default), or copy it (the FP64 face kernels, whose registers are full:
-// there the in-place reads cost scratch).
-// MAP: the phase may run in a 1-D batch, whose items come from the item map
-// when it is present (the 2-D-only kernels leave the branch out: their
-// scalar registers are full).
-template <bool CREF = true, bool MAP = false, class F>
-__device__ __forceinline__ void for_items(const BTab* tab, int ph, int remap, F&& f) {
-  const int total = tab->total[ph];
-  const int G = gridDim.x;
-  int lb = blockIdx.x;
-  if (remap) lb = (blockIdx.x & 7) * (G >> 3) + (blockIdx.x >> 3);   // G is a multiple of 8
-  const int n = tab->njobs;
-  const gptr<const int> pre = glb((const int*)tab->pre) + (size_t)ph * (tab->cap + 1);
-  const S1Item* imap = MAP ? tab->imap : nullptr;
-  for (int item = lb; item < total; item += G) {
-    // the job and tile are the same for the whole block: made wave-uniform,
-    // the job descriptor comes through scalar loads instead of occupying
-    // vector registers.  1-D batches read them from the item map.
-    int j, k;
-    if (MAP && imap) {
-#if defined(__HIP_DEVICE_COMPILE__)
-      const S1Item e = glb(imap)[tab->ioff[ph] + item];
-#else
-      const S1Item e = imap[tab->ioff[ph] + item];
-#endif
-      j = __builtin_amdgcn_readfirstlane(e.job);
-      k = __builtin_amdgcn_readfirstlane(e.seg);
-    } else {
-      j = __builtin_amdgcn_readfirstlane(find_job(pre, n, item));
-      k = __builtin_amdgcn_readfirstlane(item - pre[j]);
-    }
-#if defined(__HIP_DEVICE_COMPILE__)
-    if (CREF) {
-      f(job_ref(tab, j), k);
-    } else {
-      // a copy, read through a pointer of global type: scalar loads
-      const BJob J = glb((const BJob*)tab->jobs)[j];
-      f(J, k);
-    }
-#else
-    f(tab->jobs[j], k);
-#endif
-  }
-}
 
 __global__ __launch_bounds__(256) void kb_dt(const BTab* tab) {
   const int n = tab->njobs;
@@ -197,18 +82,6 @@ __global__ __launch_bounds__(256) void kb_lines(const BTab* tab, int stage, int 
   });
 }
 
-// Fused reconstruction + flux + update of one direction and stage over the
-// face tiles (shape V) of every job of order m = M.
-template <int DIR, int STAGE, typename T, int M, int V>
-__global__ __launch_bounds__(256, sizeof(T) == 4 ? 2 : 1) void kb_face(const BTab* tab, int remap) {
-  extern __shared__ __align__(16) unsigned char smem[];
-  for_items<sizeof(T) == 4>(tab, ph_face(DIR, M), remap, [&](const BJob& J, int k) {
-    const int nbx = J.fnb[DIR][0], nby = J.fnb[DIR][1];
-    // neighbours along x first (x-faces: normal-first, y-faces: tangential-first)
-    const int bx = DIR == 0 ? k % nbx : k / nby, by = DIR == 0 ? k / nbx : k % nby;
-    face2d_tile<DIR, STAGE, M, T, false, 32, false, V, sizeof(T) == 4>(J.g, J.C, J.B, smem, bx, by, nbx, nby);
-  });
-}
 
 // One stage of the 1-D scheme over the segments of every job.
 template <int STAGE, typename T>
@@ -315,7 +188,7 @@ void set_grids(cgks_batch* b) {
 template <int DIR, int STAGE, typename T, int M, int V>
 cgks_status prepare_bface() {
   const void* f = (const void*)kb_face<DIR, STAGE, T, M, V>;
-  hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)Lds<M, T, V>::total);
+  hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kb_face_lds<DIR, STAGE, T, M, V>());
   if (e != hipSuccess) return fail(CGKS_EHIP, std::string("hipFuncSetAttribute: ") + hipGetErrorString(e));
   return check_private(f, 0, "batched face kernel");
 }
@@ -340,9 +213,13 @@ cgks_status prepare_bshape() {
 template <typename T>
 cgks_status prepare_batch() {
   cgks_status s;
-  if ((s = prepare_bshape<T, 0>()) != CGKS_OK) return s;
-  if ((s = prepare_bshape<T, 1>()) != CGKS_OK) return s;
-  if ((s = prepare_bshape<T, 2>()) != CGKS_OK) return s;
+  if constexpr (sizeof(T) == 4) {
+    if ((s = cgks_bf32::prepare()) != CGKS_OK) return s;
+  } else {
+    if ((s = prepare_bshape<T, 0>()) != CGKS_OK) return s;
+    if ((s = prepare_bshape<T, 1>()) != CGKS_OK) return s;
+    if ((s = prepare_bshape<T, 2>()) != CGKS_OK) return s;
+  }
   const void* k[] = {(const void*)kb_dt, (const void*)kb_prep<T>, (const void*)kb_bcs<T>, (const void*)kb_lines<0, T>,
                      (const void*)kb_lines<1, T>, (const void*)kb_stage1d<1, T>, (const void*)kb_stage1d<2, T>};
   for (const void* f : k)
@@ -358,25 +235,29 @@ hipError_t occupancy(cgks_batch* b) {
   if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&b->occ[K_BCS], kb_bcs<T>, 256, 0))) return e;
   if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&b->occ_lines[0], kb_lines<0, T>, 256, 0))) return e;
   if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&b->occ_lines[1], kb_lines<1, T>, 256, 0))) return e;
-  // the face grid serves every order: size it by the order that fits the
-  // fewest blocks (the largest LDS tile)
-  auto face_occ = [&](const void* f2, size_t l2, const void* f3, size_t l3, const void* f4, size_t l4, int* out) {
-    int a = 0, c = 0, d = 0;
-    hipError_t r = hipOccupancyMaxActiveBlocksPerMultiprocessor(&a, f2, 256, l2);
-    if (r == hipSuccess) r = hipOccupancyMaxActiveBlocksPerMultiprocessor(&c, f3, 256, l3);
-    if (r == hipSuccess) r = hipOccupancyMaxActiveBlocksPerMultiprocessor(&d, f4, 256, l4);
-    *out = std::min(a, std::min(c, d));
-    return r;
-  };
-  if ((e = face_occ((const void*)kb_face<1, 2, T, 2, 0>, Lds<2, T, 0>::total, (const void*)kb_face<1, 2, T, 3, 0>,
-                    Lds<3, T, 0>::total, (const void*)kb_face<1, 2, T, 4, 0>, Lds<4, T, 0>::total, &b->occ_face[0])))
-    return e;
-  if ((e = face_occ((const void*)kb_face<1, 2, T, 2, 1>, Lds<2, T, 1>::total, (const void*)kb_face<1, 2, T, 3, 1>,
-                    Lds<3, T, 1>::total, (const void*)kb_face<1, 2, T, 4, 1>, Lds<4, T, 1>::total, &b->occ_face[1])))
-    return e;
-  if ((e = face_occ((const void*)kb_face<1, 2, T, 2, 2>, Lds<2, T, 2>::total, (const void*)kb_face<1, 2, T, 3, 2>,
-                    Lds<3, T, 2>::total, (const void*)kb_face<1, 2, T, 4, 2>, Lds<4, T, 2>::total, &b->occ_face[2])))
-    return e;
+  if constexpr (sizeof(T) == 4) {
+    if ((e = cgks_bf32::occupancy(b->occ_face))) return e;
+  } else {
+    // the face grid serves every order: size it by the order that fits the
+    // fewest blocks (the largest LDS tile)
+    auto face_occ = [&](const void* f2, size_t l2, const void* f3, size_t l3, const void* f4, size_t l4, int* out) {
+      int a = 0, c = 0, d = 0;
+      hipError_t r = hipOccupancyMaxActiveBlocksPerMultiprocessor(&a, f2, 256, l2);
+      if (r == hipSuccess) r = hipOccupancyMaxActiveBlocksPerMultiprocessor(&c, f3, 256, l3);
+      if (r == hipSuccess) r = hipOccupancyMaxActiveBlocksPerMultiprocessor(&d, f4, 256, l4);
+      *out = std::min(a, std::min(c, d));
+      return r;
+    };
+    if ((e = face_occ((const void*)kb_face<1, 2, T, 2, 0>, Lds<2, T, 0>::total, (const void*)kb_face<1, 2, T, 3, 0>,
+                      Lds<3, T, 0>::total, (const void*)kb_face<1, 2, T, 4, 0>, Lds<4, T, 0>::total, &b->occ_face[0])))
+      return e;
+    if ((e = face_occ((const void*)kb_face<1, 2, T, 2, 1>, Lds<2, T, 1>::total, (const void*)kb_face<1, 2, T, 3, 1>,
+                      Lds<3, T, 1>::total, (const void*)kb_face<1, 2, T, 4, 1>, Lds<4, T, 1>::total, &b->occ_face[1])))
+      return e;
+    if ((e = face_occ((const void*)kb_face<1, 2, T, 2, 2>, Lds<2, T, 2>::total, (const void*)kb_face<1, 2, T, 3, 2>,
+                      Lds<3, T, 2>::total, (const void*)kb_face<1, 2, T, 4, 2>, Lds<4, T, 2>::total, &b->occ_face[2])))
+      return e;
+  }
   return hipOccupancyMaxActiveBlocksPerMultiprocessor(&b->occ[K_S1D], kb_stage1d<2, T>, 256, 0);
 }
 
@@ -389,12 +270,18 @@ void launch_faces_v(int gf, hipStream_t st, const BTab* t, int r) {
   hipLaunchKernelGGL((kb_face<DIR, STAGE, T, 4, V>), dim3(gf), dim3(256), l4, st, t, r);
 }
 
+// FP32: each kernel's own persistent grid (its waves per SIMD differ by
+// direction, stage and order), from the CU count and the grid multiplier
 template <int DIR, int STAGE, typename T>
-void launch_faces(int v, int gf, hipStream_t st, const BTab* t, int r) {
-  switch (v) {
-    case 1: launch_faces_v<DIR, STAGE, T, 1>(gf, st, t, r); break;
-    case 2: launch_faces_v<DIR, STAGE, T, 2>(gf, st, t, r); break;
-    default: launch_faces_v<DIR, STAGE, T, 0>(gf, st, t, r); break;
+void launch_faces(const cgks_batch* b, int v, int gf, hipStream_t st, const BTab* t, int r) {
+  if constexpr (sizeof(T) == 4) {
+    cgks_bf32::launch_faces(DIR, STAGE, v, b->ncu, std::max(1, b->tune.grid_mult), st, t, r);
+  } else {
+    switch (v) {
+      case 1: launch_faces_v<DIR, STAGE, T, 1>(gf, st, t, r); break;
+      case 2: launch_faces_v<DIR, STAGE, T, 2>(gf, st, t, r); break;
+      default: launch_faces_v<DIR, STAGE, T, 0>(gf, st, t, r); break;
+    }
   }
 }
 
@@ -421,12 +308,12 @@ hipError_t enqueue_batch_step(const cgks_batch* b, hipStream_t st) {
   // every order is launched (a phase without jobs of that order ends at
   // once), so a captured step serves any later mix of orders
   launch_lines<T>(lw, gl, st, t, 1, r);
-  launch_faces<0, 1, T>(v, gf, st, t, r);
-  launch_faces<1, 1, T>(v, gf, st, t, r);
+  launch_faces<0, 1, T>(b, v, gf, st, t, r);
+  launch_faces<1, 1, T>(b, v, gf, st, t, r);
   hipLaunchKernelGGL(kb_bcs<T>, dim3(b->grid[K_BCS]), dim3(256), 0, st, t, r);
   launch_lines<T>(lw, gl, st, t, 2, r);
-  launch_faces<0, 2, T>(v, gf, st, t, r);
-  launch_faces<1, 2, T>(v, gf, st, t, r);
+  launch_faces<0, 2, T>(b, v, gf, st, t, r);
+  launch_faces<1, 2, T>(b, v, gf, st, t, r);
   return hipGetLastError();
 }
 

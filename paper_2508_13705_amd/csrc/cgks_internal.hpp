@@ -658,6 +658,15 @@ __device__ __forceinline__ int tile_tid() {
   asm volatile("" : "+v"(t));
   return t;
 }
+// tile_tid for a block of 256 threads, with the range the compiler knows of
+// threadIdx.x there (without it, LDS addresses derived from the index lose
+// their immediate offsets)
+__device__ __forceinline__ int tile_tid256() {
+  const int t = tile_tid();
+  __builtin_assume(t >= 0 && t < 256);
+  return t;
+}
+
 // a value the compiler must take as new at this point, so that it does not
 // keep what it derived from the value earlier live until here
 __device__ __forceinline__ double fresh(double x) {
@@ -956,26 +965,24 @@ template <int M, typename T, int V = 0, int D = -1, bool OCC3 = false> struct Ld
 // Waves per SIMD the single-grid face kernels are compiled for, each without
 // spilling to scratch: FP64 with the whole register file of one wave per
 // SIMD; FP32 with a third of it (168 registers), three blocks sharing a CU.
-// (The batched face kernels, whose persistent loop and job descriptors add
-// registers, run two FP32 waves.)  The library checks at start-up that no
-// face kernel uses private memory.
+// The library checks at start-up that no face kernel uses private memory.
 template <typename T, int DIR = 0, int STAGE = 2> struct FaceWaves {
   static constexpr int value = sizeof(T) == 8 ? 1 : 3;
 };
-// LDS layout of a face tile; OWN: a single-grid kernel, sized for its own
-// direction and wave count
-template <int DIR, int STAGE, int M, typename T, int V, bool OWN>
-using FaceLds = Lds<M, T, V, OWN ? DIR : -1, OWN && FaceWaves<T, DIR, STAGE>::value == 3>;
+// LDS layout of a face tile.  OWNW = 0: the layout every direction shares;
+// OWNW = w > 0: the kernel's own direction only, for a kernel compiled for w
+// waves per SIMD (three: unpadded records where the padding would cost the
+// third block)
+template <int DIR, int M, typename T, int V, int OWNW>
+using FaceLds = Lds<M, T, V, OWNW ? DIR : -1, OWNW == 3>;
 // three FP32 tiles of the three-wave kernels, with their static LDS (the
 // tally, and the speed reduction at stage 2) and the allocation rounded up
 // to 1280 bytes, fit one CU (a tile of 53.5 KB runs three blocks per CU, one
 // of 54.2 KB two)
 constexpr size_t lds_alloc(size_t b) { return (b + 1279) / 1280 * 1280; }
 template <int M> constexpr bool fits3() {
-  return lds_alloc(FaceLds<0, 2, M, float, 0, true>::total + sizeof(Tally) + sizeof(SpeedRed)) <= 160 * 1024 / 3 &&
-         lds_alloc(FaceLds<1, 2, M, float, 0, true>::total + sizeof(Tally) + sizeof(SpeedRed)) <= 160 * 1024 / 3 &&
-         lds_alloc(FaceLds<0, 1, M, float, 0, true>::total + sizeof(Tally)) <= 160 * 1024 / 3 &&
-         lds_alloc(FaceLds<1, 1, M, float, 0, true>::total + sizeof(Tally)) <= 160 * 1024 / 3;
+  return lds_alloc(FaceLds<0, M, float, 0, 3>::total + sizeof(Tally) + sizeof(SpeedRed)) <= 160 * 1024 / 3 &&
+         lds_alloc(FaceLds<1, M, float, 0, 3>::total + sizeof(Tally) + sizeof(SpeedRed)) <= 160 * 1024 / 3;
 }
 static_assert(fits3<2>() && fits3<3>() && fits3<4>(), "FP32 three-wave face tiles fit three blocks per CU");
 
@@ -991,19 +998,21 @@ __device__ __forceinline__ T tanw(int m, int l, int k) {
 // with a barrier so the LDS of the previous tile is free).  SU: staging passes
 // whose loads are issued together (all of them where registers allow; the
 // persistent batched kernels keep more per-job state live and take fewer).
+// OWNW: the LDS layout (FaceLds); a kernel compiled for its own direction
+// (OWNW > 0) also takes the health block's indices afresh.
 template <int DIR, int STAGE, int M, typename T, bool PR, int SU = 32, bool PERSIST = false, int V = 0,
-          bool UNROLL = false, bool OWN = false>
+          bool UNROLL = false, int OWNW = 0>
 __device__ void face2d_tile(const Geo& g, const Consts& C, const Bufs& B, unsigned char* smem, int bx, int by,
                             int nbx, int nby) {
   using TL = Tile<M, V>;
-  using LD = FaceLds<DIR, STAGE, M, T, V, OWN>;
+  using LD = FaceLds<DIR, M, T, V, OWNW>;
   constexpr int NF = TL::NF, NT = TL::NT, NC = TL::NC, NR = TL::NR;
   const gptr<const Header> hdr = glb((const Header*)B.hdr);
   __shared__ Tally tally;
   __syncthreads();
   if (!hdr->active) return;
   // persistent callers: an index the compiler cannot hoist out of their loop
-  const int tx = PERSIST ? tile_tid() : (int)threadIdx.x;
+  const int tx = PERSIST ? tile_tid256() : (int)threadIdx.x;
   tally_zero(tally, tx);
   const double dt = hdr->dt;
   T* s2v = (T*)smem;
@@ -1300,10 +1309,10 @@ __device__ void face2d_tile(const Geo& g, const Consts& C, const Bufs& B, unsign
   if (DIR == 1) {
     __syncthreads();
     // health and (stage 2) the speed reduction for the next time step.  In
-    // the single-grid kernels the lane's cell indices and gamma are taken
-    // afresh (tile_tid, fresh): shared with Step 3, what is derived from them
-    // would stay live in registers through the flux
-    const int it = OWN ? tile_tid() : tx;
+    // the kernels of one direction (OWNW) the lane's cell indices and gamma
+    // are taken afresh (tile_tid, fresh): shared with Step 3, what is derived
+    // from them would stay live in registers through the flux
+    const int it = OWNW ? tile_tid256() : tx;
     bool valid = false;
     double s = 0.0, rr = 1.0;
     if (it < (NF - 1) * NT) {
@@ -1313,7 +1322,7 @@ __device__ void face2d_tile(const Geo& g, const Consts& C, const Bufs& B, unsign
         double W[4];
         for (int v = 0; v < 4; ++v) W[v] = fin[v * NFT + ci * NT + r];
         rr = W[0];
-        valid = cell_speed(W, 2, OWN ? fresh(C.gamma) : C.gamma, s);
+        valid = cell_speed(W, 2, OWNW ? fresh(C.gamma) : C.gamma, s);
         if (!valid) atomicAdd((unsigned long long*)&B.hdr->nonphysical, 1ull);
       }
     }
