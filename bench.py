@@ -95,7 +95,8 @@ def parse():
 
 def kernel_source_hash():
     h = hashlib.sha256()
-    for f in ("cgks.hip", "cgks_batch.hip", "cgks_internal.hpp", "cgks_device.hpp", "cgks_tables.inc"):
+    for f in ("cgks.hip", "cgks_batch.hip", "cgks_batch.hpp", "cgks_batch_f32.hip", "cgks_internal.hpp", "cgks_device.hpp",
+              "cgks_tables.inc"):
         with open(os.path.join(ROOT, "paper_2508_13705_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
