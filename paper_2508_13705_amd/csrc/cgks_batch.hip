@@ -66,74 +66,6 @@ __global__ __launch_bounds__(256) void kb_bcs(const BTab* tab, int remap) {
   });
 }
 
-// Step 1 line values of the stage input (2-D), one tile of shape LW per item.
-template <int LW, typename ST>
-__global__ __launch_bounds__(256) void kb_lines(const BTab* tab, int stage, int remap) {
-  __shared__ double sm[LinesLds<LW>::total];
-  for_items<false>(tab, PH_LINES, remap, [&](const BJob& J, int k) {
-    if (!J.B.hdr->active) return;
-    const double* Uin = stage == 1 ? J.B.U : J.B.S;
-    const int bx = k % J.ltx, by = k / J.ltx;
-    switch (J.M) {
-      case 2: lines_tile<2, ST, true, LW>(J.g, J.C, Uin, J.B.sxo, J.B.syo, J.B.lvx, J.B.lvy, J.B.hdr, bx, by, sm); break;
-      case 3: lines_tile<3, ST, true, LW>(J.g, J.C, Uin, J.B.sxo, J.B.syo, J.B.lvx, J.B.lvy, J.B.hdr, bx, by, sm); break;
-      default: lines_tile<4, ST, true, LW>(J.g, J.C, Uin, J.B.sxo, J.B.syo, J.B.lvx, J.B.lvy, J.B.hdr, bx, by, sm); break;
-    }
-  });
-}
-
-
-// One stage of the 1-D scheme over the segments of every job.
-template <int STAGE, typename T>
-__global__ __launch_bounds__(256, sizeof(T) == 4 ? 3 : 2) void kb_stage1d(const BTab* tab, int remap) {
-  const int total = tab->total[PH_S1D];
-  const int G = gridDim.x;
-  int lb = blockIdx.x;
-  if (remap) lb = (blockIdx.x & 7) * (G >> 3) + (blockIdx.x >> 3);   // G is a multiple of 8
-  // the item's job and segment (wave-uniform): scalar loads through a
-  // pointer of constant type, the map does not change while the kernel runs
-  auto item_of = [&](int item, int& j, int& seg) {
-#if defined(__HIP_DEVICE_COMPILE__)
-    const S1Item e = ((const __attribute__((address_space(4))) S1Item*)tab->imap)[tab->ioff[PH_S1D] + item];
-#else
-    const S1Item e = tab->imap[tab->ioff[PH_S1D] + item];
-#endif
-    j = __builtin_amdgcn_readfirstlane(e.job);
-    seg = __builtin_amdgcn_readfirstlane(e.seg);
-  };
-  if constexpr (sizeof(T) == 4) {
-    // FP32: inputs copied into LDS by DMA; the descriptor read in place
-    // (registers are this kernel's limit: three waves per SIMD)
-    __shared__ S1In<T> in;
-    __shared__ S1Acc<T> acc;
-    __shared__ S1Mid<T, STAGE> mid;
-    for (int item = lb; item < total; item += G) {
-      int j, seg;
-      item_of(item, j, seg);
-      const BJob& J = job_ref(tab, j);
-      __syncthreads();   // the previous segment is done with the LDS
-      s1_issue_in<STAGE, T>(J.g, J.B, seg, &in, tile_tid());
-      s1_landed();
-      stage1d_seg_lds<STAGE, T, false, true>(J.g, J.C, J.B, &in, &acc, &mid, seg, J.nseg);
-    }
-  } else {
-    // FP64: inputs through registers; a copy of the descriptor (its scalar
-    // registers are full: fields read in place would be reloaded, and waited
-    // for, at every use)
-    __shared__ double res[256][12];
-    __shared__ __align__(16) unsigned char sm[Lds1D<T>::total];
-    for (int item = lb; item < total; item += G) {
-      int j, seg;
-      item_of(item, j, seg);
-#if defined(__HIP_DEVICE_COMPILE__)
-      const BJob J = glb((const BJob*)tab->jobs)[j];
-#else
-      const BJob& J = tab->jobs[j];
-#endif
-      stage1d_seg<STAGE, T, false>(J.g, J.C, J.B, res, sm, seg, J.nseg);
-    }
-  }
-}
 
 // Kernel slots of the persistent launches (grid sizes are per slot).
 enum Kern { K_DT = 0, K_PREP, K_BCS, K_LINES, K_FACE, K_S1D, NK };
@@ -220,10 +152,15 @@ cgks_status prepare_batch() {
     if ((s = prepare_bshape<T, 1>()) != CGKS_OK) return s;
     if ((s = prepare_bshape<T, 2>()) != CGKS_OK) return s;
   }
-  const void* k[] = {(const void*)kb_dt, (const void*)kb_prep<T>, (const void*)kb_bcs<T>, (const void*)kb_lines<0, T>,
-                     (const void*)kb_lines<1, T>, (const void*)kb_stage1d<1, T>, (const void*)kb_stage1d<2, T>};
+  const void* k[] = {(const void*)kb_dt, (const void*)kb_prep<T>, (const void*)kb_bcs<T>};
   for (const void* f : k)
     if ((s = check_private(f, 0, "batched kernel")) != CGKS_OK) return s;
+  if constexpr (sizeof(T) == 8) {   // FP32: checked by cgks_bf32::prepare
+    const void* k2[] = {(const void*)kb_lines<0, T>, (const void*)kb_lines<1, T>, (const void*)kb_stage1d<1, T>,
+                        (const void*)kb_stage1d<2, T>};
+    for (const void* f : k2)
+      if ((s = check_private(f, 0, "batched kernel")) != CGKS_OK) return s;
+  }
   return CGKS_OK;
 }
 
@@ -233,11 +170,11 @@ hipError_t occupancy(cgks_batch* b) {
   if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&b->occ[K_DT], kb_dt, 256, 0))) return e;
   if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&b->occ[K_PREP], kb_prep<T>, 256, 0))) return e;
   if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&b->occ[K_BCS], kb_bcs<T>, 256, 0))) return e;
-  if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&b->occ_lines[0], kb_lines<0, T>, 256, 0))) return e;
-  if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&b->occ_lines[1], kb_lines<1, T>, 256, 0))) return e;
   if constexpr (sizeof(T) == 4) {
-    if ((e = cgks_bf32::occupancy(b->occ_face))) return e;
+    return cgks_bf32::occupancy(b->occ_face, b->occ_lines, &b->occ[K_S1D]);
   } else {
+    if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&b->occ_lines[0], kb_lines<0, T>, 256, 0))) return e;
+    if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&b->occ_lines[1], kb_lines<1, T>, 256, 0))) return e;
     // the face grid serves every order: size it by the order that fits the
     // fewest blocks (the largest LDS tile)
     auto face_occ = [&](const void* f2, size_t l2, const void* f3, size_t l3, const void* f4, size_t l4, int* out) {
@@ -257,8 +194,8 @@ hipError_t occupancy(cgks_batch* b) {
     if ((e = face_occ((const void*)kb_face<1, 2, T, 2, 2>, Lds<2, T, 2>::total, (const void*)kb_face<1, 2, T, 3, 2>,
                       Lds<3, T, 2>::total, (const void*)kb_face<1, 2, T, 4, 2>, Lds<4, T, 2>::total, &b->occ_face[2])))
       return e;
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(&b->occ[K_S1D], kb_stage1d<2, T>, 256, 0);
   }
-  return hipOccupancyMaxActiveBlocksPerMultiprocessor(&b->occ[K_S1D], kb_stage1d<2, T>, 256, 0);
 }
 
 // The face kernels of one direction, stage and tile shape, one launch per order.
@@ -287,8 +224,22 @@ void launch_faces(const cgks_batch* b, int v, int gf, hipStream_t st, const BTab
 
 template <typename T>
 void launch_lines(int lw, int gl, hipStream_t st, const BTab* t, int stage, int r) {
-  if (lw == 1) hipLaunchKernelGGL((kb_lines<1, T>), dim3(gl), dim3(256), 0, st, t, stage, r);
-  else hipLaunchKernelGGL((kb_lines<0, T>), dim3(gl), dim3(256), 0, st, t, stage, r);
+  if constexpr (sizeof(T) == 4) {
+    cgks_bf32::launch_lines(lw, gl, st, t, stage, r);
+  } else {
+    if (lw == 1) hipLaunchKernelGGL((kb_lines<1, T>), dim3(gl), dim3(256), 0, st, t, stage, r);
+    else hipLaunchKernelGGL((kb_lines<0, T>), dim3(gl), dim3(256), 0, st, t, stage, r);
+  }
+}
+
+template <typename T>
+void launch_stage1d(int stage, int gs, hipStream_t st, const BTab* t, int r) {
+  if constexpr (sizeof(T) == 4) {
+    cgks_bf32::launch_stage1d(stage, gs, st, t, r);
+  } else {
+    if (stage == 1) hipLaunchKernelGGL((kb_stage1d<1, T>), dim3(gs), dim3(256), 0, st, t, r);
+    else hipLaunchKernelGGL((kb_stage1d<2, T>), dim3(gs), dim3(256), 0, st, t, r);
+  }
 }
 
 template <typename T>
@@ -298,9 +249,9 @@ hipError_t enqueue_batch_step(const cgks_batch* b, hipStream_t st) {
   hipLaunchKernelGGL(kb_dt, dim3(b->grid[K_DT]), dim3(256), 0, st, t);
   hipLaunchKernelGGL(kb_prep<T>, dim3(b->grid[K_PREP]), dim3(256), 0, st, t, r);
   if (b->dim == 1) {
-    hipLaunchKernelGGL((kb_stage1d<1, T>), dim3(b->grid[K_S1D]), dim3(256), 0, st, t, r);
+    launch_stage1d<T>(1, b->grid[K_S1D], st, t, r);
     hipLaunchKernelGGL(kb_bcs<T>, dim3(b->grid[K_BCS]), dim3(256), 0, st, t, r);
-    hipLaunchKernelGGL((kb_stage1d<2, T>), dim3(b->grid[K_S1D]), dim3(256), 0, st, t, r);
+    launch_stage1d<T>(2, b->grid[K_S1D], st, t, r);
     return hipGetLastError();
   }
   const int gf = b->grid[K_FACE], gl = b->grid[K_LINES];

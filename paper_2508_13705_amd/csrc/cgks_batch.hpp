@@ -124,6 +124,76 @@ __device__ __forceinline__ void for_items(const BTab* tab, int ph, int remap, F&
   }
 }
 
+// Step 1 line values of the stage input (2-D), one tile of shape LW per item.
+template <int LW, typename ST>
+__global__ __launch_bounds__(256) void kb_lines(const BTab* tab, int stage, int remap) {
+  __shared__ double sm[LinesLds<LW>::total];
+  for_items<false>(tab, PH_LINES, remap, [&](const BJob& J, int k) {
+    if (!J.B.hdr->active) return;
+    const double* Uin = stage == 1 ? J.B.U : J.B.S;
+    const int bx = k % J.ltx, by = k / J.ltx;
+    switch (J.M) {
+      case 2: lines_tile<2, ST, true, LW>(J.g, J.C, Uin, J.B.sxo, J.B.syo, J.B.lvx, J.B.lvy, J.B.hdr, bx, by, sm); break;
+      case 3: lines_tile<3, ST, true, LW>(J.g, J.C, Uin, J.B.sxo, J.B.syo, J.B.lvx, J.B.lvy, J.B.hdr, bx, by, sm); break;
+      default: lines_tile<4, ST, true, LW>(J.g, J.C, Uin, J.B.sxo, J.B.syo, J.B.lvx, J.B.lvy, J.B.hdr, bx, by, sm); break;
+    }
+  });
+}
+
+
+// One stage of the 1-D scheme over the segments of every job.
+template <int STAGE, typename T>
+__global__ __launch_bounds__(256, sizeof(T) == 4 ? 4 : 2) void kb_stage1d(const BTab* tab, int remap) {
+  const int total = tab->total[PH_S1D];
+  const int G = gridDim.x;
+  int lb = blockIdx.x;
+  if (remap) lb = (blockIdx.x & 7) * (G >> 3) + (blockIdx.x >> 3);   // G is a multiple of 8
+  // the item's job and segment (wave-uniform): scalar loads through a
+  // pointer of constant type, the map does not change while the kernel runs
+  auto item_of = [&](int item, int& j, int& seg) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    const S1Item e = ((const __attribute__((address_space(4))) S1Item*)tab->imap)[tab->ioff[PH_S1D] + item];
+#else
+    const S1Item e = tab->imap[tab->ioff[PH_S1D] + item];
+#endif
+    j = __builtin_amdgcn_readfirstlane(e.job);
+    seg = __builtin_amdgcn_readfirstlane(e.seg);
+  };
+  if constexpr (sizeof(T) == 4) {
+    // FP32: inputs copied into LDS by DMA; the descriptor read in place
+    // (four waves per SIMD, built without machine loop-invariant code
+    // motion)
+    __shared__ S1In<T> in;
+    __shared__ S1Acc<T> acc;
+    __shared__ S1Mid<T, STAGE> mid;
+    for (int item = lb; item < total; item += G) {
+      int j, seg;
+      item_of(item, j, seg);
+      const BJob& J = job_ref(tab, j);
+      __syncthreads();   // the previous segment is done with the LDS
+      s1_issue_in<STAGE, T>(J.g, J.B, seg, &in, tile_tid256());
+      s1_landed();
+      stage1d_seg_lds<STAGE, T, false, true>(J.g, J.C, J.B, &in, &acc, &mid, seg, J.nseg);
+    }
+  } else {
+    // FP64: inputs through registers; a copy of the descriptor (its scalar
+    // registers are full: fields read in place would be reloaded, and waited
+    // for, at every use)
+    __shared__ double res[256][12];
+    __shared__ __align__(16) unsigned char sm[Lds1D<T>::total];
+    for (int item = lb; item < total; item += G) {
+      int j, seg;
+      item_of(item, j, seg);
+#if defined(__HIP_DEVICE_COMPILE__)
+      const BJob J = glb((const BJob*)tab->jobs)[j];
+#else
+      const BJob& J = tab->jobs[j];
+#endif
+      stage1d_seg<STAGE, T, false>(J.g, J.C, J.B, res, sm, seg, J.nseg);
+    }
+  }
+}
+
 // Waves per SIMD of the batched face kernels.  FP32: three at stage 2, whose
 // tiles fit 168 registers without scratch inside the persistent loop; two at
 // stage 1 (one to five registers over).  FP64: one (the shared layout, as the
@@ -156,13 +226,19 @@ constexpr size_t kb_face_lds() {
 
 }  // namespace
 
-// The FP32 face kernels of the batch (cgks_batch_f32.hip): their LDS limits
-// and scratch check; their resident blocks per CU (kept per kernel; reported
-// for each tile shape as the fewest over its kernels); and the launches of
-// one direction and stage, one per order, for tile shape v, each a
-// persistent grid of ncu x its resident blocks x mult blocks.
+// The FP32 kernels of the batch that run the tile bodies in a persistent
+// loop (cgks_batch_f32.hip): face, Step 1 line and 1-D stage kernels.
+//   prepare: their LDS limits and scratch check;
+//   occupancy: resident blocks per CU (face kernels: kept per kernel and
+//     reported for each tile shape as the fewest over its kernels; line
+//     kernels per tile shape; the 1-D stage);
+//   launch_faces: one direction and stage, one launch per order, for tile
+//     shape v, each a persistent grid of ncu x its resident blocks x mult;
+//   launch_lines, launch_stage1d: with the grid the caller sized.
 namespace cgks_bf32 {
 cgks_status prepare();
-hipError_t occupancy(int occ_face[kFaceTiles]);
+hipError_t occupancy(int occ_face[kFaceTiles], int occ_lines[kLineTiles], int* occ_s1d);
 void launch_faces(int dir, int stage, int v, int ncu, int mult, hipStream_t st, const void* tab, int remap);
+void launch_lines(int lw, int grid, hipStream_t st, const void* tab, int stage, int remap);
+void launch_stage1d(int stage, int grid, hipStream_t st, const void* tab, int remap);
 }  // namespace cgks_bf32

@@ -1,12 +1,15 @@
-// The FP32-flux face kernels of the batch (Sec. 3.3 Steps 2-4 over the face
-// tiles of every job, as cgks_batch.hip describes).  They are a unit of their
-// own because they are compiled without machine loop-invariant code motion:
-// inside the persistent item loop it would lift the FP64 constants of the
-// flux's exponentials out of the loop into vector registers, which then
-// spill; left in the loop body they are rebuilt per tile from immediates.
-// With that, most of these kernels fit 168 registers and run three waves per
-// SIMD (kBatchWaves).  Each kernel gets a persistent grid sized by its own
-// resident blocks per CU.
+// The FP32-flux kernels of the batch whose tile bodies run in a persistent
+// loop: face (Sec. 3.3 Steps 2-4), Step 1 line and 1-D stage kernels, over
+// the tiles of every job as cgks_batch.hip describes.  They are a unit of
+// their own because they are compiled without machine loop-invariant code
+// motion: inside the item loop it lifts constants out of the loop, the FP64
+// ones of the flux's exponentials into vector registers and the stencil
+// weights into scalar ones, which then spill (into scratch, or scalars into
+// vector lanes); left in the loop body they are rebuilt per tile from
+// immediates.  With that the face kernels of stage 2 fit 168 registers
+// (three waves per SIMD, kBatchWaves), the 1-D stage 128 (four), and the
+// line kernels keep their scalars.  Each face kernel gets a persistent grid
+// sized by its own resident blocks per CU.
 #define CGKS_UNIT batched_f32
 #include "cgks_internal.hpp"
 
@@ -103,11 +106,19 @@ cgks_status prepare() {
   cgks_status s;
   if ((s = prepare_v<0>()) != CGKS_OK) return s;
   if ((s = prepare_v<1>()) != CGKS_OK) return s;
-  return prepare_v<2>();
+  if ((s = prepare_v<2>()) != CGKS_OK) return s;
+  const void* k[] = {(const void*)kb_lines<0, float>, (const void*)kb_lines<1, float>, (const void*)kb_stage1d<1, float>,
+                     (const void*)kb_stage1d<2, float>};
+  for (const void* f : k)
+    if ((s = check_private(f, 0, "batched kernel")) != CGKS_OK) return s;
+  return CGKS_OK;
 }
 
-hipError_t occupancy(int occ_face[kFaceTiles]) {
+hipError_t occupancy(int occ_face[kFaceTiles], int occ_lines[kLineTiles], int* occ_s1d) {
   hipError_t e;
+  if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ_lines[0], kb_lines<0, float>, 256, 0))) return e;
+  if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ_lines[1], kb_lines<1, float>, 256, 0))) return e;
+  if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(occ_s1d, kb_stage1d<2, float>, 256, 0))) return e;
   if ((e = occupancy_v<0>())) return e;
   if ((e = occupancy_v<1>())) return e;
   if ((e = occupancy_v<2>())) return e;
@@ -128,6 +139,18 @@ void launch_faces(int dir, int stage, int v, int ncu, int mult, hipStream_t st, 
     case 2: launch_v<2>(dir, stage, ncu, mult, st, t, remap); break;
     default: launch_v<0>(dir, stage, ncu, mult, st, t, remap); break;
   }
+}
+
+void launch_lines(int lw, int grid, hipStream_t st, const void* tab, int stage, int remap) {
+  const BTab* t = (const BTab*)tab;
+  if (lw == 1) hipLaunchKernelGGL((kb_lines<1, float>), dim3(grid), dim3(256), 0, st, t, stage, remap);
+  else hipLaunchKernelGGL((kb_lines<0, float>), dim3(grid), dim3(256), 0, st, t, stage, remap);
+}
+
+void launch_stage1d(int stage, int grid, hipStream_t st, const void* tab, int remap) {
+  const BTab* t = (const BTab*)tab;
+  if (stage == 1) hipLaunchKernelGGL((kb_stage1d<1, float>), dim3(grid), dim3(256), 0, st, t, remap);
+  else hipLaunchKernelGGL((kb_stage1d<2, float>), dim3(grid), dim3(256), 0, st, t, remap);
 }
 
 }  // namespace cgks_bf32

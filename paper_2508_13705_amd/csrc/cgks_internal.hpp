@@ -721,7 +721,9 @@ __device__ __forceinline__ void lines_tile(const Geo& g, const Consts& C, const 
   double* sx = sy + L::NSY;
   __syncthreads();   // a persistent caller's previous tile has finished with the LDS
   const int i0 = -H + bx * LT_X, j0 = -H + by * LT_Y;
-  const int tid = PERSIST ? tile_tid() : (int)threadIdx.x;
+  // persistent FP32 callers: the opaque index with its range (FP64 keeps
+  // the unranged one, the code of its batched kernels as tested)
+  const int tid = PERSIST ? (sizeof(ST) == 4 ? tile_tid256() : tile_tid()) : (int)threadIdx.x;
   tally_zero(tally, tid);
   auto ci = [&](int i) { return i < -H ? -H : (i > g.nx + H - 1 ? g.nx + H - 1 : i); };
   auto cj = [&](int j) { return j < -H ? -H : (j > g.ny + H - 1 ? g.ny + H - 1 : j); };
@@ -1443,7 +1445,7 @@ __device__ void stage1d_seg_lds(const Geo& g, const Consts& C, const Bufs& B, co
   if (!hdr->active) return;
   const double dt = hdr->dt;
   const int F0 = seg * S1_CELLS;
-  const int t = PERSIST ? tile_tid() : (int)threadIdx.x;
+  const int t = PERSIST ? tile_tid256() : (int)threadIdx.x;
   const gptr<double> Ug = glb(B.U), Sg = glb(B.S), Ag = glb(B.A);
   const gptr<T> UgS = glb(slopes<T>(B.U, g)), SgS = glb(slopes<T>(B.S, g)), AgS = glb(slopes<T>(B.A, g));
   const double h = C.dx;
