@@ -27,6 +27,7 @@ Prints one JSON line.  Usage:
 """
 import argparse
 import hashlib
+import re
 import json
 import os
 import sys
@@ -94,11 +95,17 @@ def parse():
 
 
 def kernel_source_hash():
+    """Hash of the kernel sources with their comments and blank lines taken
+    out: a change to the code changes it, a change to a comment does not."""
     h = hashlib.sha256()
     for f in ("cgks.hip", "cgks_batch.hip", "cgks_batch.hpp", "cgks_batch_f32.hip", "cgks_internal.hpp", "cgks_device.hpp",
               "cgks_tables.inc"):
-        with open(os.path.join(ROOT, "paper_2508_13705_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, "paper_2508_13705_amd", "csrc", f), encoding="utf-8") as fh:
+            text = re.sub(r"/\*.*?\*/", "", fh.read(), flags=re.S)
+        for line in text.splitlines():
+            code = line.split("//", 1)[0].rstrip()
+            if code:
+                h.update(code.encode() + b"\n")
     return h.hexdigest()[:16]
 
 

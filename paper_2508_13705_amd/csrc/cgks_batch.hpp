@@ -1,9 +1,9 @@
 // Batched execution, shared by the translation units of the batched
-// kernels: the device job table, the persistent item loop and the batched
-// face kernel.  The FP64 face kernels are built with the rest of the batch
-// (cgks_batch.hip), the FP32 ones in a unit of their own
-// (cgks_batch_f32.hip), compiled without machine loop-invariant code motion.
-// Included after cgks_internal.hpp.
+// kernels: the device job table, the persistent item loop, and the batched
+// Step 1 line, 1-D stage and face kernels.  Their FP64 instances are built
+// with the rest of the batch (cgks_batch.hip), the FP32 ones in a unit of
+// their own (cgks_batch_f32.hip), compiled without machine loop-invariant
+// code motion.  Included after cgks_internal.hpp.
 #pragma once
 namespace {
 
