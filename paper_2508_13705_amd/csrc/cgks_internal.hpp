@@ -1363,10 +1363,13 @@ template <typename T> struct S1Acc {
   T slo[3][S1_CELLS];
 };
 // The reconstructions [cell][side][k][v] and, once every flux has read its
-// two states, the flux results [face][12 or 6] in the same space.
+// two states, the flux results [face][12 or 6] in the same space.  A result
+// row holds an odd number of doubles (13, 7): the 16 lanes that the LDS
+// serves together in a 64-bit access then write and read consecutive faces
+// on distinct banks (12 and 6 put four and two lanes on each).
 template <typename T, int STAGE> union S1Mid {
   T rc[256][18];
-  double res[256][STAGE == 1 ? 12 : 6];
+  double res[256][STAGE == 1 ? 13 : 7];
 };
 
 // Copy n 4-byte words into LDS at dst (word w from the global address
