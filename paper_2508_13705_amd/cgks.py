@@ -285,8 +285,12 @@ class Solver:
         dt = r.get("dt", 0.0) if dt is None else dt
         t_end = r.get("t_end", 0.0) if t_end is None else t_end
         if nsteps is None or nsteps < 0:
-            # until t_end: poll the device time every few hundred steps
-            while self.read(sync_only=True)["t"] < t_end * (1 - 1e-15):
+            # until t_end, or until the device stops the run (a nonphysical
+            # state): poll the device time and status every few hundred steps
+            while True:
+                r = self.read(sync_only=True)
+                if r["status"] != OK or r["t"] >= t_end * (1 - 1e-15):
+                    break
                 self.step(256, dt=dt, t_end=t_end)
         else:
             self.step(nsteps, dt=dt, t_end=t_end)

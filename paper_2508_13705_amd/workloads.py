@@ -147,6 +147,23 @@ def shock_tube(name, n, order, **kw):
     return riemann_1d(n=n, order=order, name=name, **d)
 
 
+def blast_wave(n=400, order=9, t_end=0.038, cfl=0.5, nsteps=-1):
+    """Interacting blast waves (Sec. 4.4): rho = 1 and u = 0 on [0, 1], p = 1000
+    for x < 0.1, 0.01 up to x = 0.9 and 100 beyond; reflective walls at both
+    ends; exact cell averages (the jumps fall on faces), zero slopes."""
+    dx = 1.0 / n
+    xc = (np.arange(n) + 0.5) * dx
+    p = np.where(xc < 0.1, 1000.0, np.where(xc < 0.9, 0.01, 100.0))
+    rho = np.ones(n)
+    avg = _cons(rho, np.zeros(n), None, p, 1.4, 1)
+    return {"name": "blast_wave",
+            "grid": {"dim": 1, "nx": n, "ny": 1, "x0": 0.0, "x1": 1.0, "y0": 0.0, "y1": 1.0,
+                     "bc": ["reflective", "reflective"]},
+            "scheme": default_scheme(order, gamma=1.4, tau="inviscid", cfl=cfl),
+            "state": {"avg": avg, "sx": np.zeros_like(avg)},
+            "run": {"nsteps": nsteps, "dt": 0.0, "t_end": t_end}}
+
+
 def riemann_batch(seed=2, count=4096, nmin=200, nmax=4000, order=9, t_end=0.15, cfl=0.5):
     """Independent 1-D Riemann problems on [0, 1], interface at the face nearest
     x = 0.5, transmissive ends."""

@@ -173,6 +173,22 @@ def test_fp32_flux_smooth_2d():
     assert e["avg"] <= 1e-5
 
 
+@pytest.mark.parametrize("order", [5, 7, 9])
+def test_blast_wave_stops_with_the_oracle(order):
+    """Interacting blast waves of Sec. 4.4 (pressure jumps of 1e5 and 1e4,
+    reflective walls, 400 cells, CFL 0.5), run to t = 0.038: with the readings
+    adopted here the first step leaves one cell nonphysical.  The GPU stops
+    after the same step and holds the same state as the oracle."""
+    pb = W.blast_wave(order=order)
+    got, ref, _ = run_both(pb)
+    assert ref["status"] == 4 and got["status"] == ref["status"]
+    assert got["steps"] == ref["stats"]["steps"] == 1
+    assert abs(got["t"] - ref["t"]) <= 1e-13 * abs(ref["t"])
+    e = errors(got, ref, 1, cell(pb))
+    print("[parity] errors", e, flush=True)
+    assert e["avg"] <= TOL64 and e["sx"] <= TOL64, e
+
+
 def test_nonphysical_state_is_reported():
     from paper_2508_13705_amd import cgks
     pb = W.quadrant_2d(W.CONFIG3, 12, 5, nsteps=1)

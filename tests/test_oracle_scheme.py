@@ -201,6 +201,28 @@ def test_le_blanc_is_reported_not_silently_wrong():
         assert not physical(r["avg"])
 
 
+@pytest.mark.parametrize("order", [5, 9])
+def test_blast_wave_first_step(order):
+    """Interacting blast waves (Sec. 4.4: p = 1000 | 0.01 | 100, rho = 1, u = 0,
+    400 cells, reflective walls, CFL 0.5).  Fixed independently of the
+    scheme: the first time step is CFL h / sqrt(gamma p_max / rho), and no
+    mass crosses a reflective wall.  With the readings adopted here the first
+    step then leaves one cell nonphysical, the second on the low-pressure
+    side of the x = 0.1 jump (the strong-pressure-ratio failure of the 1-D
+    Riemann batch); the run reports it (status 4) and stops after that
+    step."""
+    pb = W.blast_wave(order=order)
+    r = oracle.run(pb)
+    h = 1.0 / 400
+    assert r["stats"]["steps"] == 1
+    assert abs(r["t"] - 0.5 * h / math.sqrt(1.4 * 1000.0)) <= 1e-15
+    assert abs(r["avg"][0].sum() * h - 1.0) <= 1e-14
+    a = r["avg"]
+    p = 0.4 * (a[2] - 0.5 * a[1] ** 2 / a[0])
+    assert r["status"] == 4
+    assert list(np.where((a[0] <= 0) | (p <= 0))[0]) == [41]
+
+
 @pytest.mark.slow
 @pytest.mark.parametrize("order,n,steps", [(9, 20, 150), (7, 20, 150)])
 def test_cfl_half_is_stable_2d(order, n, steps):
