@@ -343,7 +343,10 @@ cgks_status cgks_batch_launch(cgks_batch* batch, void* stream);
 cgks_status cgks_batch_poll(cgks_batch* batch, cgks_job_status* out, void* stream);
 
 /* Jobs held, their state + work bytes, the device table bytes, and the grid
- * of the persistent face (2-D) or stage (1-D) launch.  Any pointer may be NULL. */
+ * of the persistent face (2-D) or stage (1-D) launch.  For the face launch
+ * this is the grid sized by the fewest resident blocks of the current tile
+ * shape's face kernels; the FP32-flux face kernels each run a grid sized by
+ * their own (at least this one).  Any pointer may be NULL. */
 cgks_status cgks_batch_info(const cgks_batch* batch, int* njobs, size_t* bytes_used, size_t* table_bytes,
                             int* grid_face);
 

@@ -19,7 +19,9 @@
 
 namespace {
 
-// resident blocks per CU of each kernel: [dir][stage - 1][m - 2][tile shape]
+// resident blocks per CU of each kernel: [dir][stage - 1][m - 2][tile shape],
+// filled when a batch is created (the same for every batch of a process on
+// one device type; concurrent creations write the same values)
 int g_occ[2][2][3][kFaceTiles];
 
 template <int DIR, int STAGE, int M, int V>
