@@ -164,6 +164,44 @@ def blast_wave(n=400, order=9, t_end=0.038, cfl=0.5, nsteps=-1):
             "run": {"nsteps": nsteps, "dt": 0.0, "t_end": t_end}}
 
 
+SHOCK_WAVES = {
+    # Sec. 4.3: a shock entering a density wave at rest (p = 1, u = 0),
+    # rho = 1 + amp sin(k (x - 5)) on [xs, 10]
+    "shu_osher": dict(left=(3.857134, 2.629369, 10.33333), xs=1.0, amp=0.2, k=5.0, n=200, t_end=1.8),
+    "titarev_toro": dict(left=(1.515695, 0.523346, 1.805), xs=0.5, amp=0.1, k=20.0 * math.pi, n=1000, t_end=5.0),
+}
+
+
+def shock_wave_1d(name, order=9, n=None, t_end=None, cfl=0.5, nsteps=-1):
+    """Shock / density-wave interaction of Sec. 4.3 on [0, 10] (the shock
+    starts at a face).  Exact cell averages and cell-averaged slopes (the
+    difference of face values over dx) of the initial data, zero on the
+    constant left side; transmissive ends (the inflow side holds the
+    post-shock state, the far side is at rest)."""
+    d = SHOCK_WAVES[name]
+    n = d["n"] if n is None else n
+    t_end = d["t_end"] if t_end is None else t_end
+    dx = 10.0 / n
+    kf = int(round(d["xs"] / dx))
+    xf = np.arange(n + 1) * dx
+    amp, k = d["amp"], d["k"]
+    rho_f = 1.0 + amp * np.sin(k * (xf - 5.0))
+    rho = 1.0 + amp * (np.cos(k * (xf[:-1] - 5.0)) - np.cos(k * (xf[1:] - 5.0))) / (k * dx)
+    u = np.zeros(n)
+    p = np.ones(n)
+    rl, ul, pl = d["left"]
+    rho[:kf], u[:kf], p[:kf] = rl, ul, pl
+    avg = _cons(rho, u, None, p, 1.4, 1)
+    sx = np.zeros_like(avg)
+    sx[0, kf:] = (rho_f[kf + 1:] - rho_f[kf:-1]) / dx
+    return {"name": name,
+            "grid": {"dim": 1, "nx": n, "ny": 1, "x0": 0.0, "x1": 10.0, "y0": 0.0, "y1": 1.0,
+                     "bc": ["transmissive", "transmissive"]},
+            "scheme": default_scheme(order, gamma=1.4, tau="inviscid", cfl=cfl),
+            "state": {"avg": avg, "sx": sx},
+            "run": {"nsteps": nsteps, "dt": 0.0, "t_end": t_end}}
+
+
 def riemann_batch(seed=2, count=4096, nmin=200, nmax=4000, order=9, t_end=0.15, cfl=0.5):
     """Independent 1-D Riemann problems on [0, 1], interface at the face nearest
     x = 0.5, transmissive ends."""

@@ -189,6 +189,17 @@ def test_blast_wave_stops_with_the_oracle(order):
     assert e["avg"] <= TOL64 and e["sx"] <= TOL64, e
 
 
+@pytest.mark.parametrize("name,order", [("shu_osher", 5), ("shu_osher", 7), ("shu_osher", 9), ("titarev_toro", 9)])
+def test_shock_density_waves_to_t_end(name, order):
+    """Shock / density-wave interaction of Sec. 4.3 to its end time
+    (Shu-Osher: 200 cells, t = 1.8, 339 steps; Titarev-Toro: 1000 cells,
+    t = 5): averages and slopes at oracle parity."""
+    pb = W.shock_wave_1d(name, order=order)
+    got, ref, _ = run_both(pb)
+    assert ref["status"] == 0
+    assert_parity(got, ref, 1, h=cell(pb))
+
+
 def test_nonphysical_state_is_reported():
     from paper_2508_13705_amd import cgks
     pb = W.quadrant_2d(W.CONFIG3, 12, 5, nsteps=1)

@@ -201,6 +201,32 @@ def test_le_blanc_is_reported_not_silently_wrong():
         assert not physical(r["avg"])
 
 
+@pytest.mark.parametrize("name,mach", [("shu_osher", 3.0), ("titarev_toro", None)])
+def test_shock_density_wave_data(name, mach):
+    """Sec. 4.3 initial data: the left state is the post-shock state of a
+    shock running into the gas at rest (rho = 1, p = 1): mass, momentum and
+    energy fluxes across it agree in the shock's frame (Rankine-Hugoniot, to
+    the digits the paper prints; Shu-Osher's is Mach 3); the right side's cell
+    averages integrate to the exact integral of 1 + amp sin(k (x - 5))."""
+    d = W.SHOCK_WAVES[name]
+    g = 1.4
+    rl, ul, pl = d["left"]
+    s = rl * ul / (rl - 1.0)                   # mass flux continuity (the right gas is at rest)
+    el = pl / (g - 1) + 0.5 * rl * ul * ul
+    er = 1.0 / (g - 1)
+    assert abs((rl * ul * (ul - s) + pl) - (1.0 + 0.0)) <= 2e-5 * pl
+    assert abs(((el + pl) * ul - s * el) - (-s * er)) <= 2e-5 * el * s
+    if mach is not None:
+        assert abs(s / math.sqrt(g) - mach) <= 1e-5
+    pb = W.shock_wave_1d(name, order=5)
+    n = pb["grid"]["nx"]
+    h = 10.0 / n
+    kf = int(round(d["xs"] / h))
+    k, amp = d["k"], d["amp"]
+    exact = (10.0 - d["xs"]) + amp * (math.cos(k * (d["xs"] - 5.0)) - math.cos(k * 5.0)) / k
+    assert abs(pb["state"]["avg"][0, kf:].sum() * h - exact) <= 1e-12 * exact
+
+
 @pytest.mark.parametrize("order", [5, 9])
 def test_blast_wave_first_step(order):
     """Interacting blast waves (Sec. 4.4: p = 1000 | 0.01 | 100, rho = 1, u = 0,
