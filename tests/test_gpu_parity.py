@@ -200,6 +200,18 @@ def test_shock_density_waves_to_t_end(name, order):
     assert_parity(got, ref, 1, h=cell(pb))
 
 
+@pytest.mark.parametrize("name,n,order", [("double_rarefaction", 400, 5), ("double_rarefaction", 400, 7),
+                                          ("double_rarefaction", 400, 9), ("lax", 200, 9)])
+def test_shock_tubes_to_t_end(name, n, order):
+    """The near-vacuum double rarefaction of Sec. 4.5 (density down to 1e-6
+    at the centre) and the Lax tube of Sec. 4.2, to their end times:
+    averages and slopes at oracle parity."""
+    pb = W.shock_tube(name, n, order)
+    got, ref, _ = run_both(pb)
+    assert ref["status"] == 0
+    assert_parity(got, ref, 1, h=cell(pb))
+
+
 def test_nonphysical_state_is_reported():
     from paper_2508_13705_amd import cgks
     pb = W.quadrant_2d(W.CONFIG3, 12, 5, nsteps=1)
