@@ -339,6 +339,8 @@ def quadrant_random(seed=3, n=1024, order=7, nsteps=200):
 
 
 # Configuration 3 of Sec. 4.7 (the paper's timing workload)
+# Sec. 4.7 (a): four rarefaction waves, split at (0.5, 0.5), t = 0.2
+CONFIG2 = [(1.0, -0.7259, -0.7259, 1.0), (0.5197, 0.0, -0.7259, 0.4), (1.0, 0.0, 0.0, 1.0), (0.5197, -0.7259, 0.0, 0.4)]
 CONFIG3 = [(0.138, 1.206, 1.206, 0.029), (0.5323, 0.0, 1.206, 0.3), (1.5, 0.0, 0.0, 1.5), (0.5323, 1.206, 0.0, 0.3)]
 
 

@@ -212,6 +212,23 @@ def test_shock_tubes_to_t_end(name, n, order):
     assert_parity(got, ref, 1, h=cell(pb))
 
 
+@pytest.mark.parametrize("order", [5, 9])
+def test_config2_rarefactions_to_t_end(order):
+    """Configuration 2 of Sec. 4.7 (four rarefaction waves) on 48 x 48 to
+    t = 0.2: oracle parity, and the mirror symmetry of the data about y = x
+    (rho(x, y) = rho(y, x), rho u(x, y) = rho v(y, x)) kept by the x- and
+    y-face kernels alike."""
+    pb = W.quadrant_2d(W.CONFIG2, 48, order, nsteps=-1, t_end=0.2, name="config2")
+    got, ref, _ = run_both(pb)
+    assert ref["status"] == 0
+    assert_parity(got, ref, 2, h=cell(pb))
+    a = got["avg"]
+    scale = np.abs(a).max()
+    assert np.abs(a[0] - a[0].T).max() <= 1e-12 * scale
+    assert np.abs(a[1] - a[2].T).max() <= 1e-12 * scale
+    assert np.abs(a[3] - a[3].T).max() <= 1e-12 * scale
+
+
 def test_nonphysical_state_is_reported():
     from paper_2508_13705_amd import cgks
     pb = W.quadrant_2d(W.CONFIG3, 12, 5, nsteps=1)
