@@ -200,6 +200,22 @@ def test_shock_density_waves_to_t_end(name, order):
     assert_parity(got, ref, 1, h=cell(pb))
 
 
+@pytest.mark.parametrize("name", ["shu_osher", "titarev_toro"])
+def test_shock_density_waves_fp32_flux(name):
+    """FP32-flux on the Sec. 4.3 problems to their end times, against the FP64
+    oracle: relative L1 of the averages within 1e-4 (measured 2.4e-6 for
+    Shu-Osher and 5.0e-6 for Titarev-Toro; the bar leaves room for FP32
+    rounding moving a state across one of the cascade's thresholds near the
+    shock, an O(1) local difference)."""
+    pb = W.shock_wave_1d(name, order=9)
+    got, ref, _ = run_both(pb, precision="fp32_flux")
+    assert got["status"] == ref["status"] == 0
+    assert abs(got["t"] - ref["t"]) <= 1e-12 * ref["t"]
+    e = errors(got, ref, 1, cell(pb))
+    print("[parity] fp32_flux errors", e, flush=True)
+    assert e["avg"] <= 1e-4, e
+
+
 @pytest.mark.parametrize("name,n,order", [("double_rarefaction", 400, 5), ("double_rarefaction", 400, 7),
                                           ("double_rarefaction", 400, 9), ("lax", 200, 9)])
 def test_shock_tubes_to_t_end(name, n, order):
